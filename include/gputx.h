@@ -1,0 +1,240 @@
+/*
+ * gputx.h -- C ABI of the MI355X bulk transaction engine.
+ *
+ * Model (He & Yu, "High-Throughput Transaction Executions on Graphics
+ * Processors"):
+ *  - Transactions are instances of pre-registered stored procedures,
+ *    "Execute procedure_name(parameter list)" (Section 3.1); the procedures of
+ *    all registered types form one combined kernel selected by a switch on the
+ *    type (Section 3.2).
+ *  - A transaction signature is <id, type, parameter values>; the unique id is
+ *    its timestamp (Section 3.2).  A bulk is a set of such signatures that runs
+ *    on the GPU as one task (Section 3.1).
+ *  - Definition 1 (Section 3.1): the database after a bulk must equal the one
+ *    obtained by running the bulk's transactions serially in increasing
+ *    timestamp order.  Every strategy of gputx_execute_bulk meets it, and so do
+ *    the per-transaction results.
+ *  - Relations are stored column-wise in device memory, one array per
+ *    fixed-length column (Section 3.2, Appendix E); inserts land in a buffer and
+ *    are applied as a batched update after the bulk (Section 3.2).
+ *
+ * Conventions
+ *  - Every call returns an int: GPUTX_OK (0) or a negative gputx error code.
+ *    Nothing throws across the ABI.  gputx_last_error() gives a message.
+ *  - "device" pointers are HIP device memory of the context's device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the context borrows table columns for its lifetime and owns only
+ *    its own small internal state.
+ *  - Work is ordered on the hipStream_t the caller passes (0 = null stream).
+ *    Calls on one context must not run concurrently from several host
+ *    threads.
+ */
+#ifndef GPUTX_H
+#define GPUTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gputx_stream_t; /* identical to hipStream_t */
+typedef struct gputx_ctx* gputx_handle;
+
+/* ---- status codes ------------------------------------------------------ */
+enum {
+    GPUTX_OK = 0,
+    GPUTX_E_ARG = -1,       /* bad argument (null pointer, size, id)            */
+    GPUTX_E_TYPE = -2,      /* unknown procedure or inconsistent type binding    */
+    GPUTX_E_DUP_TS = -3,    /* two transactions of a bulk share a timestamp      */
+    GPUTX_E_CAPACITY = -4,  /* an append table or the workspace is too small     */
+    GPUTX_E_HIP = -5,       /* a HIP runtime call failed                         */
+    GPUTX_E_STATE = -6,     /* call out of order (e.g. execute before load)      */
+    GPUTX_E_DEADLOCK = -7,  /* a bounded device wait expired (watchdog)          */
+    GPUTX_E_UNSORTED = -8   /* bulk flagged ts_sorted but timestamps not ascending */
+};
+
+/* ---- execution strategies (Section 5) -------------------------------- */
+enum {
+    GPUTX_AUTO = 0, /* Algorithm 1 (Appendix D) picks one of the three below     */
+    GPUTX_TPL = 1,  /* two-phase locking with counter-based locks (Section 5.1) */
+    GPUTX_PART = 2, /* one thread per partition (Section 5.2)                   */
+    GPUTX_KSET = 3  /* conflict-free k-set waves (Section 5.3)                  */
+};
+
+/* ---- per-transaction status ------------------------------------------ */
+enum {
+    GPUTX_COMMIT = 0,
+    GPUTX_ABORT = 1,   /* two-phase transaction aborted in its read phase (Appendix D) */
+    GPUTX_INVALID = 2  /* unregistered type or parameter outside its table: no effect   */
+};
+
+/* ---- compiled-in stored procedures ------------------------------------
+ * Role bindings (gputx_type_desc.table_ids, in this order):
+ *   bank procedures      : account, teller, branch, history
+ *   order-entry procs    : warehouse, district, customer, stock, orders, order_line
+ *   subscriber procs     : subscriber, call_fwd
+ * Column 0 of account/teller/branch/warehouse/district/customer is the int64
+ * balance; stock column 0 is the int32 quantity; subscriber columns are
+ * id (int64), 4 int32 fields, 10 int32 locations; call_fwd columns are
+ * occupied (int32), end (int32), number (int64); history, orders and
+ * order_line have 5 int64 columns.
+ * Parameters (param k of the signature):
+ *   DEBIT_CREDIT (acct, teller, branch, delta) -> (acct', teller', branch')
+ *       adds delta to the three balances, appends history (acct, teller,
+ *       branch, delta, ts).
+ *   NEW_ORDER (w, d, c, k, item[15], q[15]) -> (k, s_0..s_{k-1})
+ *       for j < k: s = stock[w*ipw + item_j] - q_j, plus 91 if below 10;
+ *       appends orders (ts, w, d, c, k) and k order lines (ts, j, item_j, q_j, w).
+ *       Valid iff 1 <= k <= 15, items < ipw, 1 <= q_j <= 1000.
+ *   PAYMENT (w, d, c, h) -> (warehouse', district', customer'), each += h.
+ *   ORDER_STATUS (w, d, c) -> (customer balance).
+ *   GET_SUB (sid) -> 14 int32 fields.            GET_CF (sid, slot) -> (occ, end, number).
+ *   UPD_SUB_FIELD (sid, f < 4, v) / UPD_LOC (sid, l < 10, v) -> previous value.
+ *   INS_CF (sid, slot, end, number): ABORT if occupied; -> (previous occupied).
+ *   DEL_CF (sid, slot): ABORT if empty; -> (1, end, number) of the deleted row.
+ * Dimensions are derived from the bound tables: ipw = stock rows / warehouses,
+ * dpw = districts / warehouses, cpd = customers / districts; a call_fwd slot is
+ * sid * 12 + slot.  Arithmetic on int64 values wraps modulo 2^64.
+ */
+enum {
+    GPUTX_DEBIT_CREDIT = 1,
+    GPUTX_NEW_ORDER = 2,
+    GPUTX_PAYMENT = 3,
+    GPUTX_ORDER_STATUS = 4,
+    GPUTX_GET_SUB = 5,
+    GPUTX_GET_CF = 6,
+    GPUTX_UPD_SUB_FIELD = 7,
+    GPUTX_UPD_LOC = 8,
+    GPUTX_INS_CF = 9,
+    GPUTX_DEL_CF = 10
+};
+
+enum { GPUTX_I32 = 1, GPUTX_I64 = 2 };
+
+#define GPUTX_MAX_TYPES 16
+#define GPUTX_MAX_TABLES 32
+#define GPUTX_MAX_COLS 16
+#define GPUTX_MAX_ROLES 8
+
+/* Engine options; gputx_default_options fills every field. */
+typedef struct {
+    int64_t w0_bar;        /* Algorithm 1: K-SET when |0-set| >= w0_bar                  */
+    int64_t c_bar;         /* Algorithm 1: PART when cross-partition txns <= c_bar ...  */
+    int64_t d_bar;         /* ... or depth >= d_bar; TPL otherwise                      */
+    int64_t part_size;     /* root keys per partition for PART and for c (Section 5.2)  */
+    int32_t group_by_type; /* 1: group executing transactions by type (Section 5.4)     */
+    int32_t kset_narrow;   /* K-SET waves of at most this many txns run in one workgroup */
+    int32_t spin_limit_ms; /* watchdog on every device wait; expiry -> GPUTX_E_DEADLOCK  */
+    int32_t grid_blocks;   /* persistent grid size (0: one workgroup per compute unit)  */
+} gputx_options;
+
+/* One relation.  Columns are device arrays of capacity rows, caller-owned,
+ * borrowed for the context's lifetime (Appendix E column store). */
+typedef struct {
+    int32_t table_id;                 /* 0 .. GPUTX_MAX_TABLES-1, unique              */
+    int32_t n_cols;                   /* 1 .. GPUTX_MAX_COLS                          */
+    int64_t n_rows;                   /* rows present at load                         */
+    int64_t capacity;                 /* rows the arrays hold (>= n_rows)             */
+    int32_t append_only;              /* 1: only appended to, never read in a bulk    */
+    int32_t root_table_id;            /* table holding this table's partition root, -1 none */
+    int64_t root_div;                 /* rows of this table per root key (>= 1)       */
+    int32_t col_dtype[GPUTX_MAX_COLS];/* GPUTX_I32 / GPUTX_I64                        */
+    void* col_ptr[GPUTX_MAX_COLS];    /* device pointers                              */
+} gputx_table_desc;
+
+/* One registered transaction type (Section 3.1) with the DBA annotations of
+ * Appendix E (partitioning through the tables' root keys; single-partition
+ * flag is informational: the engine always counts cross-partition
+ * transactions from their operations). */
+typedef struct {
+    int32_t type_id;                      /* 0 .. GPUTX_MAX_TYPES-1                 */
+    int32_t proc;                         /* GPUTX_DEBIT_CREDIT ...                 */
+    int32_t n_params;                     /* parameters the procedure reads         */
+    int32_t n_results;                    /* result values it writes                */
+    int32_t table_ids[GPUTX_MAX_ROLES];   /* role bindings, see above               */
+    int32_t root_key;                     /* 1: lock only partition roots (Section 5.1) */
+    int32_t single_partition;
+} gputx_type_desc;
+
+/* A bulk, structure-of-arrays in device memory (Section 3.2 signatures). */
+typedef struct {
+    int64_t n;              /* transactions                                         */
+    const int32_t* type;    /* [n] device                                           */
+    const int64_t* params;  /* [n_params][n] device, param-major                    */
+    int32_t n_params;       /* >= every registered type's n_params it uses          */
+    const int64_t* ts;      /* [n] device, unique                                   */
+    int32_t ts_sorted;      /* 1: caller promises ascending ts (checked on device)  */
+} gputx_bulk;
+
+/* Written by the device during gputx_execute_bulk; read it after the stream
+ * has been synchronised. */
+typedef struct {
+    int32_t error;      /* 0 or a bulk error (DUP_TS, CAPACITY, UNSORTED, DEADLOCK) */
+    int32_t chosen;     /* strategy that ran                                        */
+    int64_t n_ops;      /* basic operations emitted (Section 4.1)                   */
+    int64_t w0;         /* |0-set| (Appendix D)                                     */
+    int64_t depth;      /* maximum operation rank (Section 4.2 step 5)              */
+    int64_t cross;      /* cross-partition transactions c                           */
+    int64_t waves;      /* K-SET waves executed (= true depth + 1)                  */
+    int64_t committed;
+    int64_t aborted;
+    int64_t invalid;
+    int64_t appended;   /* rows appended to append-only tables (batched update)   */
+    int64_t reserved[7];
+} gputx_bulk_stats;
+
+/* Fill *opt with defaults. */
+int gputx_default_options(gputx_options* opt);
+
+/* Create a context on HIP device hip_device; opt may be NULL (defaults). */
+int gputx_create(int hip_device, const gputx_options* opt, gputx_handle* out);
+
+/* Destroy a context (frees only its internal state). */
+int gputx_destroy(gputx_handle h);
+
+/* Replace the options of a context. */
+int gputx_set_options(gputx_handle h, const gputx_options* opt);
+
+/* Load (borrow) tables: the database is loaded once and stays resident
+ * (Appendix E); load cost is not part of bulk execution.  May be called
+ * again to add tables; row counts of append tables then live on the device
+ * and advance with every bulk.  Errors: GPUTX_E_ARG. */
+int gputx_load_tables(gputx_handle h, const gputx_table_desc* t, int n);
+
+/* Register transaction types (Section 3.1: the combined kernel switches on
+ * the type).  Tables must be loaded first.  Errors: GPUTX_E_TYPE for an
+ * unknown procedure or a role bound to a missing or mis-typed table. */
+int gputx_register_types(gputx_handle h, const gputx_type_desc* t, int n);
+
+/* Workspace bytes gputx_execute_bulk needs for up to n_txns transactions. */
+size_t gputx_workspace_size(gputx_handle h, int64_t n_txns);
+
+/* Execute one bulk (Section 5): order by timestamp, derive the basic
+ * operations, group and rank them (Section 4.2), choose a strategy
+ * (Algorithm 1, when strategy == GPUTX_AUTO) and run it, then apply the
+ * batched appends.
+ *   workspace: device, ws_bytes >= gputx_workspace_size(h, b->n).
+ *   status_out: device int32[n]; results_out: device int64[n][width]; both
+ *     indexed by the transaction's position in the bulk arrays.  Unused
+ *     result entries are written 0.
+ *   stats: device gputx_bulk_stats, overwritten.
+ * Host-detectable errors return synchronously with nothing launched.  Device-
+ * detected bulk errors (duplicate or unsorted timestamps, append overflow)
+ * land in stats->error and leave every table unmodified. */
+int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
+                       size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
+                       gputx_bulk_stats* stats, gputx_stream_t stream);
+
+/* Current row count of a table (append tables advance on the device);
+ * synchronises the stream. */
+int gputx_row_count(gputx_handle h, int32_t table_id, int64_t* out, gputx_stream_t stream);
+
+/* Message of the last error on this context (static storage, never NULL). */
+const char* gputx_last_error(gputx_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPUTX_H */

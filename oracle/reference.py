@@ -292,11 +292,13 @@ def partitions_of(ops: Dict, roots: Dict[str, Tuple[str, int]], part_size: int) 
 
 
 def features(txn_ops: List[Dict], roots, part_size: int = 1):
-    """(w0, d, c): size of the 0-set, depth computed as the maximum paper rank
+    """(w0, d, c): size of the 0-set (transactions with operations and no
+    conflicting predecessor), depth computed as the maximum paper rank
     (Section 4.2 step 5), and the number of transactions whose items span more
     than one partition (Appendix D)."""
     _, _, maxrank = paper_ranks(txn_ops)
-    w0 = int((maxrank == 0).sum())
+    live = np.array([len(o) > 0 for o in txn_ops], dtype=bool)   # invalid txns have no ops
+    w0 = int(((maxrank == 0) & live).sum())
     d = int(maxrank.max()) if len(maxrank) else 0
     c = sum(1 for ops in txn_ops if len(partitions_of(ops, roots, part_size)) > 1)
     return w0, d, c

@@ -1,0 +1,88 @@
+// Internal interface between the host runtime and the engine's kernels.
+#pragma once
+#include "procs.h"
+#include "sort.h"
+
+namespace gtx {
+
+// Tile aggregate of the operation-ranking scan.
+struct RankAgg {
+    int32_t segf;  // a group starts inside the tile
+    int32_t segs;  // rank increments after the last group start (or all)
+    int32_t gs;    // last group-start position (inclusive max), -1 none
+    int32_t A;     // max over writes of position + 1
+    int32_t g;     // group starts
+    int32_t B;     // min over writes and group starts of position (m: none)
+};
+
+// Device workspace of one bulk (carved from the caller's workspace).
+struct Ws {
+    GtxState* st;
+    uint64_t* tsk[2];    // timestamp sort keys
+    uint32_t* tsv[2];    // timestamp sort values: input index
+    int32_t* tty;        // [n] type id at serial position, -1 invalid
+    int32_t* cnt;        // [(1 + GTX_MAX_APPEND)][n]: op count then appends; scanned in place
+    int32_t* maxrank;    // [n]
+    int32_t* indeg;      // [n]
+    int32_t* op_txn;     // [mcap] serial position of each operation
+    uint32_t* pk[2];     // [mcap] operation sort: item key
+    uint32_t* pv[2];     // [mcap] operation sort: op index << 1 | write
+    int32_t* op_grp;     // [mcap] lock group (distinct item) of the op
+    int32_t* op_tgt;     // [mcap] completed ops of the group the op waits for
+    int32_t* op_slo;     // [mcap] successor range in sorted order
+    int32_t* op_shi;
+    int32_t* srt_txn;    // [mcap] serial position of each sorted op
+    int32_t* grp_cnt;    // [mcap] per-group completion counters
+    uint32_t* qk[2];     // [n] PART sort: partition id
+    uint32_t* qv[2];     // [n] PART sort: serial position
+    int32_t* front[2];   // [n] K-SET frontiers
+    uint32_t* sort_hist; // [8][256]
+    uint32_t* sort_status;
+    uint32_t* sort_ctrl; // [16]
+    int32_t* scan_tmp;   // [(1 + GTX_MAX_APPEND)][scan blocks]
+    RankAgg* rank_tmp;   // [2][rank tiles]
+};
+
+struct BulkArgs {
+    const int32_t* type;
+    const int64_t* params;
+    const int64_t* ts;
+    int64_t n;
+    int32_t n_params;
+    int32_t ts_sorted;
+    int32_t* status;
+    int64_t* results;
+    int32_t width;
+    int32_t n_app;          // append tables in the context
+    const DevType* types;   // [GPUTX_MAX_TYPES]
+    int64_t* rowcount;      // [GTX_MAX_APPEND] device row counts of append tables
+    const int64_t* capacity;// [GTX_MAX_APPEND]
+    gputx_bulk_stats* stats;
+    int64_t mcap;           // operation capacity of the workspace
+    int32_t key_passes;     // digits of the item-key sort
+    int32_t part_passes;    // digits of the partition sort
+    int64_t n_parts;        // partitions (sentinel id = n_parts)
+    int32_t strategy;       // requested (GPUTX_AUTO ...)
+    int32_t group_by_type;
+    int64_t w0_bar, c_bar, d_bar;
+    int32_t kset_narrow;
+    int32_t grid_blocks;    // persistent grid size
+    uint64_t spin_ticks;    // watchdog
+    Ws ws;
+};
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = GTX_BLOCK * kScanItems;
+constexpr int kRankItems = 8;
+constexpr int kRankTile = GTX_BLOCK * kRankItems;
+
+// bulk generation (kernels_front.hip)
+void launch_front(const BulkArgs& a, hipStream_t s);
+// execution (kernels_exec.hip)
+void launch_exec(const BulkArgs& a, hipStream_t s);
+// zero-transaction bulk: reset state and publish statistics
+void launch_empty(const BulkArgs& a, hipStream_t s);
+// workgroups of the persistent executors that fit on one compute unit
+int exec_resident_blocks_per_cu();
+
+}  // namespace gtx

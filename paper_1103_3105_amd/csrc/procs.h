@@ -1,0 +1,292 @@
+// Compiled-in stored procedures and their basic operations.
+//
+// Section 3.2: every registered type is a device function and all of them
+// form one kernel through a switch on the type.  Section 4.1: a transaction
+// is a set of basic operations, each a read or a write of one data item;
+// items here are table rows (a coarsening of the paper's field granularity
+// that keeps every conflict, Appendix B), and a read-modify-write is one
+// write.  Section 5.1: in root-key mode a type locks only the primary key of
+// the root relation of its tree-shaped schema instead of every row.
+#pragma once
+#include "common.h"
+
+namespace gtx {
+
+// One registered type with its table bindings resolved (built on the host).
+struct DevType {
+    int32_t proc;       // GPUTX_* procedure, 0 = not registered
+    int32_t n_params;
+    int32_t n_results;
+    int32_t root_key;
+    int32_t app_idx[2];  // append-table index of the procedure's appends (-1: none)
+    int32_t pad[2];
+    int64_t dims[4];     // procedure dimensions (see type registration)
+    int64_t rows[GTX_ROLES];        // rows of each bound (non-append) table
+    int64_t root_div[GTX_ROLES];    // rows per root key
+    int64_t part_base[GTX_ROLES];   // first global partition id of the role's root table
+    int64_t part_size;              // root keys per partition
+    uint32_t key_base[GTX_ROLES];   // first item key of the role's table
+    uint32_t root_base[GTX_ROLES];  // first item key of the role's root table
+    void* col[GTX_ROLES][GPUTX_MAX_COLS];
+};
+
+// Basic operations of one transaction: item key, write flag, partition id.
+struct OpList {
+    int n;
+    uint32_t key[GTX_MAX_OPS];
+    uint32_t w[GTX_MAX_OPS];
+    int64_t pid[GTX_MAX_OPS];
+};
+
+__device__ __forceinline__ bool in_range(int64_t v, int64_t n) { return v >= 0 && v < n; }
+__device__ __forceinline__ bool fits_i32(int64_t v) { return v >= INT32_MIN && v <= INT32_MAX; }
+__device__ __forceinline__ int64_t wrap_add(int64_t a, int64_t b) {
+    return (int64_t)((uint64_t)a + (uint64_t)b);
+}
+__device__ __forceinline__ int32_t to_i32(int64_t v) { return (int32_t)(uint32_t)(uint64_t)v; }
+
+// Parameter validity; an invalid transaction has no effect (status INVALID).
+__device__ inline bool txn_valid(const DevType& T, const int64_t* p) {
+    switch (T.proc) {
+    case GPUTX_DEBIT_CREDIT:
+        return in_range(p[0], T.rows[0]) && in_range(p[1], T.rows[1]) && in_range(p[2], T.rows[2]);
+    case GPUTX_NEW_ORDER: {
+        if (!(in_range(p[0], T.dims[0]) && in_range(p[1], T.dims[1]) && in_range(p[2], T.dims[2])))
+            return false;
+        int64_t k = p[3];
+        if (k < 1 || k > 15) return false;
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < 15; ++j)
+            if (j < k) ok = ok && in_range(p[4 + j], T.dims[3]) && p[19 + j] >= 1 && p[19 + j] <= 1000;
+        return ok;
+    }
+    case GPUTX_PAYMENT:
+    case GPUTX_ORDER_STATUS:
+        return in_range(p[0], T.dims[0]) && in_range(p[1], T.dims[1]) && in_range(p[2], T.dims[2]);
+    case GPUTX_GET_SUB:
+        return in_range(p[0], T.rows[0]);
+    case GPUTX_GET_CF:
+    case GPUTX_DEL_CF:
+        return in_range(p[0], T.rows[0]) && in_range(p[1], 12);
+    case GPUTX_UPD_SUB_FIELD:
+        return in_range(p[0], T.rows[0]) && in_range(p[1], 4) && fits_i32(p[2]);
+    case GPUTX_UPD_LOC:
+        return in_range(p[0], T.rows[0]) && in_range(p[1], 10) && fits_i32(p[2]);
+    case GPUTX_INS_CF:
+        return in_range(p[0], T.rows[0]) && in_range(p[1], 12) && fits_i32(p[2]);
+    }
+    return false;
+}
+
+// Rows appended to the procedure's append tables (slot 0, slot 1).
+__device__ __forceinline__ void txn_appends(const DevType& T, const int64_t* p, int* a0, int* a1) {
+    *a0 = 0;
+    *a1 = 0;
+    if (T.proc == GPUTX_DEBIT_CREDIT) *a0 = 1;
+    if (T.proc == GPUTX_NEW_ORDER) { *a0 = 1; *a1 = (int)p[3]; }
+}
+
+__device__ __forceinline__ void op_add(OpList& L, const DevType& T, int role, int64_t row, bool w) {
+    int64_t rk = row / T.root_div[role];
+    uint32_t key = T.root_key ? T.root_base[role] + (uint32_t)rk : T.key_base[role] + (uint32_t)row;
+    int64_t pid = T.part_base[role] < 0 ? -1 : T.part_base[role] + rk / T.part_size;
+    // deduplicate: one operation per item, a write if any access writes
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < GTX_MAX_OPS; ++i) {
+        if (i < L.n && L.key[i] == key) {
+            L.w[i] |= (uint32_t)w;
+            found = true;
+        }
+    }
+    if (found) return;
+#pragma unroll
+    for (int i = 0; i < GTX_MAX_OPS; ++i) {
+        if (i == L.n) {
+            L.key[i] = key;
+            L.w[i] = (uint32_t)w;
+            L.pid[i] = pid;
+        }
+    }
+    L.n++;
+}
+
+// Basic operations of a valid transaction (Section 4.1), in procedure order.
+__device__ inline void txn_ops(const DevType& T, const int64_t* p, OpList& L) {
+    L.n = 0;
+    switch (T.proc) {
+    case GPUTX_DEBIT_CREDIT:
+        op_add(L, T, 0, p[0], true);
+        op_add(L, T, 1, p[1], true);
+        op_add(L, T, 2, p[2], true);
+        break;
+    case GPUTX_NEW_ORDER:
+#pragma unroll
+        for (int j = 0; j < 15; ++j)
+            if (j < p[3]) op_add(L, T, 3, p[0] * T.dims[3] + p[4 + j], true);
+        break;
+    case GPUTX_PAYMENT: {
+        int64_t drow = p[0] * T.dims[1] + p[1];
+        op_add(L, T, 0, p[0], true);
+        op_add(L, T, 1, drow, true);
+        op_add(L, T, 2, drow * T.dims[2] + p[2], true);
+        break;
+    }
+    case GPUTX_ORDER_STATUS:
+        op_add(L, T, 2, (p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2], false);
+        break;
+    case GPUTX_GET_SUB:
+        op_add(L, T, 0, p[0], false);
+        break;
+    case GPUTX_GET_CF:
+        op_add(L, T, 1, p[0] * 12 + p[1], false);
+        break;
+    case GPUTX_UPD_SUB_FIELD:
+    case GPUTX_UPD_LOC:
+        op_add(L, T, 0, p[0], true);
+        break;
+    case GPUTX_INS_CF:
+    case GPUTX_DEL_CF:
+        op_add(L, T, 1, p[0] * 12 + p[1], true);
+        break;
+    }
+}
+
+// Parameters of transaction i (param-major bulk), zero past np.
+__device__ __forceinline__ void load_params(const int64_t* __restrict__ params, int64_t n, int np,
+                                            int64_t i, int64_t* p) {
+#pragma unroll
+    for (int k = 0; k < GTX_MAX_PARAMS; ++k) p[k] = (k < np) ? params[(int64_t)k * n + i] : 0;
+}
+
+template <class V>
+__device__ __forceinline__ V* colp(const DevType& T, int role, int c) {
+    return reinterpret_cast<V*>(T.col[role][c]);
+}
+
+// Run one valid transaction: the switch of Section 3.2.  app0/app1 are the
+// rows its appends occupy.  Returns its status, fills res[0..15].
+__device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t ts, int64_t app0,
+                                   int64_t app1, int64_t* res) {
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
+    switch (T.proc) {
+    case GPUTX_DEBIT_CREDIT: {
+        int64_t* A = colp<int64_t>(T, 0, 0);
+        int64_t* Tl = colp<int64_t>(T, 1, 0);
+        int64_t* B = colp<int64_t>(T, 2, 0);
+        int64_t a = wrap_add(A[p[0]], p[3]);
+        int64_t t = wrap_add(Tl[p[1]], p[3]);
+        int64_t b = wrap_add(B[p[2]], p[3]);
+        A[p[0]] = a;
+        Tl[p[1]] = t;
+        B[p[2]] = b;
+        colp<int64_t>(T, 3, 0)[app0] = p[0];
+        colp<int64_t>(T, 3, 1)[app0] = p[1];
+        colp<int64_t>(T, 3, 2)[app0] = p[2];
+        colp<int64_t>(T, 3, 3)[app0] = p[3];
+        colp<int64_t>(T, 3, 4)[app0] = ts;
+        res[0] = a;
+        res[1] = t;
+        res[2] = b;
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_NEW_ORDER: {
+        int32_t* S = colp<int32_t>(T, 3, 0);
+        int64_t k = p[3];
+        res[0] = k;
+#pragma unroll
+        for (int j = 0; j < 15; ++j) {
+            if (j < k) {
+                int64_t row = p[0] * T.dims[3] + p[4 + j];
+                int64_t s = (int64_t)S[row] - p[19 + j];
+                if (s < 10) s += 91;
+                int32_t s32 = to_i32(s);
+                S[row] = s32;
+                res[1 + j] = s32;
+                int64_t r = app1 + j;
+                colp<int64_t>(T, 5, 0)[r] = ts;
+                colp<int64_t>(T, 5, 1)[r] = j;
+                colp<int64_t>(T, 5, 2)[r] = p[4 + j];
+                colp<int64_t>(T, 5, 3)[r] = p[19 + j];
+                colp<int64_t>(T, 5, 4)[r] = p[0];
+            }
+        }
+        colp<int64_t>(T, 4, 0)[app0] = ts;
+        colp<int64_t>(T, 4, 1)[app0] = p[0];
+        colp<int64_t>(T, 4, 2)[app0] = p[1];
+        colp<int64_t>(T, 4, 3)[app0] = p[2];
+        colp<int64_t>(T, 4, 4)[app0] = k;
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_PAYMENT: {
+        int64_t drow = p[0] * T.dims[1] + p[1];
+        int64_t crow = drow * T.dims[2] + p[2];
+        int64_t* Wb = colp<int64_t>(T, 0, 0);
+        int64_t* Db = colp<int64_t>(T, 1, 0);
+        int64_t* Cb = colp<int64_t>(T, 2, 0);
+        int64_t w = wrap_add(Wb[p[0]], p[3]);
+        int64_t d = wrap_add(Db[drow], p[3]);
+        int64_t c = wrap_add(Cb[crow], p[3]);
+        Wb[p[0]] = w;
+        Db[drow] = d;
+        Cb[crow] = c;
+        res[0] = w;
+        res[1] = d;
+        res[2] = c;
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_ORDER_STATUS: {
+        int64_t crow = (p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2];
+        res[0] = colp<int64_t>(T, 2, 0)[crow];
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_GET_SUB: {
+#pragma unroll
+        for (int f = 0; f < 14; ++f) res[f] = colp<int32_t>(T, 0, 1 + f)[p[0]];
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_GET_CF: {
+        int64_t slot = p[0] * 12 + p[1];
+        res[0] = colp<int32_t>(T, 1, 0)[slot];
+        res[1] = colp<int32_t>(T, 1, 1)[slot];
+        res[2] = colp<int64_t>(T, 1, 2)[slot];
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_UPD_SUB_FIELD:
+    case GPUTX_UPD_LOC: {
+        int c = 1 + (int)p[1] + (T.proc == GPUTX_UPD_LOC ? 4 : 0);
+        int32_t* F = colp<int32_t>(T, 0, c);
+        res[0] = F[p[0]];
+        F[p[0]] = to_i32(p[2]);
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_INS_CF: {
+        int64_t slot = p[0] * 12 + p[1];
+        int32_t* occ = colp<int32_t>(T, 1, 0);
+        int32_t o = occ[slot];
+        res[0] = o;
+        if (o) return GPUTX_ABORT;  // read phase decides; nothing written
+        occ[slot] = 1;
+        colp<int32_t>(T, 1, 1)[slot] = to_i32(p[2]);
+        colp<int64_t>(T, 1, 2)[slot] = p[3];
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_DEL_CF: {
+        int64_t slot = p[0] * 12 + p[1];
+        int32_t* occ = colp<int32_t>(T, 1, 0);
+        if (!occ[slot]) return GPUTX_ABORT;
+        res[0] = 1;
+        res[1] = colp<int32_t>(T, 1, 1)[slot];
+        res[2] = colp<int64_t>(T, 1, 2)[slot];
+        occ[slot] = 0;
+        colp<int32_t>(T, 1, 1)[slot] = 0;
+        colp<int64_t>(T, 1, 2)[slot] = 0;
+        return GPUTX_COMMIT;
+    }
+    }
+    return GPUTX_INVALID;
+}
+
+}  // namespace gtx

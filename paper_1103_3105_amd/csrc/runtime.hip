@@ -1,0 +1,485 @@
+// Host runtime: the C ABI of include/gputx.h.
+//
+// A context holds the catalog (Appendix E: column metadata on the host,
+// columns in device memory), the registered types resolved to device
+// descriptors (Section 3.1), the device row counts of the append tables
+// (Section 3.2 batched update) and the options of Algorithm 1.  A bulk runs
+// as an asynchronous sequence of kernels on the caller's stream; every
+// decision after the input arrives (timestamp order, strategy, wave count)
+// is taken on the device, so no host round trip sits inside a bulk.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "engine.h"
+
+using namespace gtx;
+
+struct gputx_ctx {
+    int device = 0;
+    int ncu = 0;
+    uint64_t wall_khz = 0;
+    gputx_options opt{};
+    struct Tab {
+        bool present = false;
+        gputx_table_desc d{};
+        int app_idx = -1;
+        uint32_t key_base = 0;
+        int64_t part_base = -1;  // for root tables: first global partition id
+    } tabs[GPUTX_MAX_TABLES];
+    int n_app = 0;
+    int app_table[GTX_MAX_APPEND] = {-1, -1, -1, -1};
+    uint64_t total_items = 0;
+    int key_passes = 1;
+    int64_t n_parts = 0;
+    int part_passes = 1;
+    bool type_present[GPUTX_MAX_TYPES] = {};
+    gputx_type_desc types[GPUTX_MAX_TYPES]{};
+    int max_ops = 1;
+    DevType* d_types = nullptr;
+    int64_t* d_rowcount = nullptr;
+    int64_t* d_capacity = nullptr;
+    std::string err;
+};
+
+static thread_local std::string g_err;
+
+static int set_err(gputx_handle h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+static int set_err(gputx_handle h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    else g_err = buf;
+    return code;
+}
+
+#define HIP_OK(h, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err((h), GPUTX_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static int bits_for(uint64_t v) {  // bits needed to represent v
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+static int passes_for(uint64_t maxkey) {
+    int p = (bits_for(maxkey) + 7) / 8;
+    return p < 1 ? 1 : p;
+}
+
+extern "C" int gputx_default_options(gputx_options* o) {
+    if (!o) return GPUTX_E_ARG;
+    o->w0_bar = 16384;   // about one wave64 per SIMD of 256 CUs x 4 SIMDs x 16 (recalibrated by the autotuner)
+    o->c_bar = 0;
+    o->d_bar = 1 << 30;
+    o->part_size = 1;
+    o->group_by_type = 1;
+    o->kset_narrow = 256;
+    o->spin_limit_ms = 5000;
+    o->grid_blocks = 0;
+    return GPUTX_OK;
+}
+
+static int refresh_layout(gputx_handle h);
+
+extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out) {
+    if (!out) return set_err(nullptr, GPUTX_E_ARG, "out is null");
+    *out = nullptr;
+    gputx_handle h = new gputx_ctx();
+    h->device = dev;
+    if (opt) h->opt = *opt;
+    else gputx_default_options(&h->opt);
+    hipError_t e = hipSetDevice(dev);
+    int ncu = 0, khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e == hipSuccess) e = hipMalloc(&h->d_types, sizeof(DevType) * GPUTX_MAX_TYPES);
+    if (e == hipSuccess) e = hipMalloc(&h->d_rowcount, sizeof(int64_t) * GTX_MAX_APPEND);
+    if (e == hipSuccess) e = hipMalloc(&h->d_capacity, sizeof(int64_t) * GTX_MAX_APPEND);
+    if (e == hipSuccess) e = hipMemset(h->d_types, 0, sizeof(DevType) * GPUTX_MAX_TYPES);
+    if (e == hipSuccess) e = hipMemset(h->d_rowcount, 0, sizeof(int64_t) * GTX_MAX_APPEND);
+    if (e == hipSuccess) e = hipMemset(h->d_capacity, 0, sizeof(int64_t) * GTX_MAX_APPEND);
+    if (e != hipSuccess) {
+        int rc = set_err(nullptr, GPUTX_E_HIP, "device setup failed: %s", hipGetErrorString(e));
+        if (h->d_types) (void)hipFree(h->d_types);
+        if (h->d_rowcount) (void)hipFree(h->d_rowcount);
+        if (h->d_capacity) (void)hipFree(h->d_capacity);
+        delete h;
+        return rc;
+    }
+    h->ncu = ncu;
+    h->wall_khz = khz > 0 ? (uint64_t)khz : 100000;
+    *out = h;
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_destroy(gputx_handle h) {
+    if (!h) return GPUTX_E_ARG;
+    (void)hipSetDevice(h->device);
+    (void)hipFree(h->d_types);
+    (void)hipFree(h->d_rowcount);
+    (void)hipFree(h->d_capacity);
+    delete h;
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_set_options(gputx_handle h, const gputx_options* opt) {
+    if (!h || !opt) return set_err(h, GPUTX_E_ARG, "null argument");
+    if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0)
+        return set_err(h, GPUTX_E_ARG, "bad option value");
+    h->opt = *opt;
+    return refresh_layout(h);
+}
+
+extern "C" int gputx_load_tables(gputx_handle h, const gputx_table_desc* t, int n) {
+    if (!h || (n > 0 && !t) || n < 0) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    HIP_OK(h, hipSetDevice(h->device));
+    for (int i = 0; i < n; ++i) {
+        const gputx_table_desc& d = t[i];
+        if (d.table_id < 0 || d.table_id >= GPUTX_MAX_TABLES)
+            return set_err(h, GPUTX_E_ARG, "table_id %d out of range", d.table_id);
+        if (h->tabs[d.table_id].present)
+            return set_err(h, GPUTX_E_ARG, "table %d already loaded", d.table_id);
+        if (d.n_cols < 1 || d.n_cols > GPUTX_MAX_COLS || d.n_rows < 0 || d.capacity < d.n_rows)
+            return set_err(h, GPUTX_E_ARG, "table %d: bad shape", d.table_id);
+        if (d.root_table_id >= GPUTX_MAX_TABLES || (d.root_table_id >= 0 && d.root_div < 1))
+            return set_err(h, GPUTX_E_ARG, "table %d: bad root", d.table_id);
+        for (int c = 0; c < d.n_cols; ++c) {
+            if (d.col_dtype[c] != GPUTX_I32 && d.col_dtype[c] != GPUTX_I64)
+                return set_err(h, GPUTX_E_ARG, "table %d col %d: bad dtype", d.table_id, c);
+            if (!d.col_ptr[c] && d.capacity > 0)
+                return set_err(h, GPUTX_E_ARG, "table %d col %d: null column", d.table_id, c);
+        }
+        if (d.append_only && h->n_app >= GTX_MAX_APPEND)
+            return set_err(h, GPUTX_E_CAPACITY, "at most %d append-only tables", GTX_MAX_APPEND);
+    }
+    for (int i = 0; i < n; ++i) {
+        const gputx_table_desc& d = t[i];
+        auto& T = h->tabs[d.table_id];
+        T.present = true;
+        T.d = d;
+        if (d.append_only) {
+            T.app_idx = h->n_app;
+            h->app_table[h->n_app] = d.table_id;
+            int64_t rc = d.n_rows, cap = d.capacity;
+            HIP_OK(h, hipMemcpy(h->d_rowcount + h->n_app, &rc, 8, hipMemcpyHostToDevice));
+            HIP_OK(h, hipMemcpy(h->d_capacity + h->n_app, &cap, 8, hipMemcpyHostToDevice));
+            h->n_app++;
+        }
+    }
+    return refresh_layout(h);
+}
+
+// Item keys (Section 4.1 data items) are dense: table key base + row.
+// Partition ids (Section 5.2) are dense per root table: base + root / size.
+static int refresh_layout(gputx_handle h) {
+    uint64_t base = 0;
+    for (int i = 0; i < GPUTX_MAX_TABLES; ++i) {
+        auto& T = h->tabs[i];
+        if (!T.present || T.d.append_only) continue;
+        T.key_base = (uint32_t)base;
+        base += (uint64_t)T.d.n_rows;
+    }
+    if (base >= 0xffffffffull) return set_err(h, GPUTX_E_CAPACITY, "more than 2^32-1 data items");
+    h->total_items = base;
+    h->key_passes = passes_for(base ? base - 1 : 0);
+    int64_t pb = 0;
+    bool is_root[GPUTX_MAX_TABLES] = {};
+    for (int i = 0; i < GPUTX_MAX_TABLES; ++i)
+        if (h->tabs[i].present && h->tabs[i].d.root_table_id >= 0) is_root[h->tabs[i].d.root_table_id] = true;
+    for (int i = 0; i < GPUTX_MAX_TABLES; ++i) {
+        auto& T = h->tabs[i];
+        T.part_base = -1;
+        if (!T.present || !is_root[i]) continue;
+        T.part_base = pb;
+        pb += (T.d.n_rows + h->opt.part_size - 1) / h->opt.part_size;
+    }
+    if (pb >= 0xffffffffll) return set_err(h, GPUTX_E_CAPACITY, "too many partitions");
+    h->n_parts = pb;
+    h->part_passes = passes_for((uint64_t)pb);  // sentinel id = n_parts
+    // re-resolve registered types (key bases or partition size may have moved)
+    for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
+        if (!h->type_present[t]) continue;
+        int rc = gputx_register_types(h, &h->types[t], 1);
+        if (rc) return rc;
+    }
+    return GPUTX_OK;
+}
+
+struct ProcSpec {
+    int n_roles;
+    int min_params;
+    int max_results;
+    int ops;
+    // per role: expected dtypes (0 = unchecked), append flag
+    int append[GTX_ROLES];
+    int ncols[GTX_ROLES];
+    int dtype[GTX_ROLES][16];
+};
+
+static bool proc_spec(int proc, ProcSpec* s) {
+    std::memset(s, 0, sizeof *s);
+    auto role = [&](int r, int app, std::initializer_list<int> dts) {
+        s->append[r] = app;
+        int c = 0;
+        for (int d : dts) s->dtype[r][c++] = d;
+        s->ncols[r] = c;
+    };
+    const int I = GPUTX_I32, L = GPUTX_I64;
+    switch (proc) {
+    case GPUTX_DEBIT_CREDIT:
+        s->n_roles = 4; s->min_params = 4; s->max_results = 3; s->ops = 3;
+        role(0, 0, {L}); role(1, 0, {L}); role(2, 0, {L}); role(3, 1, {L, L, L, L, L});
+        return true;
+    case GPUTX_NEW_ORDER:
+    case GPUTX_PAYMENT:
+    case GPUTX_ORDER_STATUS:
+        s->n_roles = 6;
+        s->min_params = proc == GPUTX_NEW_ORDER ? 34 : (proc == GPUTX_PAYMENT ? 4 : 3);
+        s->max_results = proc == GPUTX_NEW_ORDER ? 16 : (proc == GPUTX_PAYMENT ? 3 : 1);
+        s->ops = proc == GPUTX_NEW_ORDER ? 15 : (proc == GPUTX_PAYMENT ? 3 : 1);
+        role(0, 0, {L}); role(1, 0, {L}); role(2, 0, {L}); role(3, 0, {I});
+        role(4, 1, {L, L, L, L, L}); role(5, 1, {L, L, L, L, L});
+        return true;
+    case GPUTX_GET_SUB:
+    case GPUTX_GET_CF:
+    case GPUTX_UPD_SUB_FIELD:
+    case GPUTX_UPD_LOC:
+    case GPUTX_INS_CF:
+    case GPUTX_DEL_CF:
+        s->n_roles = 2; s->ops = 1;
+        s->min_params = (proc == GPUTX_GET_SUB) ? 1 : (proc == GPUTX_INS_CF ? 4 :
+                        (proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 2 : 3);
+        s->max_results = proc == GPUTX_GET_SUB ? 14 : ((proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 3 : 1);
+        role(0, 0, {L, I, I, I, I, I, I, I, I, I, I, I, I, I, I});
+        role(1, 0, {I, I, L});
+        return true;
+    }
+    return false;
+}
+
+extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, int n) {
+    if (!h || (n > 0 && !t) || n < 0) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    HIP_OK(h, hipSetDevice(h->device));
+    for (int i = 0; i < n; ++i) {
+        const gputx_type_desc& d = t[i];
+        if (d.type_id < 0 || d.type_id >= GPUTX_MAX_TYPES)
+            return set_err(h, GPUTX_E_ARG, "type_id %d out of range", d.type_id);
+        ProcSpec ps;
+        if (!proc_spec(d.proc, &ps)) return set_err(h, GPUTX_E_TYPE, "type %d: unknown procedure %d", d.type_id, d.proc);
+        if (d.n_params < ps.min_params || d.n_params > GTX_MAX_PARAMS)
+            return set_err(h, GPUTX_E_TYPE, "type %d: n_params %d, procedure needs %d", d.type_id, d.n_params, ps.min_params);
+        DevType D;
+        std::memset(&D, 0, sizeof D);
+        D.proc = d.proc;
+        D.n_params = d.n_params;
+        D.n_results = d.n_results;
+        D.root_key = d.root_key ? 1 : 0;
+        D.app_idx[0] = D.app_idx[1] = -1;
+        D.part_size = h->opt.part_size;
+        int app_slot = 0;
+        for (int r = 0; r < ps.n_roles; ++r) {
+            int tid = d.table_ids[r];
+            if (tid < 0 || tid >= GPUTX_MAX_TABLES || !h->tabs[tid].present)
+                return set_err(h, GPUTX_E_TYPE, "type %d role %d: table %d not loaded", d.type_id, r, tid);
+            for (int r2 = 0; r2 < r; ++r2)
+                if (d.table_ids[r2] == tid)
+                    return set_err(h, GPUTX_E_TYPE, "type %d: table %d bound to two roles", d.type_id, tid);
+            const auto& T = h->tabs[tid];
+            if (!!T.d.append_only != !!ps.append[r])
+                return set_err(h, GPUTX_E_TYPE, "type %d role %d: append-only mismatch", d.type_id, r);
+            if (T.d.n_cols < ps.ncols[r])
+                return set_err(h, GPUTX_E_TYPE, "type %d role %d: needs %d columns", d.type_id, r, ps.ncols[r]);
+            for (int c = 0; c < ps.ncols[r]; ++c)
+                if (T.d.col_dtype[c] != ps.dtype[r][c])
+                    return set_err(h, GPUTX_E_TYPE, "type %d role %d col %d: wrong dtype", d.type_id, r, c);
+            for (int c = 0; c < T.d.n_cols; ++c) D.col[r][c] = T.d.col_ptr[c];
+            D.rows[r] = T.d.n_rows;
+            D.key_base[r] = T.key_base;
+            if (T.d.root_table_id >= 0) {
+                const auto& R = h->tabs[T.d.root_table_id];
+                if (!R.present) return set_err(h, GPUTX_E_TYPE, "table %d: root table %d not loaded", tid, T.d.root_table_id);
+                D.root_div[r] = T.d.root_div;
+                D.root_base[r] = R.key_base;
+                D.part_base[r] = R.part_base;
+            } else {
+                D.root_div[r] = 1;
+                D.root_base[r] = T.key_base;
+                D.part_base[r] = -1;
+                if (d.root_key && !ps.append[r])
+                    return set_err(h, GPUTX_E_TYPE, "type %d: root-key mode but table %d has no root", d.type_id, tid);
+            }
+            if (ps.append[r]) {
+                if (d.proc == GPUTX_DEBIT_CREDIT || d.proc == GPUTX_NEW_ORDER) D.app_idx[app_slot] = T.app_idx;
+                ++app_slot;
+            }
+        }
+        if (d.proc == GPUTX_NEW_ORDER || d.proc == GPUTX_PAYMENT || d.proc == GPUTX_ORDER_STATUS) {
+            int64_t nw = D.rows[0], nd = D.rows[1];
+            if (nw < 1 || nd < 1) return set_err(h, GPUTX_E_TYPE, "type %d: empty warehouse/district", d.type_id);
+            D.dims[0] = nw;
+            D.dims[1] = nd / nw;
+            D.dims[2] = D.rows[2] / nd;
+            D.dims[3] = D.rows[3] / nw;
+        }
+        HIP_OK(h, hipMemcpy(h->d_types + d.type_id, &D, sizeof D, hipMemcpyHostToDevice));
+        h->types[d.type_id] = d;
+        h->type_present[d.type_id] = true;
+    }
+    int mo = 1;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
+        if (!h->type_present[i]) continue;
+        ProcSpec ps;
+        proc_spec(h->types[i].proc, &ps);
+        mo = std::max(mo, ps.ops);
+    }
+    h->max_ops = mo;
+    return GPUTX_OK;
+}
+
+// ---- workspace layout -----------------------------------------------------
+struct Layout {
+    size_t off = 0;
+    char* base = nullptr;
+    template <class T>
+    T* take(int64_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+        return p;
+    }
+};
+
+static void plan_ws(const gputx_ctx* h, int64_t n, void* base, Ws* ws, size_t* bytes, int64_t* mcap_out) {
+    Layout L;
+    L.base = (char*)base;
+    const int64_t mcap = n * h->max_ops;
+    Ws w{};
+    w.st = L.take<GtxState>(1);
+    w.tsk[0] = L.take<uint64_t>(n); w.tsk[1] = L.take<uint64_t>(n);
+    w.tsv[0] = L.take<uint32_t>(n); w.tsv[1] = L.take<uint32_t>(n);
+    w.tty = L.take<int32_t>(n);
+    w.cnt = L.take<int32_t>(n * (1 + GTX_MAX_APPEND));
+    w.maxrank = L.take<int32_t>(n);
+    w.indeg = L.take<int32_t>(n);
+    w.op_txn = L.take<int32_t>(mcap);
+    w.pk[0] = L.take<uint32_t>(mcap); w.pk[1] = L.take<uint32_t>(mcap);
+    w.pv[0] = L.take<uint32_t>(mcap); w.pv[1] = L.take<uint32_t>(mcap);
+    w.op_grp = L.take<int32_t>(mcap);
+    w.op_tgt = L.take<int32_t>(mcap);
+    w.op_slo = L.take<int32_t>(mcap);
+    w.op_shi = L.take<int32_t>(mcap);
+    w.srt_txn = L.take<int32_t>(mcap);
+    w.grp_cnt = L.take<int32_t>(mcap);
+    w.qk[0] = L.take<uint32_t>(n); w.qk[1] = L.take<uint32_t>(n);
+    w.qv[0] = L.take<uint32_t>(n); w.qv[1] = L.take<uint32_t>(n);
+    w.front[0] = L.take<int32_t>(n); w.front[1] = L.take<int32_t>(n);
+    w.sort_hist = L.take<uint32_t>(8 * 256);
+    size_t sw = std::max({sort_status_words(n, 8), sort_status_words(mcap, h->key_passes),
+                          sort_status_words(n, h->part_passes)});
+    w.sort_status = L.take<uint32_t>((int64_t)sw);
+    w.sort_ctrl = L.take<uint32_t>(16);
+    const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+    w.scan_tmp = L.take<int32_t>(nb * (1 + GTX_MAX_APPEND));
+    const int64_t nbr = std::max<int64_t>(1, (mcap + kRankTile - 1) / kRankTile);
+    w.rank_tmp = L.take<RankAgg>(2 * nbr);
+    *ws = w;
+    *bytes = L.off + 256;
+    *mcap_out = mcap;
+}
+
+extern "C" size_t gputx_workspace_size(gputx_handle h, int64_t n) {
+    if (!h || n < 0) return 0;
+    Ws w;
+    size_t b;
+    int64_t mcap;
+    plan_ws(h, n, nullptr, &w, &b, &mcap);
+    return b;
+}
+
+extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
+                                  size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
+                                  gputx_bulk_stats* stats, gputx_stream_t stream) {
+    if (!h || !b || !stats) return set_err(h, GPUTX_E_ARG, "null argument");
+    if (strategy < GPUTX_AUTO || strategy > GPUTX_KSET) return set_err(h, GPUTX_E_ARG, "bad strategy %d", strategy);
+    if (b->n < 0 || b->n > (int64_t)1 << 30) return set_err(h, GPUTX_E_ARG, "bulk size %lld", (long long)b->n);
+    if (width < 1) return set_err(h, GPUTX_E_ARG, "width must be >= 1");
+    if (b->n > 0 && (!b->type || !b->params || !b->ts || !status_out || !results_out || !workspace))
+        return set_err(h, GPUTX_E_ARG, "null bulk or output pointer");
+    if (b->n_params < 1 || b->n_params > GTX_MAX_PARAMS) return set_err(h, GPUTX_E_ARG, "n_params %d", b->n_params);
+    bool any = false;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) any = any || h->type_present[i];
+    if (!any) return set_err(h, GPUTX_E_STATE, "no registered types");
+    HIP_OK(h, hipSetDevice(h->device));
+    BulkArgs a{};
+    size_t need;
+    plan_ws(h, b->n, workspace, &a.ws, &need, &a.mcap);
+    if (ws_bytes < need) return set_err(h, GPUTX_E_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)workspace % 256) return set_err(h, GPUTX_E_ARG, "workspace must be 256-byte aligned");
+    if (a.mcap >= ((int64_t)1 << 31) - 2) return set_err(h, GPUTX_E_CAPACITY, "too many operations for one bulk");
+    a.type = b->type;
+    a.params = b->params;
+    a.ts = b->ts;
+    a.n = b->n;
+    a.n_params = b->n_params;
+    a.ts_sorted = b->ts_sorted ? 1 : 0;
+    a.status = status_out;
+    a.results = results_out;
+    a.width = width;
+    a.n_app = h->n_app;
+    a.types = h->d_types;
+    a.rowcount = h->d_rowcount;
+    a.capacity = h->d_capacity;
+    a.stats = stats;
+    a.key_passes = h->key_passes;
+    a.part_passes = h->part_passes;
+    a.n_parts = h->n_parts;
+    a.strategy = strategy;
+    a.group_by_type = h->opt.group_by_type;
+    a.w0_bar = h->opt.w0_bar;
+    a.c_bar = h->opt.c_bar;
+    a.d_bar = h->opt.d_bar;
+    a.kset_narrow = h->opt.kset_narrow;
+    int per_cu = exec_resident_blocks_per_cu();
+    int max_grid = h->ncu * std::max(per_cu, 1);
+    a.grid_blocks = h->opt.grid_blocks > 0 ? std::min(h->opt.grid_blocks, max_grid) : h->ncu;
+    a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    if (b->n == 0) {
+        launch_empty(a, s);
+    } else {
+        launch_front(a, s);
+        launch_exec(a, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_row_count(gputx_handle h, int32_t table_id, int64_t* out, gputx_stream_t stream) {
+    if (!h || !out || table_id < 0 || table_id >= GPUTX_MAX_TABLES || !h->tabs[table_id].present)
+        return set_err(h, GPUTX_E_ARG, "bad table");
+    const auto& T = h->tabs[table_id];
+    if (!T.d.append_only) {
+        *out = T.d.n_rows;
+        return GPUTX_OK;
+    }
+    HIP_OK(h, hipSetDevice(h->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_OK(h, hipMemcpyAsync(out, h->d_rowcount + T.app_idx, 8, hipMemcpyDeviceToHost, s));
+    HIP_OK(h, hipStreamSynchronize(s));
+    return GPUTX_OK;
+}
+
+extern "C" const char* gputx_last_error(gputx_handle h) {
+    if (!h) return g_err.c_str();
+    return h->err.c_str();
+}

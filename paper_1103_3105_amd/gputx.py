@@ -1,0 +1,296 @@
+"""Thin Python binding of the C ABI in include/gputx.h.
+
+Only argument marshalling lives here: every step of a bulk runs in the HIP
+kernels of libgputx.so.  torch provides device memory and streams.  There is
+no fallback: if the library is missing, importing this module raises.
+
+The functions keep the ABI's names (``gputx_create``, ``gputx_load_tables``,
+``gputx_register_types``, ``gputx_workspace_size``, ``gputx_execute_bulk``,
+``gputx_row_count`` ...).  ``Engine`` bundles them for one device database.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import c_int32, c_int64, c_void_p, c_size_t, POINTER
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgputx.so")
+
+OK, E_ARG, E_TYPE, E_DUP_TS, E_CAPACITY, E_HIP, E_STATE, E_DEADLOCK, E_UNSORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+AUTO, TPL, PART, KSET = 0, 1, 2, 3
+STRATEGY = {"AUTO": AUTO, "TPL": TPL, "PART": PART, "KSET": KSET}
+STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
+COMMIT, ABORT, INVALID = 0, 1, 2
+I32, I64 = 1, 2
+PROC = {"DEBIT_CREDIT": 1, "NEW_ORDER": 2, "PAYMENT": 3, "ORDER_STATUS": 4, "GET_SUB": 5,
+        "GET_CF": 6, "UPD_SUB_FIELD": 7, "UPD_LOC": 8, "INS_CF": 9, "DEL_CF": 10}
+MAX_TYPES, MAX_TABLES, MAX_COLS, MAX_ROLES = 16, 32, 16, 8
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("w0_bar", c_int64), ("c_bar", c_int64), ("d_bar", c_int64),
+                ("part_size", c_int64), ("group_by_type", c_int32), ("kset_narrow", c_int32),
+                ("spin_limit_ms", c_int32), ("grid_blocks", c_int32)]
+
+
+class TableDesc(ctypes.Structure):
+    _fields_ = [("table_id", c_int32), ("n_cols", c_int32), ("n_rows", c_int64),
+                ("capacity", c_int64), ("append_only", c_int32), ("root_table_id", c_int32),
+                ("root_div", c_int64), ("col_dtype", c_int32 * MAX_COLS),
+                ("col_ptr", c_void_p * MAX_COLS)]
+
+
+class TypeDesc(ctypes.Structure):
+    _fields_ = [("type_id", c_int32), ("proc", c_int32), ("n_params", c_int32),
+                ("n_results", c_int32), ("table_ids", c_int32 * MAX_ROLES),
+                ("root_key", c_int32), ("single_partition", c_int32)]
+
+
+class BulkDesc(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("type", c_void_p), ("params", c_void_p), ("n_params", c_int32),
+                ("ts", c_void_p), ("ts_sorted", c_int32)]
+
+
+class BulkStats(ctypes.Structure):
+    _fields_ = [("error", c_int32), ("chosen", c_int32), ("n_ops", c_int64), ("w0", c_int64),
+                ("depth", c_int64), ("cross", c_int64), ("waves", c_int64),
+                ("committed", c_int64), ("aborted", c_int64), ("invalid", c_int64),
+                ("appended", c_int64), ("reserved", c_int64 * 7)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k in ("error", "chosen", "n_ops", "w0", "depth", "cross",
+                                              "waves", "committed", "aborted", "invalid",
+                                              "appended")}
+
+
+STATS_BYTES = ctypes.sizeof(BulkStats)
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(the engine has no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = c_void_p
+    sig = {
+        "gputx_default_options": (c_int32, [POINTER(Options)]),
+        "gputx_create": (c_int32, [c_int32, POINTER(Options), POINTER(H)]),
+        "gputx_destroy": (c_int32, [H]),
+        "gputx_set_options": (c_int32, [H, POINTER(Options)]),
+        "gputx_load_tables": (c_int32, [H, POINTER(TableDesc), c_int32]),
+        "gputx_register_types": (c_int32, [H, POINTER(TypeDesc), c_int32]),
+        "gputx_workspace_size": (c_size_t, [H, c_int64]),
+        "gputx_execute_bulk": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
+                                         c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+        "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
+        "gputx_last_error": (ctypes.c_char_p, [H]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_options",
+           "gputx_load_tables", "gputx_register_types", "gputx_workspace_size",
+           "gputx_execute_bulk", "gputx_row_count", "gputx_last_error")
+
+
+class GputxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gputx error {code}: {msg}")
+        self.code = code
+
+
+def _check(h, rc: int):
+    if rc != OK:
+        raise GputxError(rc, lib.gputx_last_error(h).decode())
+
+
+# ---- same-name wrappers ----------------------------------------------------
+
+def gputx_default_options() -> Options:
+    o = Options()
+    _check(None, lib.gputx_default_options(ctypes.byref(o)))
+    return o
+
+
+def gputx_create(device: int = 0, options: Optional[Options] = None) -> c_void_p:
+    h = c_void_p()
+    _check(None, lib.gputx_create(device, ctypes.byref(options) if options else None,
+                                  ctypes.byref(h)))
+    return h
+
+
+def gputx_destroy(h) -> None:
+    _check(h, lib.gputx_destroy(h))
+
+
+def gputx_set_options(h, options: Options) -> None:
+    _check(h, lib.gputx_set_options(h, ctypes.byref(options)))
+
+
+def gputx_load_tables(h, descs: Sequence[TableDesc]) -> None:
+    arr = (TableDesc * len(descs))(*descs)
+    _check(h, lib.gputx_load_tables(h, arr, len(descs)))
+
+
+def gputx_register_types(h, descs: Sequence[TypeDesc]) -> None:
+    arr = (TypeDesc * len(descs))(*descs)
+    _check(h, lib.gputx_register_types(h, arr, len(descs)))
+
+
+def gputx_workspace_size(h, n: int) -> int:
+    return int(lib.gputx_workspace_size(h, n))
+
+
+def gputx_execute_bulk(h, bulk: BulkDesc, strategy: int, workspace: torch.Tensor,
+                       status: torch.Tensor, results: torch.Tensor, stats: torch.Tensor,
+                       stream: Optional[torch.cuda.Stream] = None) -> None:
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(h, lib.gputx_execute_bulk(h, ctypes.byref(bulk), strategy, workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(),
+                                     status.data_ptr(), results.data_ptr(), results.shape[1],
+                                     stats.data_ptr(), s))
+
+
+def gputx_row_count(h, table_id: int, stream: Optional[torch.cuda.Stream] = None) -> int:
+    out = c_int64()
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(h, lib.gputx_row_count(h, table_id, ctypes.byref(out), s))
+    return out.value
+
+
+def stats_from(t: torch.Tensor) -> BulkStats:
+    """Decode a device stats buffer (synchronises via the copy)."""
+    raw = t.cpu().numpy().tobytes()
+    return BulkStats.from_buffer_copy(raw)
+
+
+# ---- convenience: one device database -------------------------------------
+
+class Engine:
+    """A context with tables copied to the device and types registered.
+
+    ``tables``: name -> object with ``cols``, ``dtypes``, ``n_rows``,
+    ``capacity``, ``append``, ``root``, ``root_div`` (as produced by
+    ``workloads``); ``types``: objects with ``type_id``, ``proc``,
+    ``n_params``, ``n_results``, ``tables`` (role names), ``root_key``.
+    """
+
+    def __init__(self, tables: Dict[str, object], types: Sequence[object], device: int = 0,
+                 options: Optional[Options] = None, **opt_overrides):
+        self.device = torch.device("cuda", device)
+        opts = options or gputx_default_options()
+        for k, v in opt_overrides.items():
+            setattr(opts, k, v)
+        self.options = opts
+        self.h = gputx_create(device, opts)
+        self.table_id: Dict[str, int] = {}
+        self.cols: Dict[str, list] = {}
+        for i, name in enumerate(tables):
+            self.table_id[name] = i
+        descs = []
+        for name, t in tables.items():
+            d = TableDesc()
+            d.table_id = self.table_id[name]
+            d.n_cols = len(t.cols)
+            d.n_rows = t.n_rows
+            d.capacity = t.capacity
+            d.append_only = 1 if t.append else 0
+            d.root_table_id = self.table_id[t.root] if (t.root and t.root_div > 0) else -1
+            d.root_div = t.root_div if t.root_div > 0 else 1
+            dev_cols = []
+            for c, (col, dt) in enumerate(zip(t.cols, t.dtypes)):
+                dc = torch.from_numpy(np.ascontiguousarray(col)).to(self.device)
+                dev_cols.append(dc)
+                d.col_dtype[c] = I64 if dt == "i64" else I32
+                d.col_ptr[c] = dc.data_ptr()
+            self.cols[name] = dev_cols
+            descs.append(d)
+        gputx_load_tables(self.h, descs)
+        tds = []
+        for ty in types:
+            td = TypeDesc()
+            td.type_id = ty.type_id
+            td.proc = PROC[ty.proc]
+            td.n_params = ty.n_params
+            td.n_results = ty.n_results
+            for r in range(MAX_ROLES):
+                td.table_ids[r] = self.table_id[ty.tables[r]] if r < len(ty.tables) else -1
+            td.root_key = 1 if ty.root_key else 0
+            td.single_partition = 1 if getattr(ty, "single_partition", True) else 0
+            tds.append(td)
+        gputx_register_types(self.h, tds)
+        self._ws = None
+        self._ws_n = -1
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.options, k, v)
+        gputx_set_options(self.h, self.options)
+        self._ws_n = -1
+
+    def workspace(self, n: int) -> torch.Tensor:
+        if self._ws is None or self._ws_n < n:
+            nbytes = gputx_workspace_size(self.h, n)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self._ws_n = n
+        return self._ws
+
+    def bulk_to_device(self, bulk) -> dict:
+        return dict(type=torch.from_numpy(np.ascontiguousarray(bulk.type)).to(self.device),
+                    params=torch.from_numpy(np.ascontiguousarray(bulk.params)).to(self.device),
+                    ts=torch.from_numpy(np.ascontiguousarray(bulk.ts)).to(self.device))
+
+    @staticmethod
+    def bulk_desc(dev: dict, ts_sorted: bool) -> BulkDesc:
+        b = BulkDesc()
+        b.n = dev["type"].shape[0]
+        b.type = dev["type"].data_ptr()
+        b.params = dev["params"].data_ptr()
+        b.n_params = dev["params"].shape[0]
+        b.ts = dev["ts"].data_ptr()
+        b.ts_sorted = 1 if ts_sorted else 0
+        return b
+
+    def execute(self, dev: dict, strategy: int, width: int, ts_sorted: bool = False,
+                status: Optional[torch.Tensor] = None, results: Optional[torch.Tensor] = None,
+                stats: Optional[torch.Tensor] = None, stream=None):
+        """Launch one bulk (asynchronous).  Returns (status, results, stats) device tensors."""
+        n = dev["type"].shape[0]
+        if status is None:
+            status = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        if results is None:
+            results = torch.empty((max(n, 1), width), dtype=torch.int64, device=self.device)
+        if stats is None:
+            stats = torch.empty(STATS_BYTES, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(max(n, 1))
+        gputx_execute_bulk(self.h, self.bulk_desc(dev, ts_sorted), strategy, ws, status, results,
+                           stats, stream)
+        return status, results, stats
+
+    def row_count(self, name: str) -> int:
+        return gputx_row_count(self.h, self.table_id[name])
+
+    def table_host(self, name: str) -> list:
+        return [c.cpu().numpy() for c in self.cols[name]]
+
+    def close(self):
+        if self.h:
+            gputx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

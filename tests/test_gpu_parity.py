@@ -1,0 +1,181 @@
+"""Bit-exact parity of the HIP engine with the serial oracle (GPU).
+
+Every case runs the same seeded bulk through ``gputx_execute_bulk`` and
+through the oracle and compares final tables (appended rows included),
+per-transaction status and results element by element, plus the Appendix D
+features against the Python references.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import reference as ref
+from paper_1103_3105_amd import workloads as wl
+from tests import util
+
+pytestmark = pytest.mark.gpu
+
+STRATS = ["TPL", "PART", "KSET", "AUTO"]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_both(tabs, types, bulk, width, strategy, ts_sorted=False, **opts):
+    import torch
+    from paper_1103_3105_amd import gputx
+    eng = gputx.Engine(tabs, types, **opts)
+    try:
+        dev = eng.bulk_to_device(bulk)
+        st, res, stats = eng.execute(dev, gputx.STRATEGY[strategy], width, ts_sorted=ts_sorted)
+        torch.cuda.synchronize()
+        s = gputx.stats_from(stats)
+        g_tabs = util.copy_tables(tabs)
+        for name, t in g_tabs.items():
+            host = eng.table_host(name)
+            for c in range(len(t.cols)):
+                t.cols[c][:] = host[c]
+            if t.append:
+                t.n_rows = eng.row_count(name)
+        g_st = st.cpu().numpy()[:bulk.n]
+        g_res = res.cpu().numpy()[:bulk.n]
+    finally:
+        eng.close()
+    o_tabs = util.copy_tables(tabs)
+    rc, o_st, o_res = oracle.run_serial(o_tabs, types, bulk.type, bulk.params, bulk.ts, width)
+    return s, (g_tabs, g_st, g_res), (rc, o_tabs, o_st, o_res)
+
+
+def assert_parity(s, g, o, bulk):
+    g_tabs, g_st, g_res = g
+    rc, o_tabs, o_st, o_res = o
+    assert rc == 0 and s.error == 0, (rc, s.as_dict())
+    ok, msg = util.tables_equal(o_tabs, g_tabs)
+    assert ok, msg
+    bad = np.flatnonzero(o_st != g_st)
+    assert bad.size == 0, f"status differs at {bad[:8].tolist()}"
+    bad = np.flatnonzero((o_res != g_res).any(axis=1))
+    assert bad.size == 0, f"results differ at {bad[:8].tolist()}: {o_res[bad[:2]]} vs {g_res[bad[:2]]}"
+    assert s.committed == int((o_st == 0).sum()) and s.aborted == int((o_st == 1).sum())
+    assert s.invalid == int((o_st == 2).sum())
+
+
+def check_features(s, tabs, types, bulk, part_size=1):
+    per = ref.bulk_ops(types, bulk.type, bulk.params, bulk.ts, util.sizes_of(tabs),
+                       util.roots_of(tabs))
+    txn_ops = [o for _, _, o in per]
+    w0, d, c = ref.features(txn_ops, util.roots_of(tabs), part_size)
+    assert (s.w0, s.depth, s.cross) == (w0, d, c)
+    assert s.n_ops == sum(len(o) for o in txn_ops)
+    if s.chosen == 3:  # K-SET ran: one wave per k-set
+        depth = ref.depth_scan(txn_ops)
+        live = np.array([len(o) > 0 for o in txn_ops], dtype=bool)
+        assert s.waves == (int(depth[live].max()) + 1 if live.any() else 0)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("root_key", [False, True])
+def test_config1_tiny_bank(strategy, root_key):
+    w = wl.config1(root_key=root_key)
+    _say("config1", strategy, root_key)
+    s, g, o = run_both(w.tables, w.types, w.bulks[0], 3, strategy, ts_sorted=True)
+    assert_parity(s, g, o, w.bulks[0])
+    check_features(s, w.tables, w.types, w.bulks[0])
+    if strategy == "KSET":
+        assert s.waves == 4096
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("order", ["sorted", "shuffled", "gapped"])
+def test_bank_multi_tile(strategy, order):
+    tabs, types, bulk = util.small_bank(21, 20_000, n_branch=8, tpb=10, apt=300, theta=0.8)
+    if order != "sorted":
+        bulk = wl.shuffled(bulk, np.random.default_rng(5), gapped=order == "gapped")
+    _say("bank", strategy, order)
+    s, g, o = run_both(tabs, types, bulk, 3, strategy, ts_sorted=order == "sorted")
+    assert_parity(s, g, o, bulk)
+    check_features(s, tabs, types, bulk)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_order_entry(strategy):
+    tabs, types, bulk = util.small_order(22, 20_000, n_wh=4, d_per_w=10, c_per_d=30, items_per_w=500)
+    _say("order", strategy)
+    s, g, o = run_both(tabs, types, bulk, 16, strategy)
+    assert_parity(s, g, o, bulk)
+    check_features(s, tabs, types, bulk)
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_subscriber_with_aborts(strategy):
+    tabs, types, bulk = util.small_sub(23, 20_000, n_sub=2000, theta=0.8)
+    _say("subscriber", strategy)
+    s, g, o = run_both(tabs, types, bulk, 14, strategy, part_size=16)
+    assert_parity(s, g, o, bulk)
+    assert s.aborted > 0
+    check_features(s, tabs, types, bulk, part_size=16)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 4097])
+def test_small_and_empty_bulks(n):
+    tabs, types, bulk = util.small_bank(24, max(n, 1), n_branch=2, tpb=2, apt=5)
+    if n == 0:
+        bulk = wl.Bulk(bulk.type[:0], bulk.params[:, :0], bulk.ts[:0])
+    _say("small", n)
+    for strategy in STRATS:
+        s, g, o = run_both(tabs, types, bulk, 3, strategy)
+        assert_parity(s, g, o, bulk)
+
+
+def test_invalid_transactions():
+    tabs, types, bulk = util.small_bank(25, 5000, n_branch=4, tpb=4, apt=10)
+    bulk.params[0, ::7] = 10**9
+    bulk.type[::11] = 9
+    bulk.params[2, ::13] = -5
+    for strategy in STRATS:
+        s, g, o = run_both(tabs, types, bulk, 3, strategy)
+        assert_parity(s, g, o, bulk)
+        assert s.invalid > 0
+
+
+def test_duplicate_timestamp_is_bulk_error():
+    from paper_1103_3105_amd import gputx
+    tabs, types, bulk = util.small_bank(26, 3000)
+    bulk.ts[100] = bulk.ts[2000]
+    for ts_sorted in (False,):
+        s, g, o = run_both(tabs, types, bulk, 3, "AUTO", ts_sorted=ts_sorted)
+        assert s.error == gputx.E_DUP_TS and o[0] == oracle.E_DUP_TS
+        ok, msg = util.tables_equal(tabs, g[0])
+        assert ok, msg
+    bulk2 = util.small_bank(27, 3000)[2]
+    bulk2.ts[10] = bulk2.ts[11]   # adjacent duplicate in ascending input
+    s, g, o = run_both(tabs, types, bulk2, 3, "KSET", ts_sorted=True)
+    assert s.error == gputx.E_DUP_TS
+    ok, _ = util.tables_equal(tabs, g[0])
+    assert ok
+
+
+def test_unsorted_flagged_sorted_is_error():
+    from paper_1103_3105_amd import gputx
+    tabs, types, bulk = util.small_bank(28, 3000)
+    bulk = wl.shuffled(bulk, np.random.default_rng(1))
+    s, g, o = run_both(tabs, types, bulk, 3, "TPL", ts_sorted=True)
+    assert s.error == gputx.E_UNSORTED
+    ok, _ = util.tables_equal(tabs, g[0])
+    assert ok
+
+
+def test_append_capacity_error():
+    from paper_1103_3105_amd import gputx
+    tabs, types, bulk = util.small_bank(29, 3000)
+    tabs["history"] = wl.Table("history", ["i64"] * 5, [np.zeros(100, np.int64) for _ in range(5)],
+                               0, 100, append=True)
+    s, g, o = run_both(tabs, types, bulk, 3, "PART")
+    assert s.error == gputx.E_CAPACITY and o[0] == oracle.E_CAPACITY
+    ok, _ = util.tables_equal(tabs, g[0])
+    assert ok
