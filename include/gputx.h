@@ -231,6 +231,23 @@ int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* 
  * synchronises the stream. */
 int gputx_row_count(gputx_handle h, int32_t table_id, int64_t* out, gputx_stream_t stream);
 
+/* Phase timing (Figure 5 / Figure 12 style breakdowns).  When enabled, every
+ * gputx_execute_bulk records one HIP event on its stream at each phase
+ * boundary (no synchronisation); up to 256 bulks are kept, counted from the
+ * last enable.  Phases, in order: order (timestamp check/sort), prepare
+ * (validation + scans), emit (basic operations), op_sort, rank, features
+ * (+ Algorithm 1), part_sort, part, tpl, kset, finalize.  Phases that do not
+ * run for a bulk take ~0 ms. */
+int gputx_phase_timing(gputx_handle h, int enable);
+
+/* Sum over the recorded bulks of each phase's duration in milliseconds:
+ * ms[i] for phase i < cap; *n_bulks receives the number of bulks summed.
+ * Synchronises with the last recorded event.  Returns the number of phases. */
+int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n_bulks);
+
+/* Name of phase i (static storage), or NULL past the last phase. */
+const char* gputx_phase_name(int i);
+
 /* Message of the last error on this context (static storage, never NULL). */
 const char* gputx_last_error(gputx_handle h);
 

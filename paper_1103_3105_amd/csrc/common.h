@@ -31,8 +31,11 @@ struct GtxState {
     uint32_t bar_count;   // grid barrier arrivals
     uint32_t bar_gen;     // grid barrier generation
     int32_t kset_fill[3][GPUTX_MAX_TYPES];  // K-SET frontier fill per type (rotating)
-    int32_t narrow_owner; // K-SET narrow-mode flag
     int32_t dup_adj;      // two adjacent input timestamps are equal
+    uint32_t narrow_gen;  // K-SET: bumped when workgroup 0 leaves narrow mode
+    int32_t narrow_done;  // K-SET: narrow mode ran the last wave
+    int64_t narrow_k;     // K-SET: next wave after narrow mode
+    int64_t narrow_prog;  // K-SET: waves finished in narrow mode (watchdog progress)
     int32_t pad[2];
 };
 

@@ -15,6 +15,18 @@ struct RankAgg {
     int32_t B;     // min over writes and group starts of position (m: none)
 };
 
+// Everything later stages need about one basic operation, in op order
+// (transaction-major), written with one 32-byte store by the ranking scan.
+struct __attribute__((aligned(32))) OpInfo {
+    int32_t grp;   // lock group (distinct item) of the op
+    int32_t tgt;   // completed ops of the group the op waits for (TPL)
+    int32_t slo;   // successor range in sorted order (K-SET)
+    int32_t shi;
+    int32_t rank;  // the paper's rank (Section 4.2 step 3)
+    int32_t in;    // in-edges the op contributes to its transaction (K-SET)
+    int32_t pad0, pad1;
+};
+
 // Device workspace of one bulk (carved from the caller's workspace).
 struct Ws {
     GtxState* st;
@@ -27,10 +39,7 @@ struct Ws {
     int32_t* op_txn;     // [mcap] serial position of each operation
     uint32_t* pk[2];     // [mcap] operation sort: item key
     uint32_t* pv[2];     // [mcap] operation sort: op index << 1 | write
-    int32_t* op_grp;     // [mcap] lock group (distinct item) of the op
-    int32_t* op_tgt;     // [mcap] completed ops of the group the op waits for
-    int32_t* op_slo;     // [mcap] successor range in sorted order
-    int32_t* op_shi;
+    OpInfo* op_info;     // [mcap]
     int32_t* srt_txn;    // [mcap] serial position of each sorted op
     int32_t* grp_cnt;    // [mcap] per-group completion counters
     uint32_t* qk[2];     // [n] PART sort: partition id
@@ -40,6 +49,7 @@ struct Ws {
     uint32_t* sort_status;
     uint32_t* sort_ctrl; // [16]
     int32_t* scan_tmp;   // [(1 + GTX_MAX_APPEND)][scan blocks]
+    int32_t* tcnt_tmp;   // [kPrepBlocks][GPUTX_MAX_TYPES] per-block type counts
     RankAgg* rank_tmp;   // [2][rank tiles]
 };
 
@@ -71,15 +81,26 @@ struct BulkArgs {
     Ws ws;
 };
 
+constexpr int kPrepBlocks = 1024;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = GTX_BLOCK * kScanItems;
 constexpr int kRankItems = 8;
 constexpr int kRankTile = GTX_BLOCK * kRankItems;
 
+// Phase boundaries of one bulk; mark() records a timing event when enabled.
+enum Phase { PH_START, PH_ORDER, PH_PREPARE, PH_EMIT, PH_OPSORT, PH_RANK, PH_FEATURES,
+             PH_PARTSORT, PH_PART, PH_TPL, PH_KSET, PH_FINAL, PH_COUNT };
+struct PhaseMarks {
+    hipEvent_t* ev = nullptr;  // PH_COUNT events of this bulk, or null
+    void mark(int p, hipStream_t s) const {
+        if (ev) (void)hipEventRecord(ev[p], s);
+    }
+};
+
 // bulk generation (kernels_front.hip)
-void launch_front(const BulkArgs& a, hipStream_t s);
+void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 // execution (kernels_exec.hip)
-void launch_exec(const BulkArgs& a, hipStream_t s);
+void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 // zero-transaction bulk: reset state and publish statistics
 void launch_empty(const BulkArgs& a, hipStream_t s);
 // workgroups of the persistent executors that fit on one compute unit

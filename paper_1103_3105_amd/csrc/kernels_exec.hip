@@ -27,26 +27,78 @@ __device__ __forceinline__ int64_t in_index(const BulkArgs& a, int64_t p) {
     return a.ws.st->unsorted ? (int64_t)a.ws.tsv[0][p] : p;
 }
 
-// Run the transaction at serial position p (type t >= 0); returns its status.
-__device__ int32_t run_at(const BulkArgs& a, int64_t p, int32_t t) {
-    const DevType& T = a.types[t];
-    const int64_t i = in_index(a, p);
+// One transaction's signature, loaded and ready to run.
+struct TxnIn {
+    int64_t i;     // input index (status / results slot)
+    int64_t ts;
+    int64_t app0;  // rows its appends occupy
+    int64_t app1;
+    int32_t t;     // registered type
+    int32_t np;    // parameters loaded
     int64_t prm[GTX_MAX_PARAMS];
-    load_params(a.params, a.n, min(a.n_params, T.n_params), i, prm);
-    int64_t app0 = 0, app1 = 0;
-    if (T.app_idx[0] >= 0)
-        app0 = a.rowcount[T.app_idx[0]] + a.ws.cnt[(int64_t)(1 + T.app_idx[0]) * a.n + p];
-    if (T.app_idx[1] >= 0)
-        app1 = a.rowcount[T.app_idx[1]] + a.ws.cnt[(int64_t)(1 + T.app_idx[1]) * a.n + p];
+};
+
+__device__ __forceinline__ void load_txn(const BulkArgs& a, int64_t p, int32_t t, TxnIn& x) {
+    const DevType& T = a.types[t];
+    x.t = t;
+    x.i = in_index(a, p);
+    x.np = min(a.n_params, T.n_params);
+    load_params(a.params, a.n, x.np, x.i, x.prm);
+    x.ts = a.ts[x.i];
+    x.app0 = T.app_idx[0] >= 0 ? a.rowcount[T.app_idx[0]] + a.ws.cnt[(int64_t)(1 + T.app_idx[0]) * a.n + p] : 0;
+    x.app1 = T.app_idx[1] >= 0 ? a.rowcount[T.app_idx[1]] + a.ws.cnt[(int64_t)(1 + T.app_idx[1]) * a.n + p] : 0;
+}
+
+__device__ __forceinline__ int64_t rl64(int64_t v, int k) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), k);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Lane k's signature, broadcast to the whole wave (uniform values).
+__device__ __forceinline__ void bcast_txn(const TxnIn& x, int k, TxnIn& y) {
+    y.t = __builtin_amdgcn_readlane(x.t, k);
+    y.np = __builtin_amdgcn_readlane(x.np, k);
+    y.i = rl64(x.i, k);
+    y.ts = rl64(x.ts, k);
+    y.app0 = rl64(x.app0, k);
+    y.app1 = rl64(x.app1, k);
+#pragma unroll
+    for (int q = 0; q < GTX_MAX_PARAMS; ++q) y.prm[q] = q < y.np ? rl64(x.prm[q], k) : 0;
+}
+
+__device__ __forceinline__ int32_t exec_txn(const BulkArgs& a, const TxnIn& x) {
     int64_t res[GTX_MAX_RESULTS];
-    const int32_t s = txn_exec(T, prm, a.ts[i], app0, app1, res);
-    a.status[i] = s;
-    int64_t* out = a.results + i * a.width;
+    const int32_t s = txn_exec(a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+    a.status[x.i] = s;
+    int64_t* out = a.results + x.i * a.width;
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r)
         if (r < a.width) out[r] = res[r];
     for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
     return s;
+}
+
+// exec_txn for a chunk whose transactions all run procedure P: the type
+// descriptor is read once per chunk by the caller.
+template <int P>
+__device__ __forceinline__ int32_t exec_txn_p(const BulkArgs& a, const DevType& T, const TxnIn& x) {
+    int64_t res[GTX_MAX_RESULTS];
+    const int32_t s = txn_exec_p<P>(T, x.prm, x.ts, x.app0, x.app1, res);
+    a.status[x.i] = s;
+    int64_t* out = a.results + x.i * a.width;
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+        if (r < a.width) out[r] = res[r];
+    for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
+    return s;
+}
+
+// Run the transaction at serial position p (type t >= 0); returns its status.
+__device__ int32_t run_at(const BulkArgs& a, int64_t p, int32_t t) {
+    TxnIn x;
+    load_txn(a, p, t, x);
+    return exec_txn(a, x);
 }
 
 __device__ __forceinline__ void count_status(GtxState* st, bool ran, int32_t s) {
@@ -94,11 +146,49 @@ __device__ bool grid_barrier(GtxState* st, uint64_t spin_ticks) {
 // ---------------------------------------------------------------------------
 // K-SET
 
-__device__ __forceinline__ void kset_push(const BulkArgs& a, int next, const int* reg_off, int32_t q) {
-    GtxState* st = a.ws.st;
+__device__ __forceinline__ void kset_push(const BulkArgs& a, int32_t* fill, int32_t* front,
+                                          const int* reg_off, int32_t q) {
     const int32_t t = a.ws.tty[q];
-    const int slot = atomicAdd(&st->kset_fill[next % 3][t], 1);
-    a.ws.front[next & 1][reg_off[t] + slot] = q;
+    const int slot = atomicAdd(&fill[t], 1);
+    front[reg_off[t] + slot] = q;
+}
+
+// Run chunk c of the frontier (type regions cut in 64-transaction chunks) and
+// release its successors into the next frontier.
+__device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* cpre, const int* cnt,
+                                           const int* reg_off, const int32_t* F, int32_t* fill_next,
+                                           int32_t* F_next) {
+    int t = 0;
+    while (cpre[t + 1] <= c) ++t;  // wave-uniform: this chunk's type
+    const int idx = (c - cpre[t]) * 64 + lane_id();
+    const bool live = idx < cnt[t];
+    int32_t s = 0;
+    int32_t q = 0;
+    if (live) {
+        q = F[reg_off[t] + idx];
+        s = run_at(a, q, t);
+    }
+    count_status(a.ws.st, live, s);
+    if (live) {
+        const int64_t o1 = op_end(a, q);
+        for (int64_t o = op_begin(a, q); o < o1; ++o) {
+            const OpInfo inf = a.ws.op_info[o];
+            for (int32_t j = inf.slo; j < inf.shi; ++j) {
+                const int32_t q2 = a.ws.srt_txn[j];
+                if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int chunk_prefix(const int* cnt, int* cpre) {
+    int c = 0;
+    for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
+        cpre[t] = c;
+        c += (cnt[t] + 63) / 64;
+    }
+    cpre[GPUTX_MAX_TYPES] = c;
+    return c;
 }
 
 __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
@@ -106,7 +196,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
     if (failed(st) || st->chosen != GPUTX_KSET) return;
     __shared__ int reg_off[GPUTX_MAX_TYPES];
     __shared__ int wcnt[GPUTX_MAX_TYPES];
+    __shared__ int lfill[GPUTX_MAX_TYPES];
     __shared__ int cpre[GPUTX_MAX_TYPES + 1];
+    __shared__ int64_t k_s;
+    __shared__ int done_s, total_s;
     if (threadIdx.x == 0) {
         int o = 0;
         for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
@@ -118,53 +211,96 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
     // wave 0: every valid transaction without predecessors
     for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * GTX_BLOCK) {
-        if (a.ws.tty[p] >= 0 && a.ws.indeg[p] == 0) kset_push(a, 0, reg_off, (int32_t)p);
+        if (a.ws.tty[p] >= 0 && a.ws.indeg[p] == 0) kset_push(a, st->kset_fill[0], a.ws.front[0], reg_off, (int32_t)p);
     }
     const int gwaves = gridDim.x * GTX_WAVES;
     const int gw = blockIdx.x * GTX_WAVES + wave_id();
     int64_t k = 0;
-    while (grid_barrier(st, a.spin_ticks)) {
-        const int cur = (int)(k % 3);
+    uint32_t nphase = 0;  // narrow phases completed
+    bool finished = false;
+    while (!finished && grid_barrier(st, a.spin_ticks)) {
         if (threadIdx.x < GPUTX_MAX_TYPES) {
-            wcnt[threadIdx.x] = ld_relaxed(&st->kset_fill[cur][threadIdx.x]);
+            wcnt[threadIdx.x] = ld_relaxed(&st->kset_fill[k % 3][threadIdx.x]);
             if (blockIdx.x == 0) st_relaxed(&st->kset_fill[(k + 2) % 3][threadIdx.x], 0);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            int c = 0;
-            for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
-                cpre[t] = c;
-                c += (wcnt[t] + 63) / 64;
-            }
-            cpre[GPUTX_MAX_TYPES] = c;
+            int tot = 0;
+            for (int t = 0; t < GPUTX_MAX_TYPES; ++t) tot += wcnt[t];
+            total_s = tot;
+            chunk_prefix(wcnt, cpre);
         }
         __syncthreads();
-        const int nchunks = cpre[GPUTX_MAX_TYPES];
-        if (nchunks == 0) break;  // every transaction has run
-        const int32_t* F = a.ws.front[k & 1];
-        for (int c = gw; c < nchunks; c += gwaves) {
-            int t = 0;
-            while (cpre[t + 1] <= c) ++t;  // wave-uniform: this chunk's type
-            const int idx = (c - cpre[t]) * 64 + lane_id();
-            const bool live = idx < wcnt[t];
-            int32_t s = 0;
-            int32_t q = 0;
-            if (live) {
-                q = F[reg_off[t] + idx];
-                s = run_at(a, q, t);
-            }
-            count_status(st, live, s);
-            if (live) {
-                const int64_t o1 = op_end(a, q);
-                for (int64_t o = op_begin(a, q); o < o1; ++o) {
-                    const int32_t hi = a.ws.op_shi[o];
-                    for (int32_t j = a.ws.op_slo[o]; j < hi; ++j) {
-                        const int32_t q2 = a.ws.srt_txn[j];
-                        if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, (int)(k + 1), reg_off, q2);
+        if (total_s == 0) break;  // every transaction has run
+        if (total_s <= a.kset_narrow) {
+            // narrow waves: workgroup 0 runs them alone with workgroup barriers
+            if (blockIdx.x == 0) {
+                int64_t kk = k;
+                while (true) {
+                    if (threadIdx.x < GPUTX_MAX_TYPES) lfill[threadIdx.x] = 0;
+                    __syncthreads();
+                    const int32_t* F = a.ws.front[kk & 1];
+                    int32_t* Fn = a.ws.front[(kk + 1) & 1];
+                    for (int c = wave_id(); c < cpre[GPUTX_MAX_TYPES]; c += GTX_WAVES)
+                        kset_chunk(a, c, cpre, wcnt, reg_off, F, lfill, Fn);
+                    __syncthreads();
+                    ++kk;
+                    if (threadIdx.x == 0) {
+                        int tot = 0;
+                        for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
+                            wcnt[t] = lfill[t];
+                            tot += lfill[t];
+                        }
+                        total_s = tot;
+                        chunk_prefix(wcnt, cpre);
+                        if ((kk & 63) == 0) st_relaxed(&st->narrow_prog, kk);
                     }
+                    __syncthreads();
+                    if (total_s == 0 || total_s > a.kset_narrow || failed(st)) break;
                 }
+                if (threadIdx.x < GPUTX_MAX_TYPES) {
+                    st_relaxed(&st->kset_fill[kk % 3][threadIdx.x], wcnt[threadIdx.x]);
+                    st_relaxed(&st->kset_fill[(kk + 1) % 3][threadIdx.x], 0);
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    st->narrow_k = kk;
+                    st->narrow_done = total_s == 0;
+                    fence_release();
+                    __hip_atomic_fetch_add(&st->narrow_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    k_s = kk;
+                    done_s = total_s == 0;
+                }
+                __syncthreads();
+            } else {
+                if (threadIdx.x == 0) {
+                    // wait for workgroup 0; the watchdog restarts whenever it makes progress
+                    // narrow phases happen at the same waves in every workgroup,
+                    // so the generation to wait for is known locally
+                    uint64_t t0 = now_ticks();
+                    int64_t prog = ld_relaxed(&st->narrow_prog);
+                    while (ld_relaxed(&st->narrow_gen) < nphase + 1) {
+                        if (failed(st)) break;
+                        const int64_t pr = ld_relaxed(&st->narrow_prog);
+                        if (pr != prog) { prog = pr; t0 = now_ticks(); }
+                        else if (now_ticks() - t0 > a.spin_ticks) { fail(st, GPUTX_E_DEADLOCK); break; }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    fence_acquire();
+                    k_s = st->narrow_k;
+                    done_s = st->narrow_done || failed(st);
+                }
+                __syncthreads();
             }
+            k = k_s;
+            finished = done_s;
+            ++nphase;
+            continue;
         }
+        const int32_t* F = a.ws.front[k & 1];
+        int32_t* Fn = a.ws.front[(k + 1) & 1];
+        for (int c = gw; c < cpre[GPUTX_MAX_TYPES]; c += gwaves)
+            kset_chunk(a, c, cpre, wcnt, reg_off, F, st->kset_fill[(k + 1) % 3], Fn);
         ++k;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) st->waves = k;
@@ -219,9 +355,11 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
         }
         bool done = t < 0;
         int64_t o0 = 0, o1 = 0;
+        TxnIn x;
         if (!done) {
             o0 = op_begin(a, p);
             o1 = op_end(a, p);
+            load_txn(a, p, t, x);  // signatures are immutable: load before waiting
         }
         uint64_t t0 = 0;
         int32_t s = 0;
@@ -230,18 +368,20 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
             bool ready = false;
             if (!done) {
                 ready = true;
-                for (int64_t o = o0; o < o1; ++o)
-                    ready = ready && ld_relaxed(&a.ws.grp_cnt[a.ws.op_grp[o]]) >= a.ws.op_tgt[o];
+                for (int64_t o = o0; o < o1; ++o) {
+                    const OpInfo inf = a.ws.op_info[o];
+                    ready = ready && ld_relaxed(&a.ws.grp_cnt[inf.grp]) >= inf.tgt;
+                }
             }
             if (__any(ready)) {
                 fence_acquire();  // see every write released by the predecessors
                 if (ready) {
-                    s = run_at(a, p, t);
+                    s = exec_txn(a, x);
                     ran = true;
                 }
                 fence_release();  // publish this transaction's writes
                 if (ready) {
-                    for (int64_t o = o0; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_grp[o]], 1);
+                    for (int64_t o = o0; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_info[o].grp], 1);
                     done = true;
                 }
                 t0 = 0;
@@ -263,43 +403,138 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
 // ---------------------------------------------------------------------------
 // PART
 
-__global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a, int lane_stride) {
-    GtxState* st = a.ws.st;
-    if (failed(st) || st->chosen != GPUTX_PART) return;
-    const int64_t g = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x;
-    const bool mine = (g % lane_stride) == 0;
-    const int64_t q = g / lane_stride;
-    const int src = a.part_passes & 1;
-    const uint32_t* key = a.ws.qk[src];
-    const uint32_t* pos = a.ws.qv[src];
-    int32_t s = 0;
-    int64_t committed = 0, aborted = 0;
-    if (mine && q < a.n_parts) {
-        // the partition's range in the partition-sorted bulk, by binary search
-        int64_t lo = 0, hi = a.n;
-        while (lo < hi) {
-            int64_t mid = (lo + hi) >> 1;
-            if (key[mid] < (uint32_t)q) lo = mid + 1;
-            else hi = mid;
-        }
-        int64_t end = lo, hi2 = a.n;
-        while (end < hi2) {
-            int64_t mid = (end + hi2) >> 1;
-            if (key[mid] <= (uint32_t)q) end = mid + 1;
-            else hi2 = mid;
-        }
-        for (int64_t i = lo; i < end; ++i) {
-            const int32_t p = (int32_t)pos[i];
-            s = run_at(a, p, a.ws.tty[p]);
-            committed += s == GPUTX_COMMIT;
-            aborted += s == GPUTX_ABORT;
-        }
+__device__ __forceinline__ void part_range(const BulkArgs& a, const uint32_t* key, int64_t q,
+                                           int64_t* lo_out, int64_t* end_out) {
+    // the partition's range in the partition-sorted bulk, by binary search
+    int64_t lo = 0, hi = a.n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (key[mid] < (uint32_t)q) lo = mid + 1;
+        else hi = mid;
     }
+    int64_t end = lo, hi2 = a.n;
+    while (end < hi2) {
+        int64_t mid = (end + hi2) >> 1;
+        if (key[mid] <= (uint32_t)q) end = mid + 1;
+        else hi2 = mid;
+    }
+    *lo_out = lo;
+    *end_out = end;
+}
+
+__device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int64_t aborted) {
     long long c = wave_sum64(committed), ab = wave_sum64(aborted);
     if (lane_id() == 0) {
         if (c) atomicAdd((unsigned long long*)&st->committed, (unsigned long long)c);
         if (ab) atomicAdd((unsigned long long*)&st->aborted, (unsigned long long)ab);
     }
+}
+
+// One lane per partition: for many small partitions.
+__global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
+    GtxState* st = a.ws.st;
+    if (failed(st) || st->chosen != GPUTX_PART) return;
+    const int64_t q = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x;
+    const int src = a.part_passes & 1;
+    int64_t committed = 0, aborted = 0;
+    if (q < a.n_parts) {
+        int64_t lo, end;
+        part_range(a, a.ws.qk[src], q, &lo, &end);
+        for (int64_t i = lo; i < end; ++i) {
+            const int32_t p = (int32_t)a.ws.qv[src][i];
+            const int32_t s = run_at(a, p, a.ws.tty[p]);
+            committed += s == GPUTX_COMMIT;
+            aborted += s == GPUTX_ABORT;
+        }
+    }
+    add_counts(st, committed, aborted);
+}
+
+// Lane 0 runs the chunk's cnt transactions in order.  P != 0: every one runs
+// procedure P with descriptor T; P == 0: mixed types, full switch.
+template <int P>
+__device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const int64_t* lp,
+                                            int cnt, int32_t t, int32_t np, int64_t i, int64_t ts,
+                                            int64_t app0, int64_t app1, int64_t& committed,
+                                            int64_t& aborted) {
+    const int npb = P ? T.n_params : GTX_MAX_PARAMS;
+    for (int k = 0; k < cnt; ++k) {
+        TxnIn y;
+        y.t = __builtin_amdgcn_readlane(t, k);
+        y.np = __builtin_amdgcn_readlane(np, k);
+        y.i = rl64(i, k);
+        y.ts = rl64(ts, k);
+        y.app0 = rl64(app0, k);
+        y.app1 = rl64(app1, k);
+#pragma unroll
+        for (int r = 0; r < GTX_MAX_PARAMS; ++r) y.prm[r] = (r < y.np && r < npb) ? lp[r * 64 + k] : 0;
+        if (lane_id() == 0) {
+            const int32_t s = P ? exec_txn_p<P>(a, T, y) : exec_txn(a, y);
+            committed += s == GPUTX_COMMIT;
+            aborted += s == GPUTX_ABORT;
+        }
+    }
+}
+
+// One wave per partition, still one serial thread of control: the wave's 64
+// lanes load the partition's next 64 signatures (parameters staged in LDS,
+// the rest in registers) and touch the rows those transactions will use;
+// then lane 0 runs the 64 one after another, reading each signature with
+// uniform LDS reads and lane broadcasts.  For few, long partitions.
+__global__ __launch_bounds__(GTX_BLOCK) void k_part_wave(BulkArgs a) {
+    GtxState* st = a.ws.st;
+    if (failed(st) || st->chosen != GPUTX_PART) return;
+    extern __shared__ int64_t part_lds[];
+    const int64_t q = (int64_t)blockIdx.x * GTX_WAVES + wave_id();
+    if (q >= a.n_parts) return;
+    const int lane = lane_id();
+    const int src = a.part_passes & 1;
+    const int npb = min(a.n_params, GTX_MAX_PARAMS);  // parameters per signature
+    int64_t* lp = part_lds + (int64_t)wave_id() * npb * 64;
+    const uint32_t* pos = a.ws.qv[src];
+    int64_t lo, end;
+    part_range(a, a.ws.qk[src], q, &lo, &end);
+    int64_t committed = 0, aborted = 0, sink = 0;
+    for (int64_t c0 = lo; c0 < end; c0 += 64) {
+        const int64_t j = c0 + lane;
+        int32_t t = 0, np = 0;
+        int64_t i = 0, ts = 0, app0 = 0, app1 = 0;
+        if (j < end) {
+            const int32_t p = (int32_t)pos[j];
+            t = a.ws.tty[p];
+            TxnIn x;
+            load_txn(a, p, t, x);
+            for (int k = 0; k < npb; ++k) lp[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
+            sink ^= txn_touch(a.types[t], x.prm);
+            i = x.i; ts = x.ts; app0 = x.app0; app1 = x.app1; np = x.np;
+        }
+        const int cnt = (int)min<int64_t>(64, end - c0);
+        // one procedure for the whole chunk (the common case): dispatch once
+        const int t0 = __builtin_amdgcn_readfirstlane(t);
+        const bool uniform = __ballot(j < end && t != t0) == 0;
+        const int proc = uniform ? a.types[t0].proc : 0;
+        switch (proc) {
+#define GTX_PART_CASE(P)                                                                   \
+    case P:                                                                                \
+        part_serial<P>(a, a.types[t0], lp, cnt, t, np, i, ts, app0, app1, committed, aborted); \
+        break;
+            GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
+            GTX_PART_CASE(GPUTX_NEW_ORDER)
+            GTX_PART_CASE(GPUTX_PAYMENT)
+            GTX_PART_CASE(GPUTX_ORDER_STATUS)
+            GTX_PART_CASE(GPUTX_GET_SUB)
+            GTX_PART_CASE(GPUTX_GET_CF)
+            GTX_PART_CASE(GPUTX_UPD_SUB_FIELD)
+            GTX_PART_CASE(GPUTX_UPD_LOC)
+            GTX_PART_CASE(GPUTX_INS_CF)
+            GTX_PART_CASE(GPUTX_DEL_CF)
+#undef GTX_PART_CASE
+        default:
+            part_serial<0>(a, a.types[t0], lp, cnt, t, np, i, ts, app0, app1, committed, aborted);
+        }
+    }
+    if (sink == (int64_t)0x7fe1d2c3b4a59687ll) st->pad[0] = 1;  // keeps the touches live
+    add_counts(st, committed, aborted);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,10 +585,11 @@ int exec_resident_blocks_per_cu() {
     return cached;
 }
 
-void launch_exec(const BulkArgs& a, hipStream_t s) {
+void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     // PART: group transactions by partition (stable, so timestamp order is
     // kept inside each partition); only when PART was chosen
-    if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_PART) {
+    const bool part = a.strategy == GPUTX_AUTO || a.strategy == GPUTX_PART;
+    if (part) {
         SortPlan sp{};
         sp.key_bytes = 4;
         sp.keys[0] = a.ws.qk[0]; sp.keys[1] = a.ws.qk[1];
@@ -362,16 +598,27 @@ void launch_exec(const BulkArgs& a, hipStream_t s) {
         sp.cap = a.n; sp.count_dev = nullptr; sp.npass = a.part_passes;
         sp.gate = &a.ws.st->run_part; sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
         sort_pairs(sp, s);
-        const int stride = a.n_parts <= 4096 ? 64 : 1;
-        const int64_t threads = a.n_parts * stride;
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, (threads + GTX_BLOCK - 1) / GTX_BLOCK);
-        hipLaunchKernelGGL(k_part, dim3(blocks), dim3(GTX_BLOCK), 0, s, a, stride);
     }
+    pm.mark(PH_PARTSORT, s);
+    if (part) {
+        if (a.n_parts <= 8192) {  // few long partitions: one wave each
+            const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_WAVES - 1) / GTX_WAVES);
+            const size_t lds = (size_t)GTX_WAVES * 64 * std::min(a.n_params, GTX_MAX_PARAMS) * 8;
+            hipLaunchKernelGGL(k_part_wave, dim3(blocks), dim3(GTX_BLOCK), lds, s, a);
+        } else {
+            const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_BLOCK - 1) / GTX_BLOCK);
+            hipLaunchKernelGGL(k_part, dim3(blocks), dim3(GTX_BLOCK), 0, s, a);
+        }
+    }
+    pm.mark(PH_PART, s);
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_TPL || a.strategy == GPUTX_PART)
         hipLaunchKernelGGL(k_tpl, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_TPL, s);
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_KSET)
         hipLaunchKernelGGL(k_kset, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_KSET, s);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    pm.mark(PH_FINAL, s);
 }
 
 }  // namespace gtx

@@ -67,9 +67,8 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_prepare(BulkArgs a) {
     __shared__ int tcount[GPUTX_MAX_TYPES];
     if (threadIdx.x < GPUTX_MAX_TYPES) tcount[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t p = gid();
-    bool invalid = false;
-    if (p < a.n) {
+    int ninv = 0;
+    for (int64_t p = gid(); p < a.n; p += (int64_t)gridDim.x * GTX_BLOCK) {
         const int64_t i = input_index(a, p);
         const int32_t t = a.type[i];
         bool valid = false;
@@ -92,21 +91,19 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_prepare(BulkArgs a) {
         a.ws.cnt[p] = nops;
         for (int k = 0; k < a.n_app; ++k)
             a.ws.cnt[(int64_t)(1 + k) * a.n + p] = (k == ai0 ? a0 : 0) + (k == ai1 ? a1 : 0);
-        a.ws.maxrank[p] = 0;
-        a.ws.indeg[p] = 0;
         if (valid) {
             atomicAdd(&tcount[t], 1);
         } else {
-            invalid = true;
+            ++ninv;
             a.status[i] = GPUTX_INVALID;
             for (int r = 0; r < a.width; ++r) a.results[i * a.width + r] = 0;
         }
     }
-    int ninv = wave_sum(invalid ? 1 : 0);
+    ninv = wave_sum(ninv);
     if (lane_id() == 0 && ninv) atomicAdd((unsigned long long*)&st->invalid, (unsigned long long)ninv);
     __syncthreads();
-    if (threadIdx.x < GPUTX_MAX_TYPES && tcount[threadIdx.x])
-        atomicAdd(&st->type_count[threadIdx.x], tcount[threadIdx.x]);
+    // per-block type counts; the scan's single workgroup adds them up
+    if (threadIdx.x < GPUTX_MAX_TYPES) a.ws.tcnt_tmp[blockIdx.x * GPUTX_MAX_TYPES + threadIdx.x] = tcount[threadIdx.x];
 }
 
 // ---- exclusive scans of the per-position counts --------------------------
@@ -146,6 +143,12 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_scan_mid(BulkArgs a, int K, int n
             if (k == 0) st->m = running;
             else st->app_total[k - 1] = running;
         }
+    }
+    if (threadIdx.x < GPUTX_MAX_TYPES) {
+        const int nblk = (int)std::min<int64_t>(kPrepBlocks, (a.n + GTX_BLOCK - 1) / GTX_BLOCK);
+        int c = 0;
+        for (int b = 0; b < nblk; ++b) c += a.ws.tcnt_tmp[b * GPUTX_MAX_TYPES + threadIdx.x];
+        st->type_count[threadIdx.x] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -449,13 +452,16 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
             in_c = Aex > gs ? 1 : 0;
         }
         a.ws.srt_txn[i] = txn;
-        a.ws.op_grp[o] = g;
-        a.ws.op_tgt[o] = tgt;
-        a.ws.op_slo[o] = slo;
-        a.ws.op_shi[o] = shi;
+        OpInfo inf;
+        inf.grp = g;
+        inf.tgt = tgt;
+        inf.slo = slo;
+        inf.shi = shi;
+        inf.rank = rank;
+        inf.in = in_c;
+        inf.pad0 = inf.pad1 = 0;
+        a.ws.op_info[o] = inf;
         if (i == gs) a.ws.grp_cnt[g] = 0;
-        if (in_c) atomicAdd(&a.ws.indeg[txn], in_c);
-        if (rank) atomicMax(&a.ws.maxrank[txn], rank);
     }
 }
 
@@ -464,17 +470,40 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_features(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (bulk_failed(st)) return;
     __shared__ uint32_t is_last;
-    const int64_t p = gid();
-    int zero = 0, mr = 0;
-    if (p < a.n && a.ws.tty[p] >= 0) {
-        mr = a.ws.maxrank[p];
-        zero = mr == 0;
+    __shared__ int red[2][GTX_WAVES];
+    int zero = 0, dmax = 0;
+    for (int64_t p = gid(); p < a.n; p += (int64_t)gridDim.x * GTX_BLOCK) {
+        int mr = 0, in = 0;
+        if (a.ws.tty[p] >= 0) {
+            // Section 4.2 steps 4-5: a transaction's k-set rank is the maximum
+            // rank of its operations (reduced over its contiguous op range)
+            const int64_t o1 = p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : st->m;
+            for (int64_t o = a.ws.cnt[p]; o < o1; ++o) {
+                const OpInfo inf = a.ws.op_info[o];
+                mr = max(mr, inf.rank);
+                in += inf.in;
+            }
+            zero += mr == 0;
+            dmax = max(dmax, mr);
+        }
+        a.ws.maxrank[p] = mr;
+        a.ws.indeg[p] = in;
     }
     int z = wave_sum(zero);
-    int d = wave_max(mr);
+    int d = wave_max(dmax);
     if (lane_id() == 0) {
-        if (z) atomicAdd((unsigned long long*)&st->w0, (unsigned long long)z);
-        if (d) atomicMax((unsigned long long*)&st->depth, (unsigned long long)d);
+        red[0][wave_id()] = z;
+        red[1][wave_id()] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int zz = 0, dd = 0;
+        for (int w = 0; w < GTX_WAVES; ++w) {
+            zz += red[0][w];
+            dd = max(dd, red[1][w]);
+        }
+        if (zz) atomicAdd((unsigned long long*)&st->w0, (unsigned long long)zz);
+        if (dd) atomicMax((unsigned long long*)&st->depth, (unsigned long long)dd);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -501,7 +530,8 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_features(BulkArgs a) {
 // ---- host side ------------------------------------------------------------
 static unsigned blocks_for(int64_t n, int64_t per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
-void launch_front(const BulkArgs& a, hipStream_t s) {
+void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
+    pm.mark(PH_START, s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(GTX_BLOCK), 0, s, a.ws.st);
     hipLaunchKernelGGL(k_order_check, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
     if (!a.ts_sorted) {
@@ -515,13 +545,16 @@ void launch_front(const BulkArgs& a, hipStream_t s) {
         sort_pairs(sp, s);  // 8 passes: result back in buffer 0
     }
     hipLaunchKernelGGL(k_ts_check, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_prepare, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_ORDER, s);
+    hipLaunchKernelGGL(k_prepare, dim3(std::min<unsigned>(kPrepBlocks, blocks_for(a.n, GTX_BLOCK))), dim3(GTX_BLOCK), 0, s, a);
     const int K = 1 + a.n_app;
     const int nb = (int)blocks_for(a.n, kScanTile);
     hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
     hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, K, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
+    pm.mark(PH_PREPARE, s);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_EMIT, s);
     {
         SortPlan sp{};
         sp.key_bytes = 4;
@@ -532,11 +565,14 @@ void launch_front(const BulkArgs& a, hipStream_t s) {
         sp.gate = nullptr; sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
         sort_pairs(sp, s);
     }
+    pm.mark(PH_OPSORT, s);
     const int nbr = (int)blocks_for(a.mcap, kRankTile);
     hipLaunchKernelGGL(k_rank_up, dim3(nbr), dim3(GTX_BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_rank_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, nbr);
     hipLaunchKernelGGL(k_rank_down, dim3(nbr), dim3(GTX_BLOCK), 0, s, a, nbr);
-    hipLaunchKernelGGL(k_features, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_RANK, s);
+    hipLaunchKernelGGL(k_features, dim3(std::min<unsigned>(1024, blocks_for(a.n, GTX_BLOCK))), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_FEATURES, s);
 }
 
 }  // namespace gtx

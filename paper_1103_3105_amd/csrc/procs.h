@@ -160,22 +160,76 @@ __device__ __forceinline__ void load_params(const int64_t* __restrict__ params, 
     for (int k = 0; k < GTX_MAX_PARAMS; ++k) p[k] = (k < np) ? params[(int64_t)k * n + i] : 0;
 }
 
+
+// Table columns live in global memory: tag the pointers so that accesses
+// compile to global_* rather than flat_* instructions.
+#define GTX_GLOBAL __attribute__((address_space(1)))
 template <class V>
-__device__ __forceinline__ V* colp(const DevType& T, int role, int c) {
-    return reinterpret_cast<V*>(T.col[role][c]);
+__device__ __forceinline__ GTX_GLOBAL V* colp(const DevType& T, int role, int c) {
+    return (GTX_GLOBAL V*)(T.col[role][c]);
 }
 
-// Run one valid transaction: the switch of Section 3.2.  app0/app1 are the
-// rows its appends occupy.  Returns its status, fills res[0..15].
-__device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t ts, int64_t app0,
-                                   int64_t app1, int64_t* res) {
+// Read one value of every row the transaction will touch, to pull the rows
+// towards the compute unit before the transaction runs; returns an XOR of
+// the values so the loads stay live.  Values are not used for execution.
+__device__ inline int64_t txn_touch(const DevType& T, const int64_t* p) {
+    int64_t s = 0;
+    switch (T.proc) {
+    case GPUTX_DEBIT_CREDIT:
+        s ^= colp<const int64_t>(T, 0, 0)[p[0]];
+        s ^= colp<const int64_t>(T, 1, 0)[p[1]];
+        s ^= colp<const int64_t>(T, 2, 0)[p[2]];
+        break;
+    case GPUTX_NEW_ORDER: {
+        GTX_GLOBAL const int32_t* S = colp<const int32_t>(T, 3, 0);
+#pragma unroll
+        for (int j = 0; j < 15; ++j)
+            if (j < p[3]) s ^= S[p[0] * T.dims[3] + p[4 + j]];
+        break;
+    }
+    case GPUTX_PAYMENT: {
+        int64_t drow = p[0] * T.dims[1] + p[1];
+        s ^= colp<const int64_t>(T, 0, 0)[p[0]];
+        s ^= colp<const int64_t>(T, 1, 0)[drow];
+        s ^= colp<const int64_t>(T, 2, 0)[drow * T.dims[2] + p[2]];
+        break;
+    }
+    case GPUTX_ORDER_STATUS:
+        s ^= colp<const int64_t>(T, 2, 0)[(p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2]];
+        break;
+    case GPUTX_GET_SUB:
+#pragma unroll
+        for (int f = 0; f < 14; ++f) s ^= colp<const int32_t>(T, 0, 1 + f)[p[0]];
+        break;
+    case GPUTX_UPD_SUB_FIELD:
+    case GPUTX_UPD_LOC:
+        s ^= colp<const int32_t>(T, 0, 1 + (int)p[1] + (T.proc == GPUTX_UPD_LOC ? 4 : 0))[p[0]];
+        break;
+    case GPUTX_GET_CF:
+    case GPUTX_INS_CF:
+    case GPUTX_DEL_CF: {
+        int64_t slot = p[0] * 12 + p[1];
+        s ^= colp<const int32_t>(T, 1, 0)[slot];
+        s ^= colp<const int64_t>(T, 1, 2)[slot];
+        break;
+    }
+    }
+    return s;
+}
+
+// Run one valid transaction of procedure P (one case of the switch of
+// Section 3.2).  app0/app1 are the rows its appends occupy.  Returns its
+// status, fills res[0..15].
+template <int P>
+__device__ __forceinline__ int32_t txn_exec_p(const DevType& T, const int64_t* p, int64_t ts,
+                                              int64_t app0, int64_t app1, int64_t* res) {
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
-    switch (T.proc) {
+    switch (P) {
     case GPUTX_DEBIT_CREDIT: {
-        int64_t* A = colp<int64_t>(T, 0, 0);
-        int64_t* Tl = colp<int64_t>(T, 1, 0);
-        int64_t* B = colp<int64_t>(T, 2, 0);
+        GTX_GLOBAL int64_t* A = colp<int64_t>(T, 0, 0);
+        GTX_GLOBAL int64_t* Tl = colp<int64_t>(T, 1, 0);
+        GTX_GLOBAL int64_t* B = colp<int64_t>(T, 2, 0);
         int64_t a = wrap_add(A[p[0]], p[3]);
         int64_t t = wrap_add(Tl[p[1]], p[3]);
         int64_t b = wrap_add(B[p[2]], p[3]);
@@ -193,7 +247,7 @@ __device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t t
         return GPUTX_COMMIT;
     }
     case GPUTX_NEW_ORDER: {
-        int32_t* S = colp<int32_t>(T, 3, 0);
+        GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0);
         int64_t k = p[3];
         res[0] = k;
 #pragma unroll
@@ -223,9 +277,9 @@ __device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t t
     case GPUTX_PAYMENT: {
         int64_t drow = p[0] * T.dims[1] + p[1];
         int64_t crow = drow * T.dims[2] + p[2];
-        int64_t* Wb = colp<int64_t>(T, 0, 0);
-        int64_t* Db = colp<int64_t>(T, 1, 0);
-        int64_t* Cb = colp<int64_t>(T, 2, 0);
+        GTX_GLOBAL int64_t* Wb = colp<int64_t>(T, 0, 0);
+        GTX_GLOBAL int64_t* Db = colp<int64_t>(T, 1, 0);
+        GTX_GLOBAL int64_t* Cb = colp<int64_t>(T, 2, 0);
         int64_t w = wrap_add(Wb[p[0]], p[3]);
         int64_t d = wrap_add(Db[drow], p[3]);
         int64_t c = wrap_add(Cb[crow], p[3]);
@@ -256,15 +310,15 @@ __device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t t
     }
     case GPUTX_UPD_SUB_FIELD:
     case GPUTX_UPD_LOC: {
-        int c = 1 + (int)p[1] + (T.proc == GPUTX_UPD_LOC ? 4 : 0);
-        int32_t* F = colp<int32_t>(T, 0, c);
+        int c = 1 + (int)p[1] + (P == GPUTX_UPD_LOC ? 4 : 0);
+        GTX_GLOBAL int32_t* F = colp<int32_t>(T, 0, c);
         res[0] = F[p[0]];
         F[p[0]] = to_i32(p[2]);
         return GPUTX_COMMIT;
     }
     case GPUTX_INS_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        int32_t* occ = colp<int32_t>(T, 1, 0);
+        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0);
         int32_t o = occ[slot];
         res[0] = o;
         if (o) return GPUTX_ABORT;  // read phase decides; nothing written
@@ -275,7 +329,7 @@ __device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t t
     }
     case GPUTX_DEL_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        int32_t* occ = colp<int32_t>(T, 1, 0);
+        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0);
         if (!occ[slot]) return GPUTX_ABORT;
         res[0] = 1;
         res[1] = colp<int32_t>(T, 1, 1)[slot];
@@ -286,6 +340,25 @@ __device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t t
         return GPUTX_COMMIT;
     }
     }
+    return GPUTX_INVALID;
+}
+
+// The combined kernel's switch on the procedure (Section 3.2).
+__device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t ts, int64_t app0,
+                                   int64_t app1, int64_t* res) {
+    switch (T.proc) {
+    case GPUTX_DEBIT_CREDIT: return txn_exec_p<GPUTX_DEBIT_CREDIT>(T, p, ts, app0, app1, res);
+    case GPUTX_NEW_ORDER: return txn_exec_p<GPUTX_NEW_ORDER>(T, p, ts, app0, app1, res);
+    case GPUTX_PAYMENT: return txn_exec_p<GPUTX_PAYMENT>(T, p, ts, app0, app1, res);
+    case GPUTX_ORDER_STATUS: return txn_exec_p<GPUTX_ORDER_STATUS>(T, p, ts, app0, app1, res);
+    case GPUTX_GET_SUB: return txn_exec_p<GPUTX_GET_SUB>(T, p, ts, app0, app1, res);
+    case GPUTX_GET_CF: return txn_exec_p<GPUTX_GET_CF>(T, p, ts, app0, app1, res);
+    case GPUTX_UPD_SUB_FIELD: return txn_exec_p<GPUTX_UPD_SUB_FIELD>(T, p, ts, app0, app1, res);
+    case GPUTX_UPD_LOC: return txn_exec_p<GPUTX_UPD_LOC>(T, p, ts, app0, app1, res);
+    case GPUTX_INS_CF: return txn_exec_p<GPUTX_INS_CF>(T, p, ts, app0, app1, res);
+    case GPUTX_DEL_CF: return txn_exec_p<GPUTX_DEL_CF>(T, p, ts, app0, app1, res);
+    }
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
     return GPUTX_INVALID;
 }
 

@@ -41,6 +41,11 @@ struct gputx_ctx {
     int64_t* d_rowcount = nullptr;
     int64_t* d_capacity = nullptr;
     std::string err;
+    // phase timing ring
+    static constexpr int kRing = 256;
+    bool timing = false;
+    hipEvent_t* ev = nullptr;  // kRing * PH_COUNT
+    int ring_used = 0;
 };
 
 static thread_local std::string g_err;
@@ -126,8 +131,49 @@ extern "C" int gputx_destroy(gputx_handle h) {
     (void)hipFree(h->d_types);
     (void)hipFree(h->d_rowcount);
     (void)hipFree(h->d_capacity);
+    if (h->ev) {
+        for (int i = 0; i < gputx_ctx::kRing * PH_COUNT; ++i) (void)hipEventDestroy(h->ev[i]);
+        delete[] h->ev;
+    }
     delete h;
     return GPUTX_OK;
+}
+
+extern "C" int gputx_phase_timing(gputx_handle h, int enable) {
+    if (!h) return set_err(h, GPUTX_E_ARG, "null handle");
+    HIP_OK(h, hipSetDevice(h->device));
+    if (enable && !h->ev) {
+        h->ev = new hipEvent_t[gputx_ctx::kRing * PH_COUNT];
+        for (int i = 0; i < gputx_ctx::kRing * PH_COUNT; ++i) HIP_OK(h, hipEventCreate(&h->ev[i]));
+    }
+    h->timing = enable != 0;
+    h->ring_used = 0;
+    return GPUTX_OK;
+}
+
+static const char* kPhaseNames[PH_COUNT - 1] = {"order", "prepare", "emit", "op_sort", "rank",
+                                                "features", "part_sort", "part", "tpl", "kset",
+                                                "finalize"};
+
+extern "C" const char* gputx_phase_name(int i) {
+    return (i >= 0 && i < PH_COUNT - 1) ? kPhaseNames[i] : nullptr;
+}
+
+extern "C" int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n_bulks) {
+    if (!h || (cap > 0 && !ms)) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    HIP_OK(h, hipSetDevice(h->device));
+    for (int i = 0; i < cap; ++i) ms[i] = 0;
+    if (n_bulks) *n_bulks = h->ring_used;
+    if (!h->ev || h->ring_used == 0) return PH_COUNT - 1;
+    HIP_OK(h, hipEventSynchronize(h->ev[(h->ring_used - 1) * PH_COUNT + PH_FINAL]));
+    for (int b = 0; b < h->ring_used; ++b) {
+        for (int p = 1; p < PH_COUNT && p - 1 < cap; ++p) {
+            float t = 0;
+            HIP_OK(h, hipEventElapsedTime(&t, h->ev[b * PH_COUNT + p - 1], h->ev[b * PH_COUNT + p]));
+            ms[p - 1] += t;
+        }
+    }
+    return PH_COUNT - 1;
 }
 
 extern "C" int gputx_set_options(gputx_handle h, const gputx_options* opt) {
@@ -372,10 +418,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, void* base, Ws* ws, size_t* b
     w.op_txn = L.take<int32_t>(mcap);
     w.pk[0] = L.take<uint32_t>(mcap); w.pk[1] = L.take<uint32_t>(mcap);
     w.pv[0] = L.take<uint32_t>(mcap); w.pv[1] = L.take<uint32_t>(mcap);
-    w.op_grp = L.take<int32_t>(mcap);
-    w.op_tgt = L.take<int32_t>(mcap);
-    w.op_slo = L.take<int32_t>(mcap);
-    w.op_shi = L.take<int32_t>(mcap);
+    w.op_info = L.take<OpInfo>(mcap);
     w.srt_txn = L.take<int32_t>(mcap);
     w.grp_cnt = L.take<int32_t>(mcap);
     w.qk[0] = L.take<uint32_t>(n); w.qk[1] = L.take<uint32_t>(n);
@@ -388,6 +431,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, void* base, Ws* ws, size_t* b
     w.sort_ctrl = L.take<uint32_t>(16);
     const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
     w.scan_tmp = L.take<int32_t>(nb * (1 + GTX_MAX_APPEND));
+    w.tcnt_tmp = L.take<int32_t>(kPrepBlocks * GPUTX_MAX_TYPES);
     const int64_t nbr = std::max<int64_t>(1, (mcap + kRankTile - 1) / kRankTile);
     w.rank_tmp = L.take<RankAgg>(2 * nbr);
     *ws = w;
@@ -453,11 +497,14 @@ extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strat
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
+    PhaseMarks pm;
+    if (h->timing && h->ev && h->ring_used < gputx_ctx::kRing && b->n > 0)
+        pm.ev = h->ev + (h->ring_used++) * PH_COUNT;
     if (b->n == 0) {
         launch_empty(a, s);
     } else {
-        launch_front(a, s);
-        launch_exec(a, s);
+        launch_front(a, s, pm);
+        launch_exec(a, s, pm);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));

@@ -90,6 +90,9 @@ def _load() -> ctypes.CDLL:
                                          c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
         "gputx_last_error": (ctypes.c_char_p, [H]),
+        "gputx_phase_timing": (c_int32, [H, c_int32]),
+        "gputx_phase_times": (c_int32, [H, POINTER(ctypes.c_double), c_int32, POINTER(c_int64)]),
+        "gputx_phase_name": (ctypes.c_char_p, [c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -101,7 +104,8 @@ def _load() -> ctypes.CDLL:
 lib = _load()
 EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_options",
            "gputx_load_tables", "gputx_register_types", "gputx_workspace_size",
-           "gputx_execute_bulk", "gputx_row_count", "gputx_last_error")
+           "gputx_execute_bulk", "gputx_row_count", "gputx_last_error", "gputx_phase_timing",
+           "gputx_phase_times", "gputx_phase_name")
 
 
 class GputxError(RuntimeError):
@@ -167,6 +171,25 @@ def gputx_row_count(h, table_id: int, stream: Optional[torch.cuda.Stream] = None
     s = (stream or torch.cuda.current_stream()).cuda_stream
     _check(h, lib.gputx_row_count(h, table_id, ctypes.byref(out), s))
     return out.value
+
+
+def gputx_phase_timing(h, enable: bool) -> None:
+    _check(h, lib.gputx_phase_timing(h, 1 if enable else 0))
+
+
+def gputx_phase_name(i: int) -> Optional[str]:
+    r = lib.gputx_phase_name(i)
+    return r.decode() if r else None
+
+
+def gputx_phase_times(h) -> tuple:
+    """(dict phase -> summed ms, number of bulks summed)."""
+    ms = (ctypes.c_double * 32)()
+    nb = c_int64()
+    k = lib.gputx_phase_times(h, ms, 32, ctypes.byref(nb))
+    if k < 0:
+        _check(h, k)
+    return {gputx_phase_name(i): ms[i] for i in range(k)}, nb.value
 
 
 def stats_from(t: torch.Tensor) -> BulkStats:
