@@ -95,6 +95,64 @@ def oracle_baseline(w, bulk, width, budget_s=12.0):
             "sample": f"{reps} serial runs of the same {bulk.n}-txn bulk ({elapsed:.1f} s)"}
 
 
+def bench_batch(args):
+    """Config-4 form: 512 uneven bulks over two databases, batched (one graph
+    launch) vs plain (one execute + wait per bulk)."""
+    import torch
+    import oracle  # noqa: F401
+    from paper_1103_3105_amd import batching, gputx
+    reps = args.warmup + args.steps + 2
+    log(f"[bench] generating the 512-bulk batch workload")
+    bw = batching.config4(n_bulks=args.bulks, repeats=reps)
+    n_txn = bw.n_txns
+    eng = gputx.Engine(bw.tables, bw.types)
+    jobs = batching.device_jobs(eng, bw, gputx.STRATEGY[args.strategy])
+    o_tabs = {k: v.copy() for k, v in bw.tables.items()}
+    # plain form once, with parity against the oracle
+    gputx.gputx_phase_timing(eng.h, True)
+    outs = [dict(status=torch.empty(max(b.n, 1), dtype=torch.int32, device=eng.device),
+                 results=torch.empty((max(b.n, 1), batching.WIDTH[db]), dtype=torch.int64,
+                                     device=eng.device),
+                 stats=torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device))
+            for db, b in bw.jobs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = batching.run_plain(eng, jobs, outs)
+    plain_s = time.perf_counter() - t0
+    phases, nb = gputx.gputx_phase_times(eng.h)
+    gputx.gputx_phase_timing(eng.h, False)
+    want = batching.oracle_replay(bw, o_tabs)
+    parity = all(np.array_equal(outs[k]["status"].cpu().numpy()[:b.n], want[k][0]) and
+                 np.array_equal(outs[k]["results"].cpu().numpy()[:b.n], want[k][1])
+                 for k, (db, b) in enumerate(bw.jobs))
+    committed_plain = sum(gputx.stats_from(o["stats"]).committed for o in outs)
+    log(f"[bench] plain: {plain_s:.3f} s, parity={parity}")
+    batch = eng.batch(jobs)
+    for _ in range(args.warmup):
+        batch.launch()
+    torch.cuda.synchronize()
+    # parity of the batched form on its first timed replay (outside timing)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
+        batch.launch()
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+    committed = sum(batch.stats(k).committed for k in range(len(bw.jobs)))
+    errors = sum(batch.stats(k).error != 0 for k in range(len(bw.jobs)))
+    batched_value = committed * args.steps / (per.sum() / 1e3)
+    plain_value = committed_plain / plain_s
+    log(f"[bench] batched: {per.mean():.1f} ms/launch, {batched_value / 1e6:.2f}M txn/s; "
+        f"plain {plain_value / 1e6:.2f}M txn/s")
+    return dict(batched_value=batched_value, plain_value=plain_value, n_txns=n_txn,
+                n_bulks=len(bw.jobs), parity=bool(parity) and errors == 0,
+                ms_per_launch=float(per.mean()),
+                plain_bulk_latency_ms={"p50": float(np.percentile(lat, 50) * 1e3),
+                                       "p99": float(np.percentile(lat, 99) * 1e3)},
+                phases_ms_total_plain={k: round(v, 3) for k, v in phases.items()})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +165,8 @@ def main():
     ap.add_argument("--strategy", default="AUTO", choices=["AUTO", "TPL", "PART", "KSET"])
     ap.add_argument("--compare", action="store_true", help="also time every strategy")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
+    ap.add_argument("--bulks", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -116,6 +176,10 @@ def main():
     import torch
     import oracle
     from paper_1103_3105_amd import gputx
+
+    if args.batch_only:
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
 
     log(f"[bench] generating {args.workload} n={args.n}")
     w, wname, width = make_workload(args)

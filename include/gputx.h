@@ -166,6 +166,8 @@ typedef struct {
     int32_t n_params;       /* >= every registered type's n_params it uses          */
     const int64_t* ts;      /* [n] device, unique                                   */
     int32_t ts_sorted;      /* 1: caller promises ascending ts (checked on device)  */
+    int32_t max_ops;        /* most basic operations per txn, 0: the context's maximum
+                               over registered types (checked on device)            */
 } gputx_bulk;
 
 /* Written by the device during gputx_execute_bulk; read it after the stream
@@ -208,8 +210,12 @@ int gputx_load_tables(gputx_handle h, const gputx_table_desc* t, int n);
  * unknown procedure or a role bound to a missing or mis-typed table. */
 int gputx_register_types(gputx_handle h, const gputx_type_desc* t, int n);
 
-/* Workspace bytes gputx_execute_bulk needs for up to n_txns transactions. */
+/* Workspace bytes gputx_execute_bulk needs for up to n_txns transactions
+ * (max_ops per transaction = the context's maximum over registered types). */
 size_t gputx_workspace_size(gputx_handle h, int64_t n_txns);
+
+/* Same, for bulks whose gputx_bulk.max_ops is set to max_ops (> 0). */
+size_t gputx_workspace_size_ops(gputx_handle h, int64_t n_txns, int32_t max_ops);
 
 /* Execute one bulk (Section 5): order by timestamp, derive the basic
  * operations, group and rank them (Section 4.2), choose a strategy
@@ -226,6 +232,98 @@ size_t gputx_workspace_size(gputx_handle h, int64_t n_txns);
 int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
                        size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
                        gputx_bulk_stats* stats, gputx_stream_t stream);
+
+/* ---- batched form: many bulks, one graph launch ------------------------
+ * Each item is one bulk with its own workspace and outputs.  Items of one
+ * lane share tables and run in item order (so the serial order across them is
+ * the item order, then timestamps within a bulk); different lanes touch
+ * disjoint tables and run concurrently.  Within a lane the bulk generation of
+ * an item (timestamp order, operations, sort, ranks, Algorithm 1) overlaps the
+ * execution of the previous item, since it reads no table.  Persistent grids
+ * of concurrent lanes are sized so that all of them stay resident. */
+typedef struct {
+    gputx_bulk bulk;            /* device arrays, as for gputx_execute_bulk         */
+    int32_t strategy;           /* GPUTX_AUTO .. GPUTX_KSET                         */
+    int32_t lane;               /* 0 .. 63                                          */
+    void* workspace;            /* device, >= gputx_workspace_size(h, bulk.n)       */
+    size_t ws_bytes;
+    int32_t* status_out;        /* device int32[n]                                  */
+    int64_t* results_out;       /* device int64[n][width]                           */
+    int32_t width;
+    gputx_bulk_stats* stats;    /* device                                           */
+} gputx_batch_item;
+
+typedef struct gputx_batch_t* gputx_batch;
+
+/* Capture every item into one HIP graph and instantiate it; nothing runs
+ * yet.  Arguments are validated per item (same errors as gputx_execute_bulk).
+ * The item array is not retained; the buffers it names must stay valid while
+ * the batch exists. */
+int gputx_batch_create(gputx_handle h, const gputx_batch_item* items, int n, gputx_batch* out);
+
+/* Launch the whole batch on a stream (one graph launch).  Every launch runs
+ * every item again against the current tables. */
+int gputx_batch_launch(gputx_batch b, gputx_stream_t stream);
+
+/* Free the graph. */
+int gputx_batch_destroy(gputx_batch b);
+
+/* ---- served form: continuous batching over an arrival trace ------------
+ * Transactions enter the transaction pool at their arrival times and every
+ * bulk interval (Section 6.3's fixed interval t) everything that has arrived
+ * is cut into a bulk and issued; results return to the caller's host arrays
+ * (the result pool, Section 3.2).  Up to `slots` bulks are in flight: the
+ * bulk generation of a new bulk overlaps the execution of earlier ones, and
+ * executions keep arrival order.  Admission is bounded by an HBM budget: a
+ * cut waits for a free slot, and whatever arrives meanwhile joins it.  Runs
+ * on the calling thread until the whole trace has been answered. */
+typedef struct {
+    int64_t n;                  /* transactions                                     */
+    const int64_t* arrival_ns;  /* [n] host, non-decreasing, ns from the start      */
+    const int32_t* type;        /* [n] host                                         */
+    const int64_t* params;      /* [n_params][n] host, param-major                  */
+    int32_t n_params;
+    const int64_t* ts;          /* [n] host, ascending (ids in arrival order)       */
+} gputx_trace;
+
+typedef struct {
+    int64_t deadline_ns;        /* bulk interval                                    */
+    int32_t slots;              /* bulks in flight at most (>= 1)                   */
+    int32_t strategy;           /* GPUTX_AUTO ..                                    */
+    int64_t max_bulk;           /* largest bulk; a bigger cut is issued in pieces   */
+    int64_t hbm_budget;         /* device bytes the slots may use (0: no cap)       */
+    int32_t width;              /* result values per transaction                    */
+    int32_t max_ops;            /* per-transaction op bound (0: context maximum)    */
+} gputx_serve_opts;
+
+typedef struct {
+    int64_t first;              /* first transaction (trace index) of the bulk      */
+    int64_t count;
+    int64_t cut_ns;             /* host clock when the bulk was cut                 */
+    int64_t done_ns;            /* host clock when its results were in host memory  */
+    int32_t error;              /* bulk error, 0 = none                             */
+    int32_t slot;
+} gputx_serve_bulk;
+
+typedef struct {
+    int64_t n_bulks;            /* bulks issued (records beyond the capacity dropped) */
+    int64_t committed;
+    int64_t aborted;
+    int64_t invalid;
+    int64_t elapsed_ns;         /* start .. last results back                       */
+    int32_t slots_used;         /* slots the HBM budget allowed                     */
+    int32_t reserved;
+} gputx_serve_report;
+
+/* Serve a whole trace.  status_out [n] / results_out [n][width] are host
+ * arrays (page-locked for overlap), bulks[] receives up to bulk_capacity
+ * per-bulk records in issue order.  Per-transaction commit latency is
+ * done_ns of its bulk minus its arrival time.  Errors: GPUTX_E_ARG (trace not
+ * in arrival order, bad options), GPUTX_E_CAPACITY (budget below one slot), a
+ * device bulk error code, GPUTX_E_HIP. */
+int gputx_serve(gputx_handle h, const gputx_trace* trace, const gputx_serve_opts* opts,
+                int32_t* status_out, int64_t* results_out, gputx_serve_bulk* bulks,
+                int64_t bulk_capacity, gputx_serve_report* report);
 
 /* Current row count of a table (append tables advance on the device);
  * synchronises the stream. */

@@ -82,6 +82,7 @@ struct BulkArgs {
 };
 
 constexpr int kPrepBlocks = 1024;
+constexpr int kPartLdsMax = 120 * 1024;  // dynamic LDS cap of one PART wave
 constexpr int kScanItems = 8;
 constexpr int kScanTile = GTX_BLOCK * kScanItems;
 constexpr int kRankItems = 8;
@@ -105,5 +106,9 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 void launch_empty(const BulkArgs& a, hipStream_t s);
 // workgroups of the persistent executors that fit on one compute unit
 int exec_resident_blocks_per_cu();
+// LDS bytes of one PART wave for these arguments
+size_t part_wave_lds(const BulkArgs& a);
+// one-time kernel attributes (large dynamic LDS for PART)
+void exec_init_attributes();
 
 }  // namespace gtx

@@ -84,7 +84,8 @@ __device__ __forceinline__ int32_t exec_txn(const BulkArgs& a, const TxnIn& x) {
 template <int P>
 __device__ __forceinline__ int32_t exec_txn_p(const BulkArgs& a, const DevType& T, const TxnIn& x) {
     int64_t res[GTX_MAX_RESULTS];
-    const int32_t s = txn_exec_p<P>(T, x.prm, x.ts, x.app0, x.app1, res);
+    DirectAcc acc;
+    const int32_t s = txn_exec_p<P>(acc, T, x.prm, x.ts, x.app0, x.app1, res);
     a.status[x.i] = s;
     int64_t* out = a.results + x.i * a.width;
 #pragma unroll
@@ -450,73 +451,106 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Lane 0 runs the chunk's cnt transactions in order.  P != 0: every one runs
-// procedure P with descriptor T; P == 0: mixed types, full switch.
+// Signatures of one PART chunk staged in LDS, one column per transaction.
+struct PartChunk {
+    int64_t* res;   // [16][64] results
+    int64_t* prm;   // [npb][64] parameters
+    int64_t* ts;    // [64]
+    int64_t* app0;  // [64]
+    int64_t* app1;  // [64]
+    int32_t* t;     // [64] type
+    int32_t* np;    // [64] parameters loaded
+    int32_t* st;    // [64] status
+};
+
+// Lane 0 runs the chunk's cnt transactions in order, straight against the
+// tables (the lanes have already touched every row, so loads hit cache).
+// Statuses and results go to LDS; the owning lanes write them out after the
+// chunk.  P != 0: all run procedure P with descriptor T; P == 0: mixed types.
 template <int P>
-__device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const int64_t* lp,
-                                            int cnt, int32_t t, int32_t np, int64_t i, int64_t ts,
-                                            int64_t app0, int64_t app1, int64_t& committed,
-                                            int64_t& aborted) {
-    const int npb = P ? T.n_params : GTX_MAX_PARAMS;
+__device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
+                                            int cnt, int64_t& committed, int64_t& aborted) {
+    constexpr int npb = proc_params(P);  // parameters the procedure can read
+    if (lane_id() != 0) return;
     for (int k = 0; k < cnt; ++k) {
-        TxnIn y;
-        y.t = __builtin_amdgcn_readlane(t, k);
-        y.np = __builtin_amdgcn_readlane(np, k);
-        y.i = rl64(i, k);
-        y.ts = rl64(ts, k);
-        y.app0 = rl64(app0, k);
-        y.app1 = rl64(app1, k);
+        const int32_t ynp = c.np[k];
+        int64_t prm[GTX_MAX_PARAMS];
 #pragma unroll
-        for (int r = 0; r < GTX_MAX_PARAMS; ++r) y.prm[r] = (r < y.np && r < npb) ? lp[r * 64 + k] : 0;
-        if (lane_id() == 0) {
-            const int32_t s = P ? exec_txn_p<P>(a, T, y) : exec_txn(a, y);
-            committed += s == GPUTX_COMMIT;
-            aborted += s == GPUTX_ABORT;
-        }
+        for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = (r < ynp && r < npb) ? c.prm[r * 64 + k] : 0;
+        int64_t res[GTX_MAX_RESULTS];
+        DirectAcc acc;
+        const int32_t s = P ? txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res)
+                            : txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
+        c.st[k] = s;
+#pragma unroll
+        for (int r = 0; r < GTX_MAX_RESULTS; ++r) c.res[r * 64 + k] = res[r];
+        committed += s == GPUTX_COMMIT;
+        aborted += s == GPUTX_ABORT;
     }
 }
 
-// One wave per partition, still one serial thread of control: the wave's 64
-// lanes load the partition's next 64 signatures (parameters staged in LDS,
-// the rest in registers) and touch the rows those transactions will use;
-// then lane 0 runs the 64 one after another, reading each signature with
-// uniform LDS reads and lane broadcasts.  For few, long partitions.
-__global__ __launch_bounds__(GTX_BLOCK) void k_part_wave(BulkArgs a) {
+size_t part_wave_lds(const BulkArgs& a) {
+    const int npb = std::min(a.n_params, GTX_MAX_PARAMS);
+    return (size_t)64 * 8 * (GTX_MAX_RESULTS + npb + 3) + (size_t)64 * 4 * 3;
+}
+
+// One wave per partition, still one serial thread of control (Section 5.2).
+// For each chunk of 64 of the partition's transactions the lanes load the
+// signatures into LDS and touch every row their transaction will use; lane 0
+// then runs the 64 in order; finally the owning lanes write statuses and
+// results.
+__global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
-    extern __shared__ int64_t part_lds[];
-    const int64_t q = (int64_t)blockIdx.x * GTX_WAVES + wave_id();
+    const int64_t q = blockIdx.x;
     if (q >= a.n_parts) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int lane = lane_id();
+    const int npb = min(a.n_params, GTX_MAX_PARAMS);
+    PartChunk c;
+    c.res = reinterpret_cast<int64_t*>(part_lds);
+    c.prm = c.res + 64 * GTX_MAX_RESULTS;
+    c.ts = c.prm + 64 * npb;
+    c.app0 = c.ts + 64;
+    c.app1 = c.app0 + 64;
+    c.t = reinterpret_cast<int32_t*>(c.app1 + 64);
+    c.np = c.t + 64;
+    c.st = c.np + 64;
+
     const int src = a.part_passes & 1;
-    const int npb = min(a.n_params, GTX_MAX_PARAMS);  // parameters per signature
-    int64_t* lp = part_lds + (int64_t)wave_id() * npb * 64;
     const uint32_t* pos = a.ws.qv[src];
     int64_t lo, end;
     part_range(a, a.ws.qk[src], q, &lo, &end);
     int64_t committed = 0, aborted = 0, sink = 0;
     for (int64_t c0 = lo; c0 < end; c0 += 64) {
         const int64_t j = c0 + lane;
-        int32_t t = 0, np = 0;
-        int64_t i = 0, ts = 0, app0 = 0, app1 = 0;
+        int64_t i = 0;
+        int32_t t = -1;
         if (j < end) {
             const int32_t p = (int32_t)pos[j];
             t = a.ws.tty[p];
             TxnIn x;
             load_txn(a, p, t, x);
-            for (int k = 0; k < npb; ++k) lp[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
+#pragma unroll
+            for (int k = 0; k < GTX_MAX_PARAMS; ++k)
+                if (k < npb) c.prm[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
+            c.ts[lane] = x.ts;
+            c.app0[lane] = x.app0;
+            c.app1[lane] = x.app1;
+            c.t[lane] = t;
+            c.np[lane] = x.np;
             sink ^= txn_touch(a.types[t], x.prm);
-            i = x.i; ts = x.ts; app0 = x.app0; app1 = x.app1; np = x.np;
+            i = x.i;
         }
+        __syncthreads();
         const int cnt = (int)min<int64_t>(64, end - c0);
-        // one procedure for the whole chunk (the common case): dispatch once
         const int t0 = __builtin_amdgcn_readfirstlane(t);
         const bool uniform = __ballot(j < end && t != t0) == 0;
         const int proc = uniform ? a.types[t0].proc : 0;
         switch (proc) {
-#define GTX_PART_CASE(P)                                                                   \
-    case P:                                                                                \
-        part_serial<P>(a, a.types[t0], lp, cnt, t, np, i, ts, app0, app1, committed, aborted); \
+#define GTX_PART_CASE(P)                                              \
+    case P:                                                           \
+        part_serial<P>(a, a.types[t0], c, cnt, committed, aborted);   \
         break;
             GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
             GTX_PART_CASE(GPUTX_NEW_ORDER)
@@ -530,8 +564,18 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part_wave(BulkArgs a) {
             GTX_PART_CASE(GPUTX_DEL_CF)
 #undef GTX_PART_CASE
         default:
-            part_serial<0>(a, a.types[t0], lp, cnt, t, np, i, ts, app0, app1, committed, aborted);
+            part_serial<0>(a, a.types[t0], c, cnt, committed, aborted);
         }
+        __syncthreads();
+        if (j < end) {
+            a.status[i] = c.st[lane];
+            int64_t* out = a.results + i * a.width;
+#pragma unroll
+            for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+                if (r < a.width) out[r] = c.res[r * 64 + lane];
+            for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
+        }
+        __syncthreads();
     }
     if (sink == (int64_t)0x7fe1d2c3b4a59687ll) st->pad[0] = 1;  // keeps the touches live
     add_counts(st, committed, aborted);
@@ -565,6 +609,17 @@ __global__ void k_finalize(BulkArgs a) {
 
 // ---------------------------------------------------------------------------
 
+// First kernel of the execution phase: the batched update must fit the
+// append tables (their row counts are final once the previous bulk on the
+// same tables has finished).  Nothing runs after a failure.
+__global__ void k_exec_gate(BulkArgs a) {
+    GtxState* st = a.ws.st;
+    if (threadIdx.x != 0 || st->error) return;
+    for (int k = 0; k < a.n_app; ++k)
+        if (st->app_total[k] > 0 && a.rowcount[k] + st->app_total[k] > a.capacity[k])
+            st->error = GPUTX_E_CAPACITY;
+}
+
 __global__ void k_reset_state(GtxState* st) {
     int* w = reinterpret_cast<int*>(st);
     for (int i = threadIdx.x; i < (int)(sizeof(GtxState) / 4); i += blockDim.x) w[i] = 0;
@@ -573,6 +628,14 @@ __global__ void k_reset_state(GtxState* st) {
 void launch_empty(const BulkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, a.ws.st);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+}
+
+void exec_init_attributes() {
+    static bool done = false;
+    if (done) return;
+    done = true;
+    (void)hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kPartLdsMax);
 }
 
 int exec_resident_blocks_per_cu() {
@@ -586,6 +649,7 @@ int exec_resident_blocks_per_cu() {
 }
 
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
+    hipLaunchKernelGGL(k_exec_gate, dim3(1), dim3(64), 0, s, a);
     // PART: group transactions by partition (stable, so timestamp order is
     // kept inside each partition); only when PART was chosen
     const bool part = a.strategy == GPUTX_AUTO || a.strategy == GPUTX_PART;
@@ -601,10 +665,8 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     }
     pm.mark(PH_PARTSORT, s);
     if (part) {
-        if (a.n_parts <= 8192) {  // few long partitions: one wave each
-            const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_WAVES - 1) / GTX_WAVES);
-            const size_t lds = (size_t)GTX_WAVES * 64 * std::min(a.n_params, GTX_MAX_PARAMS) * 8;
-            hipLaunchKernelGGL(k_part_wave, dim3(blocks), dim3(GTX_BLOCK), lds, s, a);
+        if (a.n_parts <= 8192 && part_wave_lds(a) <= (size_t)kPartLdsMax) {  // few long partitions: one wave each
+            hipLaunchKernelGGL(k_part_wave, dim3((unsigned)a.n_parts), dim3(64), part_wave_lds(a), s, a);
         } else {
             const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_BLOCK - 1) / GTX_BLOCK);
             hipLaunchKernelGGL(k_part, dim3(blocks), dim3(GTX_BLOCK), 0, s, a);

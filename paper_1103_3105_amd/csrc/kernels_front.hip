@@ -144,18 +144,27 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_scan_mid(BulkArgs a, int K, int n
             else st->app_total[k - 1] = running;
         }
     }
-    if (threadIdx.x < GPUTX_MAX_TYPES) {
+    {
+        // type counts: 16 threads per type, each over a stride of the blocks
+        __shared__ int part[GTX_BLOCK];
         const int nblk = (int)std::min<int64_t>(kPrepBlocks, (a.n + GTX_BLOCK - 1) / GTX_BLOCK);
+        const int ty = threadIdx.x % GPUTX_MAX_TYPES, lane16 = threadIdx.x / GPUTX_MAX_TYPES;
         int c = 0;
-        for (int b = 0; b < nblk; ++b) c += a.ws.tcnt_tmp[b * GPUTX_MAX_TYPES + threadIdx.x];
-        st->type_count[threadIdx.x] = c;
+        for (int b = lane16; b < nblk; b += GTX_BLOCK / GPUTX_MAX_TYPES)
+            c += a.ws.tcnt_tmp[b * GPUTX_MAX_TYPES + ty];
+        part[threadIdx.x] = c;
+        __syncthreads();
+        if (threadIdx.x < GPUTX_MAX_TYPES) {
+            int tot = 0;
+            for (int k = 0; k < GTX_BLOCK / GPUTX_MAX_TYPES; ++k) tot += part[k * GPUTX_MAX_TYPES + threadIdx.x];
+            st->type_count[threadIdx.x] = tot;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // (append capacity depends on the tables' row counts, so it is checked
+        // at the start of execution, not here)
         if (st->m > a.mcap) set_error(st, GPUTX_E_CAPACITY);
-        for (int k = 0; k < a.n_app; ++k)
-            if (st->app_total[k] > 0 && a.rowcount[k] + st->app_total[k] > a.capacity[k])
-                set_error(st, GPUTX_E_CAPACITY);
     }
 }
 

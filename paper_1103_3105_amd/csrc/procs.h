@@ -217,75 +217,94 @@ __device__ inline int64_t txn_touch(const DevType& T, const int64_t* p) {
     return s;
 }
 
+// Table-cell access used by the procedures.  DirectAcc reads and writes the
+// columns in place; a serial PART wave substitutes an LDS-backed accessor
+// (kernels_exec.hip).  ld/st are cells other transactions of the bulk may
+// read; app is a row appended to an append-only table.
+struct DirectAcc {
+    template <class V>
+    __device__ __forceinline__ V ld(GTX_GLOBAL V* p) { return *p; }
+    template <class V>
+    __device__ __forceinline__ void st(GTX_GLOBAL V* p, V v) { *p = v; }
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
+};
+
+// Parameters procedure P reads (0: any procedure, the widest signature).
+__host__ __device__ constexpr int proc_params(int proc) {
+    return proc == GPUTX_DEBIT_CREDIT ? 4 : proc == GPUTX_NEW_ORDER ? 34 : proc == GPUTX_PAYMENT ? 4
+         : proc == GPUTX_ORDER_STATUS ? 3 : proc == GPUTX_GET_SUB ? 1
+         : (proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 2
+         : (proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 3 : proc == GPUTX_INS_CF ? 4 : 34;
+}
 // Run one valid transaction of procedure P (one case of the switch of
-// Section 3.2).  app0/app1 are the rows its appends occupy.  Returns its
-// status, fills res[0..15].
-template <int P>
-__device__ __forceinline__ int32_t txn_exec_p(const DevType& T, const int64_t* p, int64_t ts,
+// Section 3.2) through accessor acc.  app0/app1 are the rows its appends
+// occupy.  Returns its status, fills res[0..15].
+template <int P, class Acc>
+__device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const int64_t* p, int64_t ts,
                                               int64_t app0, int64_t app1, int64_t* res) {
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
     switch (P) {
     case GPUTX_DEBIT_CREDIT: {
-        GTX_GLOBAL int64_t* A = colp<int64_t>(T, 0, 0);
-        GTX_GLOBAL int64_t* Tl = colp<int64_t>(T, 1, 0);
-        GTX_GLOBAL int64_t* B = colp<int64_t>(T, 2, 0);
-        int64_t a = wrap_add(A[p[0]], p[3]);
-        int64_t t = wrap_add(Tl[p[1]], p[3]);
-        int64_t b = wrap_add(B[p[2]], p[3]);
-        A[p[0]] = a;
-        Tl[p[1]] = t;
-        B[p[2]] = b;
-        colp<int64_t>(T, 3, 0)[app0] = p[0];
-        colp<int64_t>(T, 3, 1)[app0] = p[1];
-        colp<int64_t>(T, 3, 2)[app0] = p[2];
-        colp<int64_t>(T, 3, 3)[app0] = p[3];
-        colp<int64_t>(T, 3, 4)[app0] = ts;
+        GTX_GLOBAL int64_t* A = colp<int64_t>(T, 0, 0) + p[0];
+        GTX_GLOBAL int64_t* Tl = colp<int64_t>(T, 1, 0) + p[1];
+        GTX_GLOBAL int64_t* B = colp<int64_t>(T, 2, 0) + p[2];
+        int64_t a = wrap_add(acc.ld(A), p[3]);
+        int64_t t = wrap_add(acc.ld(Tl), p[3]);
+        int64_t b = wrap_add(acc.ld(B), p[3]);
+        acc.st(A, a);
+        acc.st(Tl, t);
+        acc.st(B, b);
+        acc.app(colp<int64_t>(T, 3, 0) + app0, p[0]);
+        acc.app(colp<int64_t>(T, 3, 1) + app0, p[1]);
+        acc.app(colp<int64_t>(T, 3, 2) + app0, p[2]);
+        acc.app(colp<int64_t>(T, 3, 3) + app0, p[3]);
+        acc.app(colp<int64_t>(T, 3, 4) + app0, ts);
         res[0] = a;
         res[1] = t;
         res[2] = b;
         return GPUTX_COMMIT;
     }
     case GPUTX_NEW_ORDER: {
-        GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0);
         int64_t k = p[3];
         res[0] = k;
 #pragma unroll
         for (int j = 0; j < 15; ++j) {
             if (j < k) {
-                int64_t row = p[0] * T.dims[3] + p[4 + j];
-                int64_t s = (int64_t)S[row] - p[19 + j];
+                GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0) + (p[0] * T.dims[3] + p[4 + j]);
+                int64_t s = (int64_t)acc.ld(S) - p[19 + j];
                 if (s < 10) s += 91;
                 int32_t s32 = to_i32(s);
-                S[row] = s32;
+                acc.st(S, s32);
                 res[1 + j] = s32;
                 int64_t r = app1 + j;
-                colp<int64_t>(T, 5, 0)[r] = ts;
-                colp<int64_t>(T, 5, 1)[r] = j;
-                colp<int64_t>(T, 5, 2)[r] = p[4 + j];
-                colp<int64_t>(T, 5, 3)[r] = p[19 + j];
-                colp<int64_t>(T, 5, 4)[r] = p[0];
+                acc.app(colp<int64_t>(T, 5, 0) + r, ts);
+                acc.app(colp<int64_t>(T, 5, 1) + r, (int64_t)j);
+                acc.app(colp<int64_t>(T, 5, 2) + r, p[4 + j]);
+                acc.app(colp<int64_t>(T, 5, 3) + r, p[19 + j]);
+                acc.app(colp<int64_t>(T, 5, 4) + r, p[0]);
             }
         }
-        colp<int64_t>(T, 4, 0)[app0] = ts;
-        colp<int64_t>(T, 4, 1)[app0] = p[0];
-        colp<int64_t>(T, 4, 2)[app0] = p[1];
-        colp<int64_t>(T, 4, 3)[app0] = p[2];
-        colp<int64_t>(T, 4, 4)[app0] = k;
+        acc.app(colp<int64_t>(T, 4, 0) + app0, ts);
+        acc.app(colp<int64_t>(T, 4, 1) + app0, p[0]);
+        acc.app(colp<int64_t>(T, 4, 2) + app0, p[1]);
+        acc.app(colp<int64_t>(T, 4, 3) + app0, p[2]);
+        acc.app(colp<int64_t>(T, 4, 4) + app0, k);
         return GPUTX_COMMIT;
     }
     case GPUTX_PAYMENT: {
         int64_t drow = p[0] * T.dims[1] + p[1];
         int64_t crow = drow * T.dims[2] + p[2];
-        GTX_GLOBAL int64_t* Wb = colp<int64_t>(T, 0, 0);
-        GTX_GLOBAL int64_t* Db = colp<int64_t>(T, 1, 0);
-        GTX_GLOBAL int64_t* Cb = colp<int64_t>(T, 2, 0);
-        int64_t w = wrap_add(Wb[p[0]], p[3]);
-        int64_t d = wrap_add(Db[drow], p[3]);
-        int64_t c = wrap_add(Cb[crow], p[3]);
-        Wb[p[0]] = w;
-        Db[drow] = d;
-        Cb[crow] = c;
+        GTX_GLOBAL int64_t* Wb = colp<int64_t>(T, 0, 0) + p[0];
+        GTX_GLOBAL int64_t* Db = colp<int64_t>(T, 1, 0) + drow;
+        GTX_GLOBAL int64_t* Cb = colp<int64_t>(T, 2, 0) + crow;
+        int64_t w = wrap_add(acc.ld(Wb), p[3]);
+        int64_t d = wrap_add(acc.ld(Db), p[3]);
+        int64_t c = wrap_add(acc.ld(Cb), p[3]);
+        acc.st(Wb, w);
+        acc.st(Db, d);
+        acc.st(Cb, c);
         res[0] = w;
         res[1] = d;
         res[2] = c;
@@ -293,73 +312,81 @@ __device__ __forceinline__ int32_t txn_exec_p(const DevType& T, const int64_t* p
     }
     case GPUTX_ORDER_STATUS: {
         int64_t crow = (p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2];
-        res[0] = colp<int64_t>(T, 2, 0)[crow];
+        res[0] = acc.ld(colp<int64_t>(T, 2, 0) + crow);
         return GPUTX_COMMIT;
     }
     case GPUTX_GET_SUB: {
 #pragma unroll
-        for (int f = 0; f < 14; ++f) res[f] = colp<int32_t>(T, 0, 1 + f)[p[0]];
+        for (int f = 0; f < 14; ++f) res[f] = acc.ld(colp<int32_t>(T, 0, 1 + f) + p[0]);
         return GPUTX_COMMIT;
     }
     case GPUTX_GET_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        res[0] = colp<int32_t>(T, 1, 0)[slot];
-        res[1] = colp<int32_t>(T, 1, 1)[slot];
-        res[2] = colp<int64_t>(T, 1, 2)[slot];
+        res[0] = acc.ld(colp<int32_t>(T, 1, 0) + slot);
+        res[1] = acc.ld(colp<int32_t>(T, 1, 1) + slot);
+        res[2] = acc.ld(colp<int64_t>(T, 1, 2) + slot);
         return GPUTX_COMMIT;
     }
     case GPUTX_UPD_SUB_FIELD:
     case GPUTX_UPD_LOC: {
         int c = 1 + (int)p[1] + (P == GPUTX_UPD_LOC ? 4 : 0);
-        GTX_GLOBAL int32_t* F = colp<int32_t>(T, 0, c);
-        res[0] = F[p[0]];
-        F[p[0]] = to_i32(p[2]);
+        GTX_GLOBAL int32_t* F = colp<int32_t>(T, 0, c) + p[0];
+        res[0] = acc.ld(F);
+        acc.st(F, to_i32(p[2]));
         return GPUTX_COMMIT;
     }
     case GPUTX_INS_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0);
-        int32_t o = occ[slot];
+        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0) + slot;
+        int32_t o = acc.ld(occ);
         res[0] = o;
         if (o) return GPUTX_ABORT;  // read phase decides; nothing written
-        occ[slot] = 1;
-        colp<int32_t>(T, 1, 1)[slot] = to_i32(p[2]);
-        colp<int64_t>(T, 1, 2)[slot] = p[3];
+        acc.st(occ, (int32_t)1);
+        acc.st(colp<int32_t>(T, 1, 1) + slot, to_i32(p[2]));
+        acc.st(colp<int64_t>(T, 1, 2) + slot, p[3]);
         return GPUTX_COMMIT;
     }
     case GPUTX_DEL_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0);
-        if (!occ[slot]) return GPUTX_ABORT;
+        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0) + slot;
+        if (!acc.ld(occ)) return GPUTX_ABORT;
         res[0] = 1;
-        res[1] = colp<int32_t>(T, 1, 1)[slot];
-        res[2] = colp<int64_t>(T, 1, 2)[slot];
-        occ[slot] = 0;
-        colp<int32_t>(T, 1, 1)[slot] = 0;
-        colp<int64_t>(T, 1, 2)[slot] = 0;
+        res[1] = acc.ld(colp<int32_t>(T, 1, 1) + slot);
+        res[2] = acc.ld(colp<int64_t>(T, 1, 2) + slot);
+        acc.st(occ, (int32_t)0);
+        acc.st(colp<int32_t>(T, 1, 1) + slot, (int32_t)0);
+        acc.st(colp<int64_t>(T, 1, 2) + slot, (int64_t)0);
         return GPUTX_COMMIT;
     }
     }
     return GPUTX_INVALID;
 }
 
-// The combined kernel's switch on the procedure (Section 3.2).
-__device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t ts, int64_t app0,
-                                   int64_t app1, int64_t* res) {
+// The combined kernel's switch on the procedure (Section 3.2), any accessor.
+template <class Acc>
+__device__ __forceinline__ int32_t txn_exec_any(Acc& acc, const DevType& T, const int64_t* p, int64_t ts,
+                                       int64_t app0, int64_t app1, int64_t* res) {
     switch (T.proc) {
-    case GPUTX_DEBIT_CREDIT: return txn_exec_p<GPUTX_DEBIT_CREDIT>(T, p, ts, app0, app1, res);
-    case GPUTX_NEW_ORDER: return txn_exec_p<GPUTX_NEW_ORDER>(T, p, ts, app0, app1, res);
-    case GPUTX_PAYMENT: return txn_exec_p<GPUTX_PAYMENT>(T, p, ts, app0, app1, res);
-    case GPUTX_ORDER_STATUS: return txn_exec_p<GPUTX_ORDER_STATUS>(T, p, ts, app0, app1, res);
-    case GPUTX_GET_SUB: return txn_exec_p<GPUTX_GET_SUB>(T, p, ts, app0, app1, res);
-    case GPUTX_GET_CF: return txn_exec_p<GPUTX_GET_CF>(T, p, ts, app0, app1, res);
-    case GPUTX_UPD_SUB_FIELD: return txn_exec_p<GPUTX_UPD_SUB_FIELD>(T, p, ts, app0, app1, res);
-    case GPUTX_UPD_LOC: return txn_exec_p<GPUTX_UPD_LOC>(T, p, ts, app0, app1, res);
-    case GPUTX_INS_CF: return txn_exec_p<GPUTX_INS_CF>(T, p, ts, app0, app1, res);
-    case GPUTX_DEL_CF: return txn_exec_p<GPUTX_DEL_CF>(T, p, ts, app0, app1, res);
+    case GPUTX_DEBIT_CREDIT: return txn_exec_p<GPUTX_DEBIT_CREDIT>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_NEW_ORDER: return txn_exec_p<GPUTX_NEW_ORDER>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_PAYMENT: return txn_exec_p<GPUTX_PAYMENT>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_ORDER_STATUS: return txn_exec_p<GPUTX_ORDER_STATUS>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_GET_SUB: return txn_exec_p<GPUTX_GET_SUB>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_GET_CF: return txn_exec_p<GPUTX_GET_CF>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_UPD_SUB_FIELD: return txn_exec_p<GPUTX_UPD_SUB_FIELD>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_UPD_LOC: return txn_exec_p<GPUTX_UPD_LOC>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_INS_CF: return txn_exec_p<GPUTX_INS_CF>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_DEL_CF: return txn_exec_p<GPUTX_DEL_CF>(acc, T, p, ts, app0, app1, res);
     }
     for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
     return GPUTX_INVALID;
 }
+
+__device__ inline int32_t txn_exec(const DevType& T, const int64_t* p, int64_t ts, int64_t app0,
+                                   int64_t app1, int64_t* res) {
+    DirectAcc acc;
+    return txn_exec_any(acc, T, p, ts, app0, app1, res);
+}
+
 
 }  // namespace gtx

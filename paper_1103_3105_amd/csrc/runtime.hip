@@ -11,47 +11,15 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
-#include "engine.h"
+#include "runtime.h"
 
 using namespace gtx;
 
-struct gputx_ctx {
-    int device = 0;
-    int ncu = 0;
-    uint64_t wall_khz = 0;
-    gputx_options opt{};
-    struct Tab {
-        bool present = false;
-        gputx_table_desc d{};
-        int app_idx = -1;
-        uint32_t key_base = 0;
-        int64_t part_base = -1;  // for root tables: first global partition id
-    } tabs[GPUTX_MAX_TABLES];
-    int n_app = 0;
-    int app_table[GTX_MAX_APPEND] = {-1, -1, -1, -1};
-    uint64_t total_items = 0;
-    int key_passes = 1;
-    int64_t n_parts = 0;
-    int part_passes = 1;
-    bool type_present[GPUTX_MAX_TYPES] = {};
-    gputx_type_desc types[GPUTX_MAX_TYPES]{};
-    int max_ops = 1;
-    DevType* d_types = nullptr;
-    int64_t* d_rowcount = nullptr;
-    int64_t* d_capacity = nullptr;
-    std::string err;
-    // phase timing ring
-    static constexpr int kRing = 256;
-    bool timing = false;
-    hipEvent_t* ev = nullptr;  // kRing * PH_COUNT
-    int ring_used = 0;
-};
-
 static thread_local std::string g_err;
 
-static int set_err(gputx_handle h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
-static int set_err(gputx_handle h, int code, const char* fmt, ...) {
+int gtx_set_err(gputx_handle h, int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -62,12 +30,7 @@ static int set_err(gputx_handle h, int code, const char* fmt, ...) {
     return code;
 }
 
-#define HIP_OK(h, call)                                                                     \
-    do {                                                                                    \
-        hipError_t e_ = (call);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return set_err((h), GPUTX_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
+
 
 static int bits_for(uint64_t v) {  // bits needed to represent v
     int b = 0;
@@ -95,7 +58,7 @@ extern "C" int gputx_default_options(gputx_options* o) {
 static int refresh_layout(gputx_handle h);
 
 extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out) {
-    if (!out) return set_err(nullptr, GPUTX_E_ARG, "out is null");
+    if (!out) return gtx_set_err(nullptr, GPUTX_E_ARG, "out is null");
     *out = nullptr;
     gputx_handle h = new gputx_ctx();
     h->device = dev;
@@ -112,7 +75,7 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     if (e == hipSuccess) e = hipMemset(h->d_rowcount, 0, sizeof(int64_t) * GTX_MAX_APPEND);
     if (e == hipSuccess) e = hipMemset(h->d_capacity, 0, sizeof(int64_t) * GTX_MAX_APPEND);
     if (e != hipSuccess) {
-        int rc = set_err(nullptr, GPUTX_E_HIP, "device setup failed: %s", hipGetErrorString(e));
+        int rc = gtx_set_err(nullptr, GPUTX_E_HIP, "device setup failed: %s", hipGetErrorString(e));
         if (h->d_types) (void)hipFree(h->d_types);
         if (h->d_rowcount) (void)hipFree(h->d_rowcount);
         if (h->d_capacity) (void)hipFree(h->d_capacity);
@@ -121,6 +84,7 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     }
     h->ncu = ncu;
     h->wall_khz = khz > 0 ? (uint64_t)khz : 100000;
+    exec_init_attributes();
     *out = h;
     return GPUTX_OK;
 }
@@ -140,7 +104,7 @@ extern "C" int gputx_destroy(gputx_handle h) {
 }
 
 extern "C" int gputx_phase_timing(gputx_handle h, int enable) {
-    if (!h) return set_err(h, GPUTX_E_ARG, "null handle");
+    if (!h) return gtx_set_err(h, GPUTX_E_ARG, "null handle");
     HIP_OK(h, hipSetDevice(h->device));
     if (enable && !h->ev) {
         h->ev = new hipEvent_t[gputx_ctx::kRing * PH_COUNT];
@@ -160,7 +124,7 @@ extern "C" const char* gputx_phase_name(int i) {
 }
 
 extern "C" int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n_bulks) {
-    if (!h || (cap > 0 && !ms)) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    if (!h || (cap > 0 && !ms)) return gtx_set_err(h, GPUTX_E_ARG, "bad arguments");
     HIP_OK(h, hipSetDevice(h->device));
     for (int i = 0; i < cap; ++i) ms[i] = 0;
     if (n_bulks) *n_bulks = h->ring_used;
@@ -177,34 +141,34 @@ extern "C" int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n
 }
 
 extern "C" int gputx_set_options(gputx_handle h, const gputx_options* opt) {
-    if (!h || !opt) return set_err(h, GPUTX_E_ARG, "null argument");
+    if (!h || !opt) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
     if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0)
-        return set_err(h, GPUTX_E_ARG, "bad option value");
+        return gtx_set_err(h, GPUTX_E_ARG, "bad option value");
     h->opt = *opt;
     return refresh_layout(h);
 }
 
 extern "C" int gputx_load_tables(gputx_handle h, const gputx_table_desc* t, int n) {
-    if (!h || (n > 0 && !t) || n < 0) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    if (!h || (n > 0 && !t) || n < 0) return gtx_set_err(h, GPUTX_E_ARG, "bad arguments");
     HIP_OK(h, hipSetDevice(h->device));
     for (int i = 0; i < n; ++i) {
         const gputx_table_desc& d = t[i];
         if (d.table_id < 0 || d.table_id >= GPUTX_MAX_TABLES)
-            return set_err(h, GPUTX_E_ARG, "table_id %d out of range", d.table_id);
+            return gtx_set_err(h, GPUTX_E_ARG, "table_id %d out of range", d.table_id);
         if (h->tabs[d.table_id].present)
-            return set_err(h, GPUTX_E_ARG, "table %d already loaded", d.table_id);
+            return gtx_set_err(h, GPUTX_E_ARG, "table %d already loaded", d.table_id);
         if (d.n_cols < 1 || d.n_cols > GPUTX_MAX_COLS || d.n_rows < 0 || d.capacity < d.n_rows)
-            return set_err(h, GPUTX_E_ARG, "table %d: bad shape", d.table_id);
+            return gtx_set_err(h, GPUTX_E_ARG, "table %d: bad shape", d.table_id);
         if (d.root_table_id >= GPUTX_MAX_TABLES || (d.root_table_id >= 0 && d.root_div < 1))
-            return set_err(h, GPUTX_E_ARG, "table %d: bad root", d.table_id);
+            return gtx_set_err(h, GPUTX_E_ARG, "table %d: bad root", d.table_id);
         for (int c = 0; c < d.n_cols; ++c) {
             if (d.col_dtype[c] != GPUTX_I32 && d.col_dtype[c] != GPUTX_I64)
-                return set_err(h, GPUTX_E_ARG, "table %d col %d: bad dtype", d.table_id, c);
+                return gtx_set_err(h, GPUTX_E_ARG, "table %d col %d: bad dtype", d.table_id, c);
             if (!d.col_ptr[c] && d.capacity > 0)
-                return set_err(h, GPUTX_E_ARG, "table %d col %d: null column", d.table_id, c);
+                return gtx_set_err(h, GPUTX_E_ARG, "table %d col %d: null column", d.table_id, c);
         }
         if (d.append_only && h->n_app >= GTX_MAX_APPEND)
-            return set_err(h, GPUTX_E_CAPACITY, "at most %d append-only tables", GTX_MAX_APPEND);
+            return gtx_set_err(h, GPUTX_E_CAPACITY, "at most %d append-only tables", GTX_MAX_APPEND);
     }
     for (int i = 0; i < n; ++i) {
         const gputx_table_desc& d = t[i];
@@ -233,7 +197,7 @@ static int refresh_layout(gputx_handle h) {
         T.key_base = (uint32_t)base;
         base += (uint64_t)T.d.n_rows;
     }
-    if (base >= 0xffffffffull) return set_err(h, GPUTX_E_CAPACITY, "more than 2^32-1 data items");
+    if (base >= 0xffffffffull) return gtx_set_err(h, GPUTX_E_CAPACITY, "more than 2^32-1 data items");
     h->total_items = base;
     h->key_passes = passes_for(base ? base - 1 : 0);
     int64_t pb = 0;
@@ -247,7 +211,7 @@ static int refresh_layout(gputx_handle h) {
         T.part_base = pb;
         pb += (T.d.n_rows + h->opt.part_size - 1) / h->opt.part_size;
     }
-    if (pb >= 0xffffffffll) return set_err(h, GPUTX_E_CAPACITY, "too many partitions");
+    if (pb >= 0xffffffffll) return gtx_set_err(h, GPUTX_E_CAPACITY, "too many partitions");
     h->n_parts = pb;
     h->part_passes = passes_for((uint64_t)pb);  // sentinel id = n_parts
     // re-resolve registered types (key bases or partition size may have moved)
@@ -312,16 +276,16 @@ static bool proc_spec(int proc, ProcSpec* s) {
 }
 
 extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, int n) {
-    if (!h || (n > 0 && !t) || n < 0) return set_err(h, GPUTX_E_ARG, "bad arguments");
+    if (!h || (n > 0 && !t) || n < 0) return gtx_set_err(h, GPUTX_E_ARG, "bad arguments");
     HIP_OK(h, hipSetDevice(h->device));
     for (int i = 0; i < n; ++i) {
         const gputx_type_desc& d = t[i];
         if (d.type_id < 0 || d.type_id >= GPUTX_MAX_TYPES)
-            return set_err(h, GPUTX_E_ARG, "type_id %d out of range", d.type_id);
+            return gtx_set_err(h, GPUTX_E_ARG, "type_id %d out of range", d.type_id);
         ProcSpec ps;
-        if (!proc_spec(d.proc, &ps)) return set_err(h, GPUTX_E_TYPE, "type %d: unknown procedure %d", d.type_id, d.proc);
+        if (!proc_spec(d.proc, &ps)) return gtx_set_err(h, GPUTX_E_TYPE, "type %d: unknown procedure %d", d.type_id, d.proc);
         if (d.n_params < ps.min_params || d.n_params > GTX_MAX_PARAMS)
-            return set_err(h, GPUTX_E_TYPE, "type %d: n_params %d, procedure needs %d", d.type_id, d.n_params, ps.min_params);
+            return gtx_set_err(h, GPUTX_E_TYPE, "type %d: n_params %d, procedure needs %d", d.type_id, d.n_params, ps.min_params);
         DevType D;
         std::memset(&D, 0, sizeof D);
         D.proc = d.proc;
@@ -334,24 +298,24 @@ extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, in
         for (int r = 0; r < ps.n_roles; ++r) {
             int tid = d.table_ids[r];
             if (tid < 0 || tid >= GPUTX_MAX_TABLES || !h->tabs[tid].present)
-                return set_err(h, GPUTX_E_TYPE, "type %d role %d: table %d not loaded", d.type_id, r, tid);
+                return gtx_set_err(h, GPUTX_E_TYPE, "type %d role %d: table %d not loaded", d.type_id, r, tid);
             for (int r2 = 0; r2 < r; ++r2)
                 if (d.table_ids[r2] == tid)
-                    return set_err(h, GPUTX_E_TYPE, "type %d: table %d bound to two roles", d.type_id, tid);
+                    return gtx_set_err(h, GPUTX_E_TYPE, "type %d: table %d bound to two roles", d.type_id, tid);
             const auto& T = h->tabs[tid];
             if (!!T.d.append_only != !!ps.append[r])
-                return set_err(h, GPUTX_E_TYPE, "type %d role %d: append-only mismatch", d.type_id, r);
+                return gtx_set_err(h, GPUTX_E_TYPE, "type %d role %d: append-only mismatch", d.type_id, r);
             if (T.d.n_cols < ps.ncols[r])
-                return set_err(h, GPUTX_E_TYPE, "type %d role %d: needs %d columns", d.type_id, r, ps.ncols[r]);
+                return gtx_set_err(h, GPUTX_E_TYPE, "type %d role %d: needs %d columns", d.type_id, r, ps.ncols[r]);
             for (int c = 0; c < ps.ncols[r]; ++c)
                 if (T.d.col_dtype[c] != ps.dtype[r][c])
-                    return set_err(h, GPUTX_E_TYPE, "type %d role %d col %d: wrong dtype", d.type_id, r, c);
+                    return gtx_set_err(h, GPUTX_E_TYPE, "type %d role %d col %d: wrong dtype", d.type_id, r, c);
             for (int c = 0; c < T.d.n_cols; ++c) D.col[r][c] = T.d.col_ptr[c];
             D.rows[r] = T.d.n_rows;
             D.key_base[r] = T.key_base;
             if (T.d.root_table_id >= 0) {
                 const auto& R = h->tabs[T.d.root_table_id];
-                if (!R.present) return set_err(h, GPUTX_E_TYPE, "table %d: root table %d not loaded", tid, T.d.root_table_id);
+                if (!R.present) return gtx_set_err(h, GPUTX_E_TYPE, "table %d: root table %d not loaded", tid, T.d.root_table_id);
                 D.root_div[r] = T.d.root_div;
                 D.root_base[r] = R.key_base;
                 D.part_base[r] = R.part_base;
@@ -360,7 +324,7 @@ extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, in
                 D.root_base[r] = T.key_base;
                 D.part_base[r] = -1;
                 if (d.root_key && !ps.append[r])
-                    return set_err(h, GPUTX_E_TYPE, "type %d: root-key mode but table %d has no root", d.type_id, tid);
+                    return gtx_set_err(h, GPUTX_E_TYPE, "type %d: root-key mode but table %d has no root", d.type_id, tid);
             }
             if (ps.append[r]) {
                 if (d.proc == GPUTX_DEBIT_CREDIT || d.proc == GPUTX_NEW_ORDER) D.app_idx[app_slot] = T.app_idx;
@@ -369,7 +333,7 @@ extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, in
         }
         if (d.proc == GPUTX_NEW_ORDER || d.proc == GPUTX_PAYMENT || d.proc == GPUTX_ORDER_STATUS) {
             int64_t nw = D.rows[0], nd = D.rows[1];
-            if (nw < 1 || nd < 1) return set_err(h, GPUTX_E_TYPE, "type %d: empty warehouse/district", d.type_id);
+            if (nw < 1 || nd < 1) return gtx_set_err(h, GPUTX_E_TYPE, "type %d: empty warehouse/district", d.type_id);
             D.dims[0] = nw;
             D.dims[1] = nd / nw;
             D.dims[2] = D.rows[2] / nd;
@@ -403,10 +367,11 @@ struct Layout {
     }
 };
 
-static void plan_ws(const gputx_ctx* h, int64_t n, void* base, Ws* ws, size_t* bytes, int64_t* mcap_out) {
+static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* ws, size_t* bytes,
+                    int64_t* mcap_out) {
     Layout L;
     L.base = (char*)base;
-    const int64_t mcap = n * h->max_ops;
+    const int64_t mcap = n * (max_ops > 0 ? std::min(max_ops, h->max_ops) : h->max_ops);
     Ws w{};
     w.st = L.take<GtxState>(1);
     w.tsk[0] = L.take<uint64_t>(n); w.tsk[1] = L.take<uint64_t>(n);
@@ -439,35 +404,40 @@ static void plan_ws(const gputx_ctx* h, int64_t n, void* base, Ws* ws, size_t* b
     *mcap_out = mcap;
 }
 
-extern "C" size_t gputx_workspace_size(gputx_handle h, int64_t n) {
-    if (!h || n < 0) return 0;
+extern "C" size_t gputx_workspace_size_ops(gputx_handle h, int64_t n, int32_t max_ops) {
+    if (!h || n < 0 || max_ops < 0) return 0;
     Ws w;
     size_t b;
     int64_t mcap;
-    plan_ws(h, n, nullptr, &w, &b, &mcap);
+    plan_ws(h, n, max_ops, nullptr, &w, &b, &mcap);
     return b;
 }
 
-extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
-                                  size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
-                                  gputx_bulk_stats* stats, gputx_stream_t stream) {
-    if (!h || !b || !stats) return set_err(h, GPUTX_E_ARG, "null argument");
-    if (strategy < GPUTX_AUTO || strategy > GPUTX_KSET) return set_err(h, GPUTX_E_ARG, "bad strategy %d", strategy);
-    if (b->n < 0 || b->n > (int64_t)1 << 30) return set_err(h, GPUTX_E_ARG, "bulk size %lld", (long long)b->n);
-    if (width < 1) return set_err(h, GPUTX_E_ARG, "width must be >= 1");
+extern "C" size_t gputx_workspace_size(gputx_handle h, int64_t n) {
+    return gputx_workspace_size_ops(h, n, 0);
+}
+
+// Validate one bulk's arguments and fill its kernel arguments.
+int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace, size_t ws_bytes,
+                     int32_t* status_out, int64_t* results_out, int32_t width, gputx_bulk_stats* stats,
+                     int grid_blocks, BulkArgs* out) {
+    if (!b || !stats) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
+    if (strategy < GPUTX_AUTO || strategy > GPUTX_KSET) return gtx_set_err(h, GPUTX_E_ARG, "bad strategy %d", strategy);
+    if (b->n < 0 || b->n > (int64_t)1 << 30) return gtx_set_err(h, GPUTX_E_ARG, "bulk size %lld", (long long)b->n);
+    if (width < 1) return gtx_set_err(h, GPUTX_E_ARG, "width must be >= 1");
     if (b->n > 0 && (!b->type || !b->params || !b->ts || !status_out || !results_out || !workspace))
-        return set_err(h, GPUTX_E_ARG, "null bulk or output pointer");
-    if (b->n_params < 1 || b->n_params > GTX_MAX_PARAMS) return set_err(h, GPUTX_E_ARG, "n_params %d", b->n_params);
+        return gtx_set_err(h, GPUTX_E_ARG, "null bulk or output pointer");
+    if (b->n_params < 1 || b->n_params > GTX_MAX_PARAMS) return gtx_set_err(h, GPUTX_E_ARG, "n_params %d", b->n_params);
     bool any = false;
     for (int i = 0; i < GPUTX_MAX_TYPES; ++i) any = any || h->type_present[i];
-    if (!any) return set_err(h, GPUTX_E_STATE, "no registered types");
-    HIP_OK(h, hipSetDevice(h->device));
+    if (!any) return gtx_set_err(h, GPUTX_E_STATE, "no registered types");
     BulkArgs a{};
     size_t need;
-    plan_ws(h, b->n, workspace, &a.ws, &need, &a.mcap);
-    if (ws_bytes < need) return set_err(h, GPUTX_E_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
-    if ((uintptr_t)workspace % 256) return set_err(h, GPUTX_E_ARG, "workspace must be 256-byte aligned");
-    if (a.mcap >= ((int64_t)1 << 31) - 2) return set_err(h, GPUTX_E_CAPACITY, "too many operations for one bulk");
+    if (b->max_ops < 0) return gtx_set_err(h, GPUTX_E_ARG, "max_ops %d", b->max_ops);
+    plan_ws(h, b->n, b->max_ops, workspace, &a.ws, &need, &a.mcap);
+    if (ws_bytes < need) return gtx_set_err(h, GPUTX_E_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, need);
+    if ((uintptr_t)workspace % 256) return gtx_set_err(h, GPUTX_E_ARG, "workspace must be 256-byte aligned");
+    if (a.mcap >= ((int64_t)1 << 31) - 2) return gtx_set_err(h, GPUTX_E_CAPACITY, "too many operations for one bulk");
     a.type = b->type;
     a.params = b->params;
     a.ts = b->ts;
@@ -491,10 +461,32 @@ extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strat
     a.c_bar = h->opt.c_bar;
     a.d_bar = h->opt.d_bar;
     a.kset_narrow = h->opt.kset_narrow;
-    int per_cu = exec_resident_blocks_per_cu();
-    int max_grid = h->ncu * std::max(per_cu, 1);
-    a.grid_blocks = h->opt.grid_blocks > 0 ? std::min(h->opt.grid_blocks, max_grid) : h->ncu;
+    a.grid_blocks = grid_blocks;
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
+    *out = a;
+    return GPUTX_OK;
+}
+
+// Most persistent-grid workgroups the device can hold at once.
+static int resident_capacity(gputx_handle h) {
+    return h->ncu * std::max(exec_resident_blocks_per_cu(), 1);
+}
+
+int gtx_grid_for(gputx_handle h, int lanes) {
+    int cap = resident_capacity(h) / std::max(lanes, 1);
+    int want = h->opt.grid_blocks > 0 ? h->opt.grid_blocks : h->ncu;
+    return std::max(1, std::min(want, cap));
+}
+
+extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
+                                  size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
+                                  gputx_bulk_stats* stats, gputx_stream_t stream) {
+    if (!h) return gtx_set_err(h, GPUTX_E_ARG, "null handle");
+    HIP_OK(h, hipSetDevice(h->device));
+    BulkArgs a;
+    int rc = gtx_make_args(h, b, strategy, workspace, ws_bytes, status_out, results_out, width, stats,
+                       gtx_grid_for(h, 1), &a);
+    if (rc) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
     PhaseMarks pm;
@@ -507,13 +499,135 @@ extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strat
         launch_exec(a, s, pm);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return gtx_set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return GPUTX_OK;
+}
+
+// ---- batched form: many bulks in one HIP graph ------------------------------
+struct gputx_batch_t {
+    gputx_handle h = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int items = 0;
+    int lanes = 0;
+};
+
+extern "C" int gputx_batch_create(gputx_handle h, const gputx_batch_item* items, int n, gputx_batch* out) {
+    if (!h || !out || n < 0 || (n > 0 && !items)) return gtx_set_err(h, GPUTX_E_ARG, "bad arguments");
+    *out = nullptr;
+    HIP_OK(h, hipSetDevice(h->device));
+    int lanes = 0;
+    for (int k = 0; k < n; ++k) {
+        if (items[k].lane < 0 || items[k].lane >= 64) return gtx_set_err(h, GPUTX_E_ARG, "lane %d out of range", items[k].lane);
+        lanes = std::max(lanes, items[k].lane + 1);
+    }
+    const int grid = gtx_grid_for(h, lanes);
+    std::vector<BulkArgs> args(n);
+    for (int k = 0; k < n; ++k) {
+        const gputx_batch_item& it = items[k];
+        int rc = gtx_make_args(h, &it.bulk, it.strategy, it.workspace, it.ws_bytes, it.status_out,
+                           it.results_out, it.width, it.stats, grid, &args[k]);
+        if (rc) return rc;
+    }
+    // Two streams per lane: bulk generation (front) and execution.  A lane's
+    // executions stay in order; the front phase of a bulk only waits for the
+    // previous front phase, so it overlaps the previous bulk's execution.
+    std::vector<hipStream_t> fs(lanes), es(lanes);
+    std::vector<hipEvent_t> evs;
+    hipStream_t origin;
+    auto mkev = [&]() {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return (hipEvent_t) nullptr;
+        evs.push_back(e);
+        return e;
+    };
+    auto cleanup = [&]() {
+        for (auto e : evs) (void)hipEventDestroy(e);
+        for (int l = 0; l < lanes; ++l) {
+            if (fs[l]) (void)hipStreamDestroy(fs[l]);
+            if (es[l]) (void)hipStreamDestroy(es[l]);
+        }
+        (void)hipStreamDestroy(origin);
+    };
+    HIP_OK(h, hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+    for (int l = 0; l < lanes; ++l) {
+        fs[l] = es[l] = nullptr;
+        if (hipStreamCreateWithFlags(&fs[l], hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&es[l], hipStreamNonBlocking) != hipSuccess) {
+            cleanup();
+            return gtx_set_err(h, GPUTX_E_HIP, "stream creation failed");
+        }
+    }
+    (void)hipGetLastError();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipEvent_t fork = mkev();
+        e = hipEventRecord(fork, origin);
+        for (int l = 0; l < lanes && e == hipSuccess; ++l) {
+            e = hipStreamWaitEvent(fs[l], fork, 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(es[l], fork, 0);
+        }
+        PhaseMarks none;
+        for (int k = 0; k < n && e == hipSuccess; ++k) {
+            const int l = items[k].lane;
+            if (args[k].n == 0) {
+                launch_empty(args[k], es[l]);
+                continue;
+            }
+            launch_front(args[k], fs[l], none);
+            hipEvent_t ready = mkev();
+            e = hipEventRecord(ready, fs[l]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(es[l], ready, 0);
+            if (e == hipSuccess) launch_exec(args[k], es[l], none);
+        }
+        for (int l = 0; l < lanes && e == hipSuccess; ++l) {
+            hipEvent_t j1 = mkev(), j2 = mkev();
+            e = hipEventRecord(j1, fs[l]);
+            if (e == hipSuccess) e = hipEventRecord(j2, es[l]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(origin, j1, 0);
+            if (e == hipSuccess) e = hipStreamWaitEvent(origin, j2, 0);
+        }
+        if (e == hipSuccess) e = hipGetLastError();
+        hipError_t e2 = hipStreamEndCapture(origin, &graph);
+        if (e == hipSuccess) e = e2;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    cleanup();
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return gtx_set_err(h, GPUTX_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    gputx_batch b = new gputx_batch_t();
+    b->h = h;
+    b->graph = graph;
+    b->exec = ex;
+    b->items = n;
+    b->lanes = lanes;
+    *out = b;
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_batch_launch(gputx_batch b, gputx_stream_t stream) {
+    if (!b) return gtx_set_err(nullptr, GPUTX_E_ARG, "null batch");
+    HIP_OK(b->h, hipSetDevice(b->h->device));
+    HIP_OK(b->h, hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream)));
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_batch_destroy(gputx_batch b) {
+    if (!b) return GPUTX_E_ARG;
+    (void)hipSetDevice(b->h->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    delete b;
     return GPUTX_OK;
 }
 
 extern "C" int gputx_row_count(gputx_handle h, int32_t table_id, int64_t* out, gputx_stream_t stream) {
     if (!h || !out || table_id < 0 || table_id >= GPUTX_MAX_TABLES || !h->tabs[table_id].present)
-        return set_err(h, GPUTX_E_ARG, "bad table");
+        return gtx_set_err(h, GPUTX_E_ARG, "bad table");
     const auto& T = h->tabs[table_id];
     if (!T.d.append_only) {
         *out = T.d.n_rows;

@@ -54,7 +54,7 @@ class TypeDesc(ctypes.Structure):
 
 class BulkDesc(ctypes.Structure):
     _fields_ = [("n", c_int64), ("type", c_void_p), ("params", c_void_p), ("n_params", c_int32),
-                ("ts", c_void_p), ("ts_sorted", c_int32)]
+                ("ts", c_void_p), ("ts_sorted", c_int32), ("max_ops", c_int32)]
 
 
 class BulkStats(ctypes.Structure):
@@ -72,6 +72,34 @@ class BulkStats(ctypes.Structure):
 STATS_BYTES = ctypes.sizeof(BulkStats)
 
 
+class Trace(ctypes.Structure):
+    _fields_ = [("n", c_int64), ("arrival_ns", c_void_p), ("type", c_void_p), ("params", c_void_p),
+                ("n_params", c_int32), ("ts", c_void_p)]
+
+
+class ServeOpts(ctypes.Structure):
+    _fields_ = [("deadline_ns", c_int64), ("slots", c_int32), ("strategy", c_int32),
+                ("max_bulk", c_int64), ("hbm_budget", c_int64), ("width", c_int32),
+                ("max_ops", c_int32)]
+
+
+class ServeBulk(ctypes.Structure):
+    _fields_ = [("first", c_int64), ("count", c_int64), ("cut_ns", c_int64), ("done_ns", c_int64),
+                ("error", c_int32), ("slot", c_int32)]
+
+
+class ServeReport(ctypes.Structure):
+    _fields_ = [("n_bulks", c_int64), ("committed", c_int64), ("aborted", c_int64),
+                ("invalid", c_int64), ("elapsed_ns", c_int64), ("slots_used", c_int32),
+                ("reserved", c_int32)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("bulk", BulkDesc), ("strategy", c_int32), ("lane", c_int32),
+                ("workspace", c_void_p), ("ws_bytes", c_size_t), ("status_out", c_void_p),
+                ("results_out", c_void_p), ("width", c_int32), ("stats", c_void_p)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -86,6 +114,7 @@ def _load() -> ctypes.CDLL:
         "gputx_load_tables": (c_int32, [H, POINTER(TableDesc), c_int32]),
         "gputx_register_types": (c_int32, [H, POINTER(TypeDesc), c_int32]),
         "gputx_workspace_size": (c_size_t, [H, c_int64]),
+        "gputx_workspace_size_ops": (c_size_t, [H, c_int64, c_int32]),
         "gputx_execute_bulk": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
                                          c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
@@ -93,6 +122,11 @@ def _load() -> ctypes.CDLL:
         "gputx_phase_timing": (c_int32, [H, c_int32]),
         "gputx_phase_times": (c_int32, [H, POINTER(ctypes.c_double), c_int32, POINTER(c_int64)]),
         "gputx_phase_name": (ctypes.c_char_p, [c_int32]),
+        "gputx_batch_create": (c_int32, [H, POINTER(BatchItem), c_int32, POINTER(H)]),
+        "gputx_batch_launch": (c_int32, [H, c_void_p]),
+        "gputx_batch_destroy": (c_int32, [H]),
+        "gputx_serve": (c_int32, [H, POINTER(Trace), POINTER(ServeOpts), c_void_p, c_void_p,
+                                  POINTER(ServeBulk), c_int64, POINTER(ServeReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -104,8 +138,10 @@ def _load() -> ctypes.CDLL:
 lib = _load()
 EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_options",
            "gputx_load_tables", "gputx_register_types", "gputx_workspace_size",
+           "gputx_workspace_size_ops",
            "gputx_execute_bulk", "gputx_row_count", "gputx_last_error", "gputx_phase_timing",
-           "gputx_phase_times", "gputx_phase_name")
+           "gputx_phase_times", "gputx_phase_name", "gputx_batch_create", "gputx_batch_launch",
+           "gputx_batch_destroy", "gputx_serve")
 
 
 class GputxError(RuntimeError):
@@ -156,6 +192,10 @@ def gputx_workspace_size(h, n: int) -> int:
     return int(lib.gputx_workspace_size(h, n))
 
 
+def gputx_workspace_size_ops(h, n: int, max_ops: int) -> int:
+    return int(lib.gputx_workspace_size_ops(h, n, max_ops))
+
+
 def gputx_execute_bulk(h, bulk: BulkDesc, strategy: int, workspace: torch.Tensor,
                        status: torch.Tensor, results: torch.Tensor, stats: torch.Tensor,
                        stream: Optional[torch.cuda.Stream] = None) -> None:
@@ -190,6 +230,35 @@ def gputx_phase_times(h) -> tuple:
     if k < 0:
         _check(h, k)
     return {gputx_phase_name(i): ms[i] for i in range(k)}, nb.value
+
+
+def gputx_batch_create(h, items: Sequence[BatchItem]) -> c_void_p:
+    arr = (BatchItem * len(items))(*items)
+    b = c_void_p()
+    _check(h, lib.gputx_batch_create(h, arr, len(items), ctypes.byref(b)))
+    return b
+
+
+def gputx_batch_launch(h, b, stream: Optional[torch.cuda.Stream] = None) -> None:
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(h, lib.gputx_batch_launch(b, s))
+
+
+def gputx_batch_destroy(h, b) -> None:
+    _check(h, lib.gputx_batch_destroy(b))
+
+
+def gputx_serve(h, trace: Trace, opts: ServeOpts, status: torch.Tensor, results: torch.Tensor,
+                bulk_capacity: int):
+    """Serve a trace; status / results are page-locked host tensors.  Returns
+    (report, numpy structured array of per-bulk records)."""
+    recs = (ServeBulk * max(bulk_capacity, 1))()
+    rep = ServeReport()
+    _check(h, lib.gputx_serve(h, ctypes.byref(trace), ctypes.byref(opts), status.data_ptr(),
+                              results.data_ptr(), recs, bulk_capacity, ctypes.byref(rep)))
+    n = min(rep.n_bulks, bulk_capacity)
+    arr = np.ctypeslib.as_array(recs)[:n].copy() if n else np.zeros(0)
+    return rep, arr
 
 
 def stats_from(t: torch.Tensor) -> BulkStats:
@@ -275,8 +344,9 @@ class Engine:
                     ts=torch.from_numpy(np.ascontiguousarray(bulk.ts)).to(self.device))
 
     @staticmethod
-    def bulk_desc(dev: dict, ts_sorted: bool) -> BulkDesc:
+    def bulk_desc(dev: dict, ts_sorted: bool, max_ops: int = 0) -> BulkDesc:
         b = BulkDesc()
+        b.max_ops = max_ops
         b.n = dev["type"].shape[0]
         b.type = dev["type"].data_ptr()
         b.params = dev["params"].data_ptr()
@@ -301,6 +371,11 @@ class Engine:
                            stats, stream)
         return status, results, stats
 
+    def batch(self, jobs: Sequence[dict]) -> "Batch":
+        """jobs: dicts with dev (device bulk), lane, strategy, width and
+        optional ts_sorted / max_ops."""
+        return Batch(self, jobs)
+
     def row_count(self, name: str) -> int:
         return gputx_row_count(self.h, self.table_id[name])
 
@@ -311,6 +386,57 @@ class Engine:
         if self.h:
             gputx_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many bulks captured into one HIP graph (``gputx_batch_create``); every
+    job gets its own workspace and output buffers."""
+
+    def __init__(self, eng: Engine, jobs: Sequence[dict]):
+        self.eng = eng
+        self.jobs = list(jobs)
+        self.outputs = []
+        items = []
+        for j in self.jobs:
+            dev = j["dev"]
+            n = int(dev["type"].shape[0])
+            width = int(j["width"])
+            max_ops = int(j.get("max_ops", 0))
+            ws = torch.empty(gputx_workspace_size_ops(eng.h, max(n, 1), max_ops), dtype=torch.uint8,
+                             device=eng.device)
+            st = torch.empty(max(n, 1), dtype=torch.int32, device=eng.device)
+            res = torch.empty((max(n, 1), width), dtype=torch.int64, device=eng.device)
+            stats = torch.empty(STATS_BYTES, dtype=torch.uint8, device=eng.device)
+            it = BatchItem()
+            it.bulk = Engine.bulk_desc(dev, bool(j.get("ts_sorted", True)), max_ops)
+            it.strategy = int(j["strategy"])
+            it.lane = int(j["lane"])
+            it.workspace = ws.data_ptr()
+            it.ws_bytes = ws.numel()
+            it.status_out = st.data_ptr()
+            it.results_out = res.data_ptr()
+            it.width = width
+            it.stats = stats.data_ptr()
+            items.append(it)
+            self.outputs.append(dict(ws=ws, status=st, results=res, stats=stats, n=n))
+        self.b = gputx_batch_create(eng.h, items)
+
+    def launch(self, stream=None) -> None:
+        gputx_batch_launch(self.eng.h, self.b, stream)
+
+    def stats(self, k: int) -> BulkStats:
+        return stats_from(self.outputs[k]["stats"])
+
+    def close(self) -> None:
+        if self.b:
+            gputx_batch_destroy(self.eng.h, self.b)
+            self.b = None
 
     def __del__(self):
         try:

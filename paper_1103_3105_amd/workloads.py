@@ -24,6 +24,7 @@ Layouts
 from __future__ import annotations
 
 import dataclasses
+import functools
 import math
 from typing import Dict, List, Optional, Sequence
 
@@ -123,12 +124,18 @@ def zipf_ids(rng: np.random.Generator, n_keys: int, theta: float, size: int) -> 
     """
     if theta == 0.0:
         return rng.integers(0, n_keys, size=size, dtype=np.int64)
-    w = np.arange(1, n_keys + 1, dtype=np.float64) ** (-theta)
-    cdf = np.cumsum(w)
-    cdf /= cdf[-1]
+    cdf = _zipf_cdf(n_keys, theta)
     u = rng.random(size)
     ids = np.searchsorted(cdf, u, side="right").astype(np.int64)
     return np.minimum(ids, n_keys - 1)
+
+
+@functools.lru_cache(maxsize=8)
+def _zipf_cdf(n_keys: int, theta: float) -> np.ndarray:
+    w = np.arange(1, n_keys + 1, dtype=np.float64) ** (-theta)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    return cdf
 
 
 def _col(n: int, dt: str) -> np.ndarray:
