@@ -27,6 +27,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "committed txns/sec on 1 MI355X, batched vs plain bulk; p50/p99 commit latency"
 HBM_PEAK_GBS = 8000.0
+COPY_CALIB_BYTES = 256 << 20   # a plain device copy of this size calibrates the PMC byte counters
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources the executor kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_exec.hip", "procs.h", "common.h", "engine.h"):
+        with open(os.path.join(ROOT, "paper_1103_3105_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None
+    when the kernel's sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
 
 
 def log(*a):
@@ -97,19 +122,26 @@ def oracle_baseline(w, bulk, width, budget_s=12.0):
 
 def bench_batch(args):
     """Config-4 form: 512 uneven bulks over two databases, batched (one graph
-    launch) vs plain (one execute + wait per bulk)."""
+    launch) vs plain (one execute + wait per bulk), with Algorithm 1's
+    thresholds calibrated on a sample of the bulks first."""
     import torch
-    import oracle  # noqa: F401
-    from paper_1103_3105_amd import batching, gputx
-    reps = args.warmup + args.steps + 2
-    log(f"[bench] generating the 512-bulk batch workload")
-    bw = batching.config4(n_bulks=args.bulks, repeats=reps)
+    from paper_1103_3105_amd import autotune, batching, gputx
+    log("[bench] generating the 512-bulk batch workload")
+    bw = batching.config4(n_bulks=args.bulks)
     n_txn = bw.n_txns
+    # calibration on a spread of sample bulks (scratch copy of the database)
+    order = sorted(range(len(bw.jobs)), key=lambda k: bw.jobs[k][1].n)
+    picks = [order[int(q * (len(order) - 1))] for q in np.linspace(0.05, 0.75, 12)]
+    samples = [(bw.jobs[k][1], batching.WIDTH[bw.jobs[k][0]], batching.MAX_OPS[bw.jobs[k][0]])
+               for k in picks]
+    tuned = autotune.calibrate(bw.tables, bw.types, samples, log=log)
+    log(f"[bench] calibrated: w0_bar={tuned['w0_bar']} d_bar={tuned['d_bar']} "
+        f"narrow={tuned['kset_narrow']}")
     eng = gputx.Engine(bw.tables, bw.types)
-    jobs = batching.device_jobs(eng, bw, gputx.STRATEGY[args.strategy])
+    eng.set_options(w0_bar=int(min(tuned["w0_bar"], 2**62)), c_bar=int(tuned["c_bar"]),
+                    d_bar=int(min(tuned["d_bar"], 2**62)), kset_narrow=int(tuned["kset_narrow"]))
+    jobs = batching.device_jobs(eng, bw, gputx.AUTO)
     o_tabs = {k: v.copy() for k, v in bw.tables.items()}
-    # plain form once, with parity against the oracle
-    gputx.gputx_phase_timing(eng.h, True)
     outs = [dict(status=torch.empty(max(b.n, 1), dtype=torch.int32, device=eng.device),
                  results=torch.empty((max(b.n, 1), batching.WIDTH[db]), dtype=torch.int64,
                                      device=eng.device),
@@ -119,38 +151,113 @@ def bench_batch(args):
     t0 = time.perf_counter()
     lat = batching.run_plain(eng, jobs, outs)
     plain_s = time.perf_counter() - t0
-    phases, nb = gputx.gputx_phase_times(eng.h)
-    gputx.gputx_phase_timing(eng.h, False)
     want = batching.oracle_replay(bw, o_tabs)
     parity = all(np.array_equal(outs[k]["status"].cpu().numpy()[:b.n], want[k][0]) and
                  np.array_equal(outs[k]["results"].cpu().numpy()[:b.n], want[k][1])
                  for k, (db, b) in enumerate(bw.jobs))
     committed_plain = sum(gputx.stats_from(o["stats"]).committed for o in outs)
-    log(f"[bench] plain: {plain_s:.3f} s, parity={parity}")
+    chosen = [gputx.STRATEGY_NAME[gputx.stats_from(o["stats"]).chosen] for o in outs]
+    log(f"[bench] plain: {plain_s:.3f} s, parity={parity}, chosen={ {c: chosen.count(c) for c in set(chosen)} }")
     batch = eng.batch(jobs)
-    for _ in range(args.warmup):
+    per = []
+    for k in range(args.warmup + args.steps):
+        eng.truncate_appends()   # the replay appends the same rows again
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         batch.launch()
-    torch.cuda.synchronize()
-    # parity of the batched form on its first timed replay (outside timing)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    ev[0].record()
-    for k in range(args.steps):
-        batch.launch()
-        ev[k + 1].record()
-    torch.cuda.synchronize()
-    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+        e1.record()
+        torch.cuda.synchronize()
+        if k >= args.warmup:
+            per.append(e0.elapsed_time(e1))
+    per = np.array(per)
     committed = sum(batch.stats(k).committed for k in range(len(bw.jobs)))
     errors = sum(batch.stats(k).error != 0 for k in range(len(bw.jobs)))
-    batched_value = committed * args.steps / (per.sum() / 1e3)
+    batched_value = committed / (per.mean() / 1e3)
     plain_value = committed_plain / plain_s
     log(f"[bench] batched: {per.mean():.1f} ms/launch, {batched_value / 1e6:.2f}M txn/s; "
         f"plain {plain_value / 1e6:.2f}M txn/s")
-    return dict(batched_value=batched_value, plain_value=plain_value, n_txns=n_txn,
-                n_bulks=len(bw.jobs), parity=bool(parity) and errors == 0,
-                ms_per_launch=float(per.mean()),
-                plain_bulk_latency_ms={"p50": float(np.percentile(lat, 50) * 1e3),
-                                       "p99": float(np.percentile(lat, 99) * 1e3)},
-                phases_ms_total_plain={k: round(v, 3) for k, v in phases.items()})
+    batch.close()
+    eng.close()
+    return dict(workload=f"{len(bw.jobs)} bulks, log-uniform 256..262144 txns, bank (theta in "
+                         f"{{0,0.8,0.99}}) or order-entry by coin flip; two lanes",
+                n_txns=n_txn, batched_txn_per_s=round(batched_value, 1),
+                plain_txn_per_s=round(plain_value, 1), speedup=round(batched_value / plain_value, 3),
+                ms_per_launch=round(float(per.mean()), 3), parity_vs_oracle=bool(parity) and errors == 0,
+                plain_bulk_latency_ms={"p50": round(float(np.percentile(lat, 50) * 1e3), 4),
+                                       "p99": round(float(np.percentile(lat, 99) * 1e3), 4)},
+                calibrated={k: (int(v) if isinstance(v, (int, np.integer)) else v)
+                            for k, v in tuned.items() if k != "samples"},
+                chosen={c: chosen.count(c) for c in set(chosen)})
+
+
+def bench_serve(args):
+    """Served form: Poisson arrivals over 10M subscribers, a bulk every deadline."""
+    from paper_1103_3105_amd import gputx, serving, workloads as wl
+    import oracle
+    log(f"[bench] generating subscriber tables ({args.n_sub}) and the arrival trace")
+    tabs = wl.sub_tables(wl.rng_for(5, 0), args.n_sub)
+    eng = gputx.Engine(tabs, wl.sub_types(), part_size=128)
+    points = []
+    parity = None
+    try:
+        for k, (rate, dl) in enumerate(args.serve_points):
+            trace = serving.make_trace(rate, args.serve_seconds, args.n_sub, seed=int(rate) % 97)
+            res = serving.serve(eng, trace, dl, slots=args.slots, width=14, max_bulk=1 << 17)
+            pc = res.percentiles()
+            if k == 0:  # first point starts from the initial tables: check it against the oracle
+                o_tabs = {kk: v.copy() for kk, v in tabs.items()}
+                rc, o_st, o_res = oracle.run_serial(o_tabs, wl.sub_types(), trace.type, trace.params,
+                                                    trace.ts, 14)
+                parity = bool(rc == 0 and np.array_equal(res.status, o_st)
+                              and np.array_equal(res.results, o_res))
+                log(f"[bench] served parity vs oracle (first point): {parity}")
+            points.append(dict(rate_per_s=rate, deadline_us=dl, txns=trace.n,
+                               throughput_txn_per_s=round(res.throughput, 1),
+                               p50_us=round(pc["p50_us"], 1), p99_us=round(pc["p99_us"], 1),
+                               bulks=int(res.bulks.shape[0]),
+                               mean_bulk=round(float(res.bulks["count"].mean()), 1),
+                               slots=res.slots_used))
+            log(f"[bench] serve rate={rate:.0e}/s deadline={dl}us: {res.throughput / 1e6:.2f}M txn/s "
+                f"p50={pc['p50_us']:.0f}us p99={pc['p99_us']:.0f}us bulks={res.bulks.shape[0]}")
+    finally:
+        eng.close()
+    return dict(workload=f"subscriber: {args.n_sub} subscribers x 12 call-forwarding slots, "
+                         f"mix 60/20/8/8/2/2, sid Zipf 0.8, Poisson arrivals, "
+                         f"{args.serve_seconds}s per point", points=points,
+                parity_vs_oracle=parity)
+
+
+def bench_grid(args):
+    """TPL, PART and K-SET on the same scaled-bank bulks (n x theta)."""
+    import torch
+    from paper_1103_3105_amd import gputx, workloads as wl
+    out = []
+    for theta in (0.0, 0.8, 0.99):
+        for n in args.grid_n:
+            w = wl.config2(n=n, theta=theta, history_capacity=n)
+            eng = gputx.Engine(w.tables, w.types)
+            dev = eng.bulk_to_device(w.bulks[0])
+            row = dict(n=n, theta=theta)
+            for strat in ("TPL", "PART", "KSET"):
+                eng.truncate_appends()
+                st, res, stats = eng.execute(dev, gputx.STRATEGY[strat], 3, ts_sorted=True)
+                torch.cuda.synchronize()
+                eng.truncate_appends()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                eng.execute(dev, gputx.STRATEGY[strat], 3, ts_sorted=True, status=st, results=res, stats=stats)
+                b.record()
+                torch.cuda.synchronize()
+                s = gputx.stats_from(stats)
+                ms = a.elapsed_time(b)
+                row[strat] = dict(ms=round(ms, 3), txn_per_s=round(s.committed / (ms / 1e3)))
+                row["depth"], row["w0"] = int(s.depth), int(s.w0)
+            log(f"[bench] grid n={n} theta={theta}: " + ", ".join(
+                f"{k}={row[k]['ms']:.2f}ms" for k in ("TPL", "PART", "KSET")))
+            out.append(row)
+            eng.close()
+    return out
 
 
 def main():
@@ -167,6 +274,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
+    ap.add_argument("--sections", default="grid,batch,serve",
+                    help="extra sections after the headline bulk: grid,batch,serve (or none)")
+    ap.add_argument("--grid-n", type=lambda v: [int(x) for x in v.split(",")],
+                    default=[1 << 16, 1 << 18, 1 << 20])
+    ap.add_argument("--serve-points", type=lambda v: [(float(p.split(':')[0]), float(p.split(':')[1]))
+                                                      for p in v.split(",")],
+                    default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 200.0)],
+                    help="rate:deadline_us,...")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -180,6 +297,7 @@ def main():
     if args.batch_only:
         print(json.dumps(bench_batch(args)), flush=True)
         return
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
 
     log(f"[bench] generating {args.workload} n={args.n}")
     w, wname, width = make_workload(args)
@@ -216,6 +334,14 @@ def main():
         step(args.strategy)
     torch.cuda.synchronize()
 
+    # a plain copy of known size (outside timing): PMC byte counters of the
+    # profiled runs are scaled by what they read for it
+    calib_src = torch.empty(COPY_CALIB_BYTES // 8, dtype=torch.int64, device=eng.device)
+    calib_dst = torch.empty_like(calib_src)
+    calib_dst.copy_(calib_src)
+    torch.cuda.synchronize()
+    del calib_src, calib_dst
+
     gputx.gputx_phase_timing(eng.h, True)
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
@@ -242,8 +368,11 @@ def main():
     dom = max((k for k in phases if k in pb), key=lambda k: phases[k])
     dom_ms = phases[dom] / max(nb, 1)
     achieved = pb[dom] / (dom_ms / 1e3) / 1e9 if dom_ms > 0 else 0.0
+    kernel_of = {"part": "k_part_wave", "tpl": "k_tpl", "kset": "k_kset", "rank": "k_rank_down",
+                 "op_sort": "k_sort_pass", "prepare": "k_prepare", "emit": "k_emit"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 6),
+                "traffic": measured_traffic(kernel_of.get(dom, dom)), "kernel": dom,
                 "bytes_per_launch": pb[dom], "ms_per_launch": round(dom_ms, 4)}
 
     # PCIe-inclusive rate: bulk H2D + status/results D2H around each bulk
@@ -317,6 +446,19 @@ def main():
     if extra:
         out["strategies"] = extra
     eng.close()
+    del eng, dev, status, results
+    torch.cuda.empty_cache()
+    if "grid" in sections:
+        out["strategy_grid"] = bench_grid(args)
+    if "batch" in sections:
+        out["batched_vs_plain"] = bench_batch(args)
+    if "serve" in sections:
+        sv = bench_serve(args)
+        out["served"] = sv
+        if sv["points"]:
+            best = max(sv["points"], key=lambda p: p["throughput_txn_per_s"])
+            out["latency_ms"]["served_p50"] = round(best["p50_us"] / 1e3, 4)
+            out["latency_ms"]["served_p99"] = round(best["p99_us"] / 1e3, 4)
     print(json.dumps(out), flush=True)
 
 

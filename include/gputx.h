@@ -313,6 +313,7 @@ typedef struct {
     int64_t elapsed_ns;         /* start .. last results back                       */
     int32_t slots_used;         /* slots the HBM budget allowed                     */
     int32_t reserved;
+    int64_t slot_bytes;         /* device bytes one slot takes                      */
 } gputx_serve_report;
 
 /* Serve a whole trace.  status_out [n] / results_out [n][width] are host
@@ -345,6 +346,11 @@ int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n_bulks);
 
 /* Name of phase i (static storage), or NULL past the last phase. */
 const char* gputx_phase_name(int i);
+
+/* Set the row count of an append-only table (0 <= n <= capacity), e.g. to
+ * truncate it after its rows were archived; ordered on the stream and
+ * synchronised.  Errors: GPUTX_E_ARG for a table that is not append-only. */
+int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, gputx_stream_t stream);
 
 /* Message of the last error on this context (static storage, never NULL). */
 const char* gputx_last_error(gputx_handle h);

@@ -24,7 +24,8 @@ struct __attribute__((aligned(32))) OpInfo {
     int32_t shi;
     int32_t rank;  // the paper's rank (Section 4.2 step 3)
     int32_t in;    // in-edges the op contributes to its transaction (K-SET)
-    int32_t pad0, pad1;
+    int32_t s0;    // transaction of the first successor op (-1: none)
+    int32_t s0ty;  // its type
 };
 
 // Device workspace of one bulk (carved from the caller's workspace).

@@ -165,16 +165,34 @@ __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* 
     const bool live = idx < cnt[t];
     int32_t s = 0;
     int32_t q = 0;
+    constexpr int kPre = 4;  // op records read before the procedure runs
+    OpInfo pre[kPre];
+    int64_t o0 = 0, o1 = 0;
     if (live) {
         q = F[reg_off[t] + idx];
+        o0 = op_begin(a, q);
+        o1 = op_end(a, q);
+#pragma unroll
+        for (int k = 0; k < kPre; ++k)
+            if (o0 + k < o1) pre[k] = a.ws.op_info[o0 + k];
         s = run_at(a, q, t);
     }
     count_status(a.ws.st, live, s);
     if (live) {
-        const int64_t o1 = op_end(a, q);
-        for (int64_t o = op_begin(a, q); o < o1; ++o) {
-            const OpInfo inf = a.ws.op_info[o];
-            for (int32_t j = inf.slo; j < inf.shi; ++j) {
+        for (int64_t o = o0; o < o1; ++o) {
+            OpInfo inf;
+            if (o - o0 < kPre) {
+#pragma unroll
+                for (int k = 0; k < kPre; ++k)
+                    if (o - o0 == k) inf = pre[k];
+            } else {
+                inf = a.ws.op_info[o];
+            }
+            if (inf.slo < inf.shi && atomicSub(&a.ws.indeg[inf.s0], 1) == 1) {
+                const int slot = atomicAdd(&fill_next[inf.s0ty], 1);
+                F_next[reg_off[inf.s0ty] + slot] = inf.s0;
+            }
+            for (int32_t j = inf.slo + 1; j < inf.shi; ++j) {  // rest of a read run
                 const int32_t q2 = a.ws.srt_txn[j];
                 if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
             }
@@ -362,6 +380,19 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
             o1 = op_end(a, p);
             load_txn(a, p, t, x);  // signatures are immutable: load before waiting
         }
+        // lock groups and targets of the first ops, kept in registers while waiting
+        constexpr int kPre = 4;
+        int32_t pg[kPre], pt[kPre];
+#pragma unroll
+        for (int k = 0; k < kPre; ++k) {
+            pg[k] = 0;
+            pt[k] = 0;
+            if (!done && o0 + k < o1) {
+                const OpInfo inf = a.ws.op_info[o0 + k];
+                pg[k] = inf.grp;
+                pt[k] = inf.tgt;
+            }
+        }
         uint64_t t0 = 0;
         int32_t s = 0;
         bool ran = false;
@@ -369,7 +400,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
             bool ready = false;
             if (!done) {
                 ready = true;
-                for (int64_t o = o0; o < o1; ++o) {
+#pragma unroll
+                for (int k = 0; k < kPre; ++k)
+                    if (o0 + k < o1) ready = ready && ld_relaxed(&a.ws.grp_cnt[pg[k]]) >= pt[k];
+                for (int64_t o = o0 + kPre; o < o1; ++o) {
                     const OpInfo inf = a.ws.op_info[o];
                     ready = ready && ld_relaxed(&a.ws.grp_cnt[inf.grp]) >= inf.tgt;
                 }
@@ -382,7 +416,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
                 }
                 fence_release();  // publish this transaction's writes
                 if (ready) {
-                    for (int64_t o = o0; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_info[o].grp], 1);
+#pragma unroll
+                    for (int k = 0; k < kPre; ++k)
+                        if (o0 + k < o1) atomicAdd(&a.ws.grp_cnt[pg[k]], 1);
+                    for (int64_t o = o0 + kPre; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_info[o].grp], 1);
                     done = true;
                 }
                 t0 = 0;
@@ -478,7 +515,7 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
 #pragma unroll
         for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = (r < ynp && r < npb) ? c.prm[r * 64 + k] : 0;
         int64_t res[GTX_MAX_RESULTS];
-        DirectAcc acc;
+        NoAppendAcc acc;  // the owning lanes already wrote the appended rows
         const int32_t s = P ? txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res)
                             : txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
         c.st[k] = s;
@@ -496,9 +533,9 @@ size_t part_wave_lds(const BulkArgs& a) {
 
 // One wave per partition, still one serial thread of control (Section 5.2).
 // For each chunk of 64 of the partition's transactions the lanes load the
-// signatures into LDS and touch every row their transaction will use; lane 0
-// then runs the 64 in order; finally the owning lanes write statuses and
-// results.
+// signatures into LDS, touch every row their transaction will use and write
+// its appended rows; lane 0 then runs the 64 in order (shared state only);
+// finally the owning lanes write statuses and results.
 __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
@@ -540,6 +577,11 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
             c.t[lane] = t;
             c.np[lane] = x.np;
             sink ^= txn_touch(a.types[t], x.prm);
+            {   // insert-buffer rows (Section 3.2), written in parallel by their owners
+                AppendOnlyAcc ap;
+                int64_t unused[GTX_MAX_RESULTS];
+                (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+            }
             i = x.i;
         }
         __syncthreads();

@@ -468,7 +468,12 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
         inf.shi = shi;
         inf.rank = rank;
         inf.in = in_c;
-        inf.pad0 = inf.pad1 = 0;
+        inf.s0 = -1;
+        inf.s0ty = -1;
+        if (slo < shi) {  // first successor's transaction, so K-SET needs no gather
+            inf.s0 = a.ws.op_txn[in.val[slo] >> 1];
+            inf.s0ty = a.ws.tty[inf.s0];
+        }
         a.ws.op_info[o] = inf;
         if (i == gs) a.ws.grp_cnt[g] = 0;
     }

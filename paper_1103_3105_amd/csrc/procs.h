@@ -230,6 +230,28 @@ struct DirectAcc {
     __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
 };
 
+// In every procedure below, whether and what a transaction appends depends
+// only on its signature (appending procedures never abort, and appended
+// values come from parameters and the timestamp).  So appends can be split
+// from the rest of a transaction: AppendOnlyAcc performs only the appends
+// (reads yield 0 and touch no memory), NoAppendAcc everything else.
+struct AppendOnlyAcc {
+    template <class V>
+    __device__ __forceinline__ V ld(GTX_GLOBAL V*) { return V(0); }
+    template <class V>
+    __device__ __forceinline__ void st(GTX_GLOBAL V*, V) {}
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
+};
+struct NoAppendAcc {
+    template <class V>
+    __device__ __forceinline__ V ld(GTX_GLOBAL V* p) { return *p; }
+    template <class V>
+    __device__ __forceinline__ void st(GTX_GLOBAL V* p, V v) { *p = v; }
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}
+};
+
 // Parameters procedure P reads (0: any procedure, the widest signature).
 __host__ __device__ constexpr int proc_params(int proc) {
     return proc == GPUTX_DEBIT_CREDIT ? 4 : proc == GPUTX_NEW_ORDER ? 34 : proc == GPUTX_PAYMENT ? 4

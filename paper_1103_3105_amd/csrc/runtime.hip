@@ -640,6 +640,20 @@ extern "C" int gputx_row_count(gputx_handle h, int32_t table_id, int64_t* out, g
     return GPUTX_OK;
 }
 
+extern "C" int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, gputx_stream_t stream) {
+    if (!h || table_id < 0 || table_id >= GPUTX_MAX_TABLES || !h->tabs[table_id].present)
+        return gtx_set_err(h, GPUTX_E_ARG, "bad table");
+    const auto& T = h->tabs[table_id];
+    if (!T.d.append_only || n < 0 || n > T.d.capacity)
+        return gtx_set_err(h, GPUTX_E_ARG, "table %d: not append-only or %lld out of range", table_id, (long long)n);
+    HIP_OK(h, hipSetDevice(h->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int64_t v = n;
+    HIP_OK(h, hipMemcpyAsync(h->d_rowcount + T.app_idx, &v, 8, hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipStreamSynchronize(s));
+    return GPUTX_OK;
+}
+
 extern "C" const char* gputx_last_error(gputx_handle h) {
     if (!h) return g_err.c_str();
     return h->err.c_str();

@@ -95,6 +95,7 @@ extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_se
     const size_t off_results = off_status + up256((size_t)maxb * 4);
     const size_t off_stats = off_results + up256((size_t)maxb * 8 * W);
     const size_t slot_bytes = off_stats + up256(sizeof(gputx_bulk_stats));
+    rep->slot_bytes = (int64_t)slot_bytes;
     int nslots = o->slots;
     if (o->hbm_budget > 0) nslots = (int)std::min<int64_t>(nslots, o->hbm_budget / (int64_t)slot_bytes);
     if (nslots < 1) return gtx_set_err(h, GPUTX_E_CAPACITY, "HBM budget below one slot (%zu bytes)", slot_bytes);

@@ -91,7 +91,7 @@ class ServeBulk(ctypes.Structure):
 class ServeReport(ctypes.Structure):
     _fields_ = [("n_bulks", c_int64), ("committed", c_int64), ("aborted", c_int64),
                 ("invalid", c_int64), ("elapsed_ns", c_int64), ("slots_used", c_int32),
-                ("reserved", c_int32)]
+                ("reserved", c_int32), ("slot_bytes", c_int64)]
 
 
 class BatchItem(ctypes.Structure):
@@ -118,6 +118,7 @@ def _load() -> ctypes.CDLL:
         "gputx_execute_bulk": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
                                          c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
+        "gputx_set_row_count": (c_int32, [H, c_int32, c_int64, c_void_p]),
         "gputx_last_error": (ctypes.c_char_p, [H]),
         "gputx_phase_timing": (c_int32, [H, c_int32]),
         "gputx_phase_times": (c_int32, [H, POINTER(ctypes.c_double), c_int32, POINTER(c_int64)]),
@@ -139,7 +140,7 @@ lib = _load()
 EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_options",
            "gputx_load_tables", "gputx_register_types", "gputx_workspace_size",
            "gputx_workspace_size_ops",
-           "gputx_execute_bulk", "gputx_row_count", "gputx_last_error", "gputx_phase_timing",
+           "gputx_execute_bulk", "gputx_row_count", "gputx_set_row_count", "gputx_last_error", "gputx_phase_timing",
            "gputx_phase_times", "gputx_phase_name", "gputx_batch_create", "gputx_batch_launch",
            "gputx_batch_destroy", "gputx_serve")
 
@@ -211,6 +212,11 @@ def gputx_row_count(h, table_id: int, stream: Optional[torch.cuda.Stream] = None
     s = (stream or torch.cuda.current_stream()).cuda_stream
     _check(h, lib.gputx_row_count(h, table_id, ctypes.byref(out), s))
     return out.value
+
+
+def gputx_set_row_count(h, table_id: int, n: int, stream: Optional[torch.cuda.Stream] = None) -> None:
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(h, lib.gputx_set_row_count(h, table_id, n, s))
 
 
 def gputx_phase_timing(h, enable: bool) -> None:
@@ -288,6 +294,7 @@ class Engine:
         self.h = gputx_create(device, opts)
         self.table_id: Dict[str, int] = {}
         self.cols: Dict[str, list] = {}
+        self.append_tables = {name: bool(t.append) for name, t in tables.items()}
         for i, name in enumerate(tables):
             self.table_id[name] = i
         descs = []
@@ -378,6 +385,12 @@ class Engine:
 
     def row_count(self, name: str) -> int:
         return gputx_row_count(self.h, self.table_id[name])
+
+    def truncate_appends(self, n: int = 0) -> None:
+        """Set every append-only table's row count to n (default: empty)."""
+        for name, tid in self.table_id.items():
+            if self.append_tables.get(name):
+                gputx_set_row_count(self.h, tid, n)
 
     def table_host(self, name: str) -> list:
         return [c.cpu().numpy() for c in self.cols[name]]

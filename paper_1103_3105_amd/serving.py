@@ -48,6 +48,7 @@ class ServeResult:
     invalid: int
     elapsed_ns: int
     slots_used: int
+    slot_bytes: int
     latency_ns: np.ndarray     # per transaction
 
     def percentiles(self):
@@ -100,4 +101,4 @@ def serve(eng, trace: Trace, deadline_us: float, slots: int = 4, width: int = 14
         f, c = int(r["first"]), int(r["count"])
         lat[f:f + c] = int(r["done_ns"]) - arrival[f:f + c]
     return ServeResult(st, res, recs, rep.committed, rep.aborted, rep.invalid, rep.elapsed_ns,
-                       rep.slots_used, lat)
+                       rep.slots_used, rep.slot_bytes, lat)

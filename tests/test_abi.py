@@ -33,10 +33,14 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_1103_3105_amd import gputx
     prog = tmp_path / "layout.c"
     prog.write_text('#include <stdio.h>\n#include "gputx.h"\n#include <stddef.h>\nint main(void){\n'
-                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gputx_options), '
+                    'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", '
+                    'sizeof(gputx_options), '
                     'sizeof(gputx_table_desc), sizeof(gputx_type_desc), sizeof(gputx_bulk), '
                     'sizeof(gputx_bulk_stats), offsetof(gputx_table_desc, col_ptr), '
-                    'offsetof(gputx_bulk, ts), offsetof(gputx_bulk_stats, appended));\n'
+                    'offsetof(gputx_bulk, ts), offsetof(gputx_bulk_stats, appended), '
+                    'sizeof(gputx_batch_item), offsetof(gputx_batch_item, stats), '
+                    'sizeof(gputx_trace), sizeof(gputx_serve_opts), sizeof(gputx_serve_bulk), '
+                    'sizeof(gputx_serve_report));\n'
                     'return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(prog), "-o", str(exe)])
@@ -44,7 +48,10 @@ def test_struct_layout_matches_header(tmp_path):
     want = [ctypes.sizeof(gputx.Options), ctypes.sizeof(gputx.TableDesc),
             ctypes.sizeof(gputx.TypeDesc), ctypes.sizeof(gputx.BulkDesc),
             ctypes.sizeof(gputx.BulkStats), gputx.TableDesc.col_ptr.offset,
-            gputx.BulkDesc.ts.offset, gputx.BulkStats.appended.offset]
+            gputx.BulkDesc.ts.offset, gputx.BulkStats.appended.offset,
+            ctypes.sizeof(gputx.BatchItem), gputx.BatchItem.stats.offset,
+            ctypes.sizeof(gputx.Trace), ctypes.sizeof(gputx.ServeOpts),
+            ctypes.sizeof(gputx.ServeBulk), ctypes.sizeof(gputx.ServeReport)]
     assert got == want
 
 

@@ -82,9 +82,11 @@ def test_hbm_budget_limits_slots():
     else:
         raise AssertionError("a budget below one slot must be refused")
     try:
-        ws = gputx.gputx_workspace_size_ops(eng.h, 1024, 1)
-        res = serving.serve(eng, trace, 200, slots=8, max_bulk=1024, hbm_budget=2 * ws + 4 * 2**20)
-        assert 1 <= res.slots_used <= 2
+        first = serving.serve(eng, trace, 200, slots=8, max_bulk=1024)
+        assert first.slots_used == 8 and first.slot_bytes > 0
+        res = serving.serve(eng, trace, 200, slots=8, max_bulk=1024,
+                            hbm_budget=int(2.5 * first.slot_bytes))
+        assert res.slots_used == 2
         _check_records(res, trace, 200_000, 1024)
     finally:
         eng.close()
