@@ -272,6 +272,8 @@ def main():
     ap.add_argument("--strategy", default="AUTO", choices=["AUTO", "TPL", "PART", "KSET"])
     ap.add_argument("--compare", action="store_true", help="also time every strategy")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--part-pipeline", type=int, default=1, choices=[0, 1],
+                    help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
     ap.add_argument("--sections", default="grid,batch,serve",
@@ -302,7 +304,8 @@ def main():
     log(f"[bench] generating {args.workload} n={args.n}")
     w, wname, width = make_workload(args)
     bulk = w.bulks[0]
-    eng = gputx.Engine(w.tables, w.types, part_size=(128 if args.workload == "sub" else 1))
+    eng = gputx.Engine(w.tables, w.types, part_size=(128 if args.workload == "sub" else 1),
+                       part_pipeline=args.part_pipeline)
     dev = eng.bulk_to_device(bulk)
     n = bulk.n
     status = torch.empty(n, dtype=torch.int32, device=eng.device)

@@ -52,7 +52,8 @@ enum {
     GPUTX_E_HIP = -5,       /* a HIP runtime call failed                         */
     GPUTX_E_STATE = -6,     /* call out of order (e.g. execute before load)      */
     GPUTX_E_DEADLOCK = -7,  /* a bounded device wait expired (watchdog)          */
-    GPUTX_E_UNSORTED = -8   /* bulk flagged ts_sorted but timestamps not ascending */
+    GPUTX_E_UNSORTED = -8,  /* bulk flagged ts_sorted but timestamps not ascending */
+    GPUTX_E_INTERNAL = -9   /* an engine invariant failed on the device (a bug)  */
 };
 
 /* ---- execution strategies (Section 5) -------------------------------- */
@@ -128,6 +129,8 @@ typedef struct {
     int32_t kset_narrow;   /* K-SET waves of at most this many txns run in one workgroup */
     int32_t spin_limit_ms; /* watchdog on every device wait; expiry -> GPUTX_E_DEADLOCK  */
     int32_t grid_blocks;   /* persistent grid size (0: one workgroup per compute unit)  */
+    int32_t part_pipeline; /* PART with a staging wave beside the serial one (1, default) */
+    int32_t reserved;      /* 0                                                          */
 } gputx_options;
 
 /* One relation.  Columns are device arrays of capacity rows, caller-owned,

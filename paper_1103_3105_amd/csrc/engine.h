@@ -79,6 +79,12 @@ struct BulkArgs {
     int32_t kset_narrow;
     int32_t grid_blocks;    // persistent grid size
     uint64_t spin_ticks;    // watchdog
+    int32_t cell_bits;      // PART cell table: 1 << cell_bits slots
+    int32_t cells_max;      // most cells one registered type's transaction lists
+    int32_t prm_rows;       // PART LDS parameter rows: widest registered procedure
+    int32_t pipe_bits;      // pipelined PART cell table: 1 << pipe_bits slots
+    int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
+    int32_t pad_;
     Ws ws;
 };
 
@@ -107,8 +113,9 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 void launch_empty(const BulkArgs& a, hipStream_t s);
 // workgroups of the persistent executors that fit on one compute unit
 int exec_resident_blocks_per_cu();
-// LDS bytes of one PART wave for these arguments
+// LDS bytes of one PART workgroup for these arguments (one wave; pipelined)
 size_t part_wave_lds(const BulkArgs& a);
+size_t part_pipe_lds(const BulkArgs& a);
 // one-time kernel attributes (large dynamic LDS for PART)
 void exec_init_attributes();
 

@@ -495,47 +495,307 @@ struct PartChunk {
     int64_t* ts;    // [64]
     int64_t* app0;  // [64]
     int64_t* app1;  // [64]
+    int64_t* idx;   // [64] input index (status / results slot)
     int32_t* t;     // [64] type
     int32_t* np;    // [64] parameters loaded
     int32_t* st;    // [64] status
+    uint16_t* cs;   // [cells][64] cell table slot of each of the transaction's cells
 };
 
-// Lane 0 runs the chunk's cnt transactions in order, straight against the
-// tables (the lanes have already touched every row, so loads hit cache).
-// Statuses and results go to LDS; the owning lanes write them out after the
-// chunk.  P != 0: all run procedure P with descriptor T; P == 0: mixed types.
+// The chunk's table cells, staged in LDS: an open-addressing hash table keyed
+// by cell address (bit 1: 64-bit cell, bit 0: written; key 0 = empty slot),
+// plus the list of claimed slots.  Under PART a cell belongs to exactly one
+// partition, so the wave may hold it in LDS while the chunk runs and write it
+// back afterwards: no other wave reads or writes it meanwhile.
+#define GTX_LDS __attribute__((address_space(3)))
+struct __attribute__((aligned(16))) CellSlot {
+    uint64_t key;
+    int64_t val;
+};
+struct CellTab {
+    GTX_LDS CellSlot* slot;  // [1 << bits]
+    GTX_LDS int32_t* list;   // claimed slots
+    GTX_LDS int32_t* nlist;
+    int bits;
+};
+template <class V>
+__device__ __forceinline__ uint64_t cell_key(GTX_GLOBAL V* p) {
+    return (uint64_t)p | (sizeof(V) == 8 ? 2u : 0u);
+}
+__device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
+    return ((uint32_t)(key >> 2) * 0x9E3779B1u) >> (32 - bits);
+}
+
+// Fetch side: each lane claims the cells of its transaction and records the
+// slot of each of its cell ordinals.  The first claimant of a cell loads it
+// from global memory into the slot; a cell the procedure may write is marked
+// written (bit 0), so it is stored back when the table is flushed.
+struct CellClaim {
+    CellTab tab;
+    uint16_t* cs;  // the lane's column of slot ids
+    template <class V>
+    __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
+        const V v = *p;  // issued before the claim; kept only by the winner
+        const uint64_t key = cell_key(p);
+        const uint32_t mask = (1u << tab.bits) - 1;
+        uint32_t h = cell_hash(key, tab.bits);
+        uint32_t got = 0xffff;  // no free slot: the serial side reports the miss
+        for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1) & mask) {
+            uint64_t prev = 0;
+            __hip_atomic_compare_exchange_strong(&tab.slot[h].key, &prev, key | (w ? 1u : 0u),
+                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (prev == 0) {
+                tab.slot[h].val = (int64_t)v;
+                const int e = __hip_atomic_fetch_add(tab.nlist, 1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+                tab.list[e] = (int32_t)h;
+                got = h;
+                break;
+            }
+            if ((prev & ~(uint64_t)1) == key) {  // staged already
+                if (w && !(prev & 1))
+                    __hip_atomic_fetch_or(&tab.slot[h].key, (uint64_t)1, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                got = h;
+                break;
+            }
+        }
+        cs[ord * 64] = (uint16_t)got;
+    }
+};
+
+// Serial side: the procedures' accessor over the staged cells.  The fetch
+// lanes resolved every cell ordinal of the transaction to its slot, so a
+// reference is one LDS read and a write one LDS store: no address or hash
+// arithmetic on the serial path, and no global access (no store can then
+// alias the type descriptor, whose fields stay in registers).  An ordinal
+// the cell list did not name carries slot id 0xffff; it is recorded in miss
+// (bit 16) and fails the bulk with GPUTX_E_INTERNAL.
+struct LdsAcc {
+    GTX_LDS CellSlot* slot;
+    uint32_t mask;
+    const uint32_t* ids;  // slot id per cell ordinal (registers)
+    uint32_t* miss;
+    template <class V>
+    struct Ref {
+        GTX_LDS CellSlot* s;
+        int64_t v;
+        __device__ __forceinline__ V get() const { return (V)v; }
+        __device__ __forceinline__ void set(V x) { s->val = (int64_t)x; v = (int64_t)x; }
+    };
+    template <class V>
+    __device__ __forceinline__ Ref<V> ref(int ord, GTX_GLOBAL V*) {
+        const uint32_t id = ids[ord];
+        *miss |= id + 1;
+        Ref<V> r;
+        r.s = slot + (id & mask);
+        r.v = r.s->val;
+        return r;
+    }
+    template <class V>
+    __device__ __forceinline__ V ld(int ord, GTX_GLOBAL V* p) { return ref(ord, p).get(); }
+    template <class V>
+    __device__ __forceinline__ void st(int ord, GTX_GLOBAL V* p, V v) { ref(ord, p).set(v); }
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by the owning lanes
+};
+
+// Lane 0 runs the chunk's cnt transactions in order against the staged
+// cells.  Statuses and results go to LDS; the owning lanes write them out
+// after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
+// mixed types.  The LDS parameter rows past a transaction's own are zero, so
+// they are read without a bound; for narrow procedures the next
+// transaction's parameters and slot ids are read while the current one runs.
 template <int P>
 __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
-                                            int cnt, int64_t& committed, int64_t& aborted) {
-    constexpr int npb = proc_params(P);  // parameters the procedure can read
+                                            const CellTab& tab, int cnt, int64_t& committed,
+                                            int64_t& aborted) {
+    constexpr int NP = proc_params(P);  // parameters the procedure can read
+    constexpr int NR = proc_results(P); // results it can write
+    constexpr int NC = proc_cells(P);   // cells it can name
+    constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4;
     if (lane_id() != 0) return;
-    for (int k = 0; k < cnt; ++k) {
-        const int32_t ynp = c.np[k];
-        int64_t prm[GTX_MAX_PARAMS];
+    const int rows = a.prm_rows;
+    uint32_t miss = 0;
+    int64_t nxt[NP];
+    uint32_t nid[NC];
+    if constexpr (ahead) {
 #pragma unroll
-        for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = (r < ynp && r < npb) ? c.prm[r * 64 + k] : 0;
+        for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * 64];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * 64];
+    }
+    for (int k = 0; k < cnt; ++k) {
+        int64_t prm[GTX_MAX_PARAMS];
+        uint32_t ids[NC];
+#pragma unroll
+        for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = 0;
+        if constexpr (ahead) {
+#pragma unroll
+            for (int r = 0; r < NP; ++r) prm[r] = nxt[r];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) ids[r] = nid[r];
+            const int kn = k + 1 < cnt ? k + 1 : k;
+#pragma unroll
+            for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * 64 + kn];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * 64 + kn];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NP; ++r)
+                if (P != 0 || r < rows) prm[r] = c.prm[r * 64 + k];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * 64 + k] : 0xffffu;
+        }
+        LdsAcc acc{tab.slot, (1u << tab.bits) - 1, ids, &miss};
         int64_t res[GTX_MAX_RESULTS];
-        NoAppendAcc acc;  // the owning lanes already wrote the appended rows
-        const int32_t s = P ? txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res)
-                            : txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
+        int32_t s;
+        if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+        else s = txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
         c.st[k] = s;
 #pragma unroll
-        for (int r = 0; r < GTX_MAX_RESULTS; ++r) c.res[r * 64 + k] = res[r];
+        for (int r = 0; r < NR; ++r) c.res[r * 64 + k] = res[r];
         committed += s == GPUTX_COMMIT;
         aborted += s == GPUTX_ABORT;
     }
+    if (miss & 0x10000u) fail(a.ws.st, GPUTX_E_INTERNAL);
 }
 
+// LDS of the PART kernels: chunk buffers, then the cell table and its list.
+__host__ __device__ inline size_t part_chunk_bytes(int rows, int cells) {
+    return (size_t)64 * 8 * (GTX_MAX_RESULTS + rows + 4) + (size_t)64 * 4 * 3 +
+           (size_t)64 * 2 * ((cells + 7) & ~7);
+}
 size_t part_wave_lds(const BulkArgs& a) {
-    const int npb = std::min(a.n_params, GTX_MAX_PARAMS);
-    return (size_t)64 * 8 * (GTX_MAX_RESULTS + npb + 3) + (size_t)64 * 4 * 3;
+    return part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.cell_bits) +
+           (size_t)4 * (64 * a.cells_max + 4);
+}
+size_t part_pipe_lds(const BulkArgs& a) {
+    return 2 * part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.pipe_bits) +
+           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
+}
+
+__device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, int rows) {
+    PartChunk c;
+    c.res = reinterpret_cast<int64_t*>(base);
+    c.prm = c.res + 64 * GTX_MAX_RESULTS;
+    c.ts = c.prm + 64 * rows;
+    c.app0 = c.ts + 64;
+    c.app1 = c.app0 + 64;
+    c.idx = c.app1 + 64;
+    c.t = reinterpret_cast<int32_t*>(c.idx + 64);
+    c.np = c.t + 64;
+    c.st = c.np + 64;
+    c.cs = reinterpret_cast<uint16_t*>(c.st + 64);
+    return c;
+}
+
+// One lane per transaction of the chunk starting at c0: load its signature
+// into the chunk buffer, write its appended rows (insert buffers, Section
+// 3.2) and stage its cells in the table.
+__device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
+    const int64_t j = c0 + lane;
+    if (j >= end) return;
+    const int32_t p = (int32_t)pos[j];
+    const int32_t t = a.ws.tty[p];
+    TxnIn x;
+    load_txn(a, p, t, x);
+    const int rows = a.prm_rows;
+#pragma unroll
+    for (int k = 0; k < GTX_MAX_PARAMS; ++k)
+        if (k < rows) c.prm[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r) c.res[r * 64 + lane] = 0;
+    c.ts[lane] = x.ts;
+    c.app0[lane] = x.app0;
+    c.app1[lane] = x.app1;
+    c.idx[lane] = x.i;
+    c.t[lane] = t;
+    c.np[lane] = x.np;
+    for (int r = 0; r < a.cells_max; ++r) c.cs[r * 64 + lane] = 0xffff;
+    CellClaim claim{tab, c.cs + lane};
+    txn_cells(a.types[t], x.prm, claim);
+    AppendOnlyAcc ap;
+    int64_t unused[GTX_MAX_RESULTS];
+    (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+}
+
+// The owning lanes write the chunk's statuses and results.
+__device__ __forceinline__ void part_writeout(const BulkArgs& a, const PartChunk& c, int64_t c0,
+                                              int64_t end, int lane) {
+    if (c0 + lane >= end) return;
+    const int64_t i = c.idx[lane];
+    a.status[i] = c.st[lane];
+    int64_t* out = a.results + i * a.width;
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+        if (r < a.width) out[r] = c.res[r * 64 + lane];
+    for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
+}
+
+// Written cells back to the tables; the listed slots are emptied.  The
+// caller resets the list count after a barrier.
+__device__ __forceinline__ void part_flush(const CellTab& tab, int tid, int nthreads) {
+    const int ncl = *tab.nlist;
+    for (int e = tid; e < ncl; e += nthreads) {
+        const int32_t h = tab.list[e];
+        const uint64_t sk = tab.slot[h].key;
+        const int64_t sv = tab.slot[h].val;
+        if (sk & 1) {
+            const uint64_t addr = sk & ~(uint64_t)3;
+            if (sk & 2) *(GTX_GLOBAL int64_t*)addr = sv;
+            else *(GTX_GLOBAL int32_t*)addr = (int32_t)sv;
+        }
+        tab.slot[h].key = 0;
+    }
+}
+
+// Lane 0 of the calling wave runs the chunk, specialised on its procedure
+// when every transaction of the chunk has the same type.
+__device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                               int cnt, int lane, int64_t& committed, int64_t& aborted) {
+    const int32_t t = lane < cnt ? c.t[lane] : -1;
+    const int t0 = __builtin_amdgcn_readfirstlane(t);
+    const bool uniform = __ballot(lane < cnt && t != t0) == 0;
+    const int proc = uniform ? a.types[t0].proc : 0;
+    switch (proc) {
+#define GTX_PART_CASE(P)                                                   \
+    case P:                                                                \
+        part_serial<P>(a, a.types[t0], c, tab, cnt, committed, aborted);   \
+        break;
+        GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
+        GTX_PART_CASE(GPUTX_NEW_ORDER)
+        GTX_PART_CASE(GPUTX_PAYMENT)
+        GTX_PART_CASE(GPUTX_ORDER_STATUS)
+        GTX_PART_CASE(GPUTX_GET_SUB)
+        GTX_PART_CASE(GPUTX_GET_CF)
+        GTX_PART_CASE(GPUTX_UPD_SUB_FIELD)
+        GTX_PART_CASE(GPUTX_UPD_LOC)
+        GTX_PART_CASE(GPUTX_INS_CF)
+        GTX_PART_CASE(GPUTX_DEL_CF)
+#undef GTX_PART_CASE
+    default:
+        part_serial<0>(a, a.types[t0], c, tab, cnt, committed, aborted);
+    }
+}
+
+__device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, int list_cap) {
+    CellTab tab;
+    tab.bits = bits;
+    tab.slot = (GTX_LDS CellSlot*)base;
+    tab.list = (GTX_LDS int32_t*)(tab.slot + (1 << bits));
+    tab.nlist = tab.list + list_cap;
+    return tab;
 }
 
 // One wave per partition, still one serial thread of control (Section 5.2).
 // For each chunk of 64 of the partition's transactions the lanes load the
-// signatures into LDS, touch every row their transaction will use and write
-// its appended rows; lane 0 then runs the 64 in order (shared state only);
-// finally the owning lanes write statuses and results.
+// signatures into LDS, write their appended rows and stage every cell the
+// chunk may use in the LDS cell table; lane 0 then runs the 64 in order
+// against the table; finally the owning lanes write statuses, results and
+// the cells that were written.
 __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
@@ -543,83 +803,96 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (q >= a.n_parts) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int lane = lane_id();
-    const int npb = min(a.n_params, GTX_MAX_PARAMS);
-    PartChunk c;
-    c.res = reinterpret_cast<int64_t*>(part_lds);
-    c.prm = c.res + 64 * GTX_MAX_RESULTS;
-    c.ts = c.prm + 64 * npb;
-    c.app0 = c.ts + 64;
-    c.app1 = c.app0 + 64;
-    c.t = reinterpret_cast<int32_t*>(c.app1 + 64);
-    c.np = c.t + 64;
-    c.st = c.np + 64;
+    const PartChunk c = part_chunk_at(part_lds, a.prm_rows);
+    const CellTab tab = part_table_at(part_lds + part_chunk_bytes(a.prm_rows, a.cells_max), a.cell_bits,
+                                      64 * a.cells_max);
+    for (int s = lane; s < (1 << a.cell_bits); s += 64) tab.slot[s].key = 0;
+    if (lane == 0) *tab.nlist = 0;
+    __syncthreads();
 
     const int src = a.part_passes & 1;
     const uint32_t* pos = a.ws.qv[src];
     int64_t lo, end;
     part_range(a, a.ws.qk[src], q, &lo, &end);
-    int64_t committed = 0, aborted = 0, sink = 0;
+    int64_t committed = 0, aborted = 0;
     for (int64_t c0 = lo; c0 < end; c0 += 64) {
-        const int64_t j = c0 + lane;
-        int64_t i = 0;
-        int32_t t = -1;
-        if (j < end) {
-            const int32_t p = (int32_t)pos[j];
-            t = a.ws.tty[p];
-            TxnIn x;
-            load_txn(a, p, t, x);
-#pragma unroll
-            for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-                if (k < npb) c.prm[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
-            c.ts[lane] = x.ts;
-            c.app0[lane] = x.app0;
-            c.app1[lane] = x.app1;
-            c.t[lane] = t;
-            c.np[lane] = x.np;
-            sink ^= txn_touch(a.types[t], x.prm);
-            {   // insert-buffer rows (Section 3.2), written in parallel by their owners
-                AppendOnlyAcc ap;
-                int64_t unused[GTX_MAX_RESULTS];
-                (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
-            }
-            i = x.i;
-        }
+        part_fetch(a, c, tab, pos, c0, end, lane);
         __syncthreads();
-        const int cnt = (int)min<int64_t>(64, end - c0);
-        const int t0 = __builtin_amdgcn_readfirstlane(t);
-        const bool uniform = __ballot(j < end && t != t0) == 0;
-        const int proc = uniform ? a.types[t0].proc : 0;
-        switch (proc) {
-#define GTX_PART_CASE(P)                                              \
-    case P:                                                           \
-        part_serial<P>(a, a.types[t0], c, cnt, committed, aborted);   \
-        break;
-            GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
-            GTX_PART_CASE(GPUTX_NEW_ORDER)
-            GTX_PART_CASE(GPUTX_PAYMENT)
-            GTX_PART_CASE(GPUTX_ORDER_STATUS)
-            GTX_PART_CASE(GPUTX_GET_SUB)
-            GTX_PART_CASE(GPUTX_GET_CF)
-            GTX_PART_CASE(GPUTX_UPD_SUB_FIELD)
-            GTX_PART_CASE(GPUTX_UPD_LOC)
-            GTX_PART_CASE(GPUTX_INS_CF)
-            GTX_PART_CASE(GPUTX_DEL_CF)
-#undef GTX_PART_CASE
-        default:
-            part_serial<0>(a, a.types[t0], c, cnt, committed, aborted);
-        }
+        part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
         __syncthreads();
-        if (j < end) {
-            a.status[i] = c.st[lane];
-            int64_t* out = a.results + i * a.width;
-#pragma unroll
-            for (int r = 0; r < GTX_MAX_RESULTS; ++r)
-                if (r < a.width) out[r] = c.res[r * 64 + lane];
-            for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
-        }
+        part_writeout(a, c, c0, end, lane);
+        part_flush(tab, lane, 64);
+        __syncthreads();
+        if (lane == 0) *tab.nlist = 0;
         __syncthreads();
     }
-    if (sink == (int64_t)0x7fe1d2c3b4a59687ll) st->pad[0] = 1;  // keeps the touches live
+    add_counts(st, committed, aborted);
+}
+
+// Pipelined PART: one 128-thread workgroup per partition.  Wave 0 (lane 0)
+// runs chunk k serially while wave 1 writes out chunk k-1 and stages chunk
+// k+1 in the other buffer.  The cell table persists across chunks (a cell
+// chunk k+1 shares with chunk k is found staged, with chunk k's writes
+// applied by the time chunk k+1 runs); it is flushed and emptied when a
+// further chunk might fill it past half, at a point where no wave probes it,
+// so linear probing never sees a deleted slot.
+__global__ __launch_bounds__(128) void k_part_pipe(BulkArgs a) {
+    GtxState* st = a.ws.st;
+    const int64_t q = blockIdx.x;
+    if (q >= a.n_parts) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const size_t cb = part_chunk_bytes(a.prm_rows, a.cells_max);
+    auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a.prm_rows); };
+    const int cap = 1 << a.pipe_bits;
+    const CellTab tab = part_table_at(part_lds + 2 * cb, a.pipe_bits, cap / 2);
+    GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk
+    // one decision for the whole workgroup (another workgroup may fail the
+    // bulk meanwhile; both waves must still meet at every barrier)
+    if (tid == 0) flag[0] = !failed(st) && st->chosen == GPUTX_PART;
+    __syncthreads();
+    if (!flag[0]) return;
+    for (int s = tid; s < cap; s += 128) tab.slot[s].key = 0;
+    if (tid == 0) *tab.nlist = 0;
+
+    const int src = a.part_passes & 1;
+    const uint32_t* pos = a.ws.qv[src];
+    int64_t lo, end;
+    part_range(a, a.ws.qk[src], q, &lo, &end);
+    const int64_t nch = (end - lo + 63) / 64;
+    int64_t committed = 0, aborted = 0;
+    __syncthreads();
+    if (wave == 1) part_fetch(a, buf(0), tab, pos, lo, end, lane);
+    __syncthreads();
+    for (int64_t k = 0; k < nch; ++k) {
+        const int64_t c0 = lo + 64 * k;
+        if (wave == 0) {
+            part_run_chunk(a, buf(k), tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+        } else {
+            if (k > 0) part_writeout(a, buf(k - 1), c0 - 64, end, lane);
+            bool flush = false;
+            if (k + 1 < nch) {
+                flush = *tab.nlist + 64 * a.cells_max > cap / 2;
+                if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+            }
+            if (lane == 0) flag[k & 1] = flush;
+        }
+        __syncthreads();
+        if (flag[k & 1]) {  // same value in every wave
+            part_flush(tab, tid, 128);
+            __syncthreads();
+            if (tid == 0) *tab.nlist = 0;
+            __syncthreads();
+            if (wave == 1) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+            __syncthreads();
+        }
+    }
+    if (nch > 0) {
+        if (wave == 1) part_writeout(a, buf(nch - 1), lo + 64 * (nch - 1), end, lane);
+        part_flush(tab, tid, 128);
+    }
     add_counts(st, committed, aborted);
 }
 
@@ -678,6 +951,8 @@ void exec_init_attributes() {
     done = true;
     (void)hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kPartLdsMax);
+    (void)hipFuncSetAttribute((const void*)k_part_pipe, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kPartLdsMax);
 }
 
 int exec_resident_blocks_per_cu() {
@@ -707,7 +982,9 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     }
     pm.mark(PH_PARTSORT, s);
     if (part) {
-        if (a.n_parts <= 8192 && part_wave_lds(a) <= (size_t)kPartLdsMax) {  // few long partitions: one wave each
+        if (a.part_pipeline && a.n_parts <= 8192 && part_pipe_lds(a) <= (size_t)kPartLdsMax) {
+            hipLaunchKernelGGL(k_part_pipe, dim3((unsigned)a.n_parts), dim3(128), part_pipe_lds(a), s, a);
+        } else if (a.n_parts <= 8192 && part_wave_lds(a) <= (size_t)kPartLdsMax) {  // one wave each
             hipLaunchKernelGGL(k_part_wave, dim3((unsigned)a.n_parts), dim3(64), part_wave_lds(a), s, a);
         } else {
             const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_BLOCK - 1) / GTX_BLOCK);

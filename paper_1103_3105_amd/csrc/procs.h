@@ -169,63 +169,84 @@ __device__ __forceinline__ GTX_GLOBAL V* colp(const DevType& T, int role, int c)
     return (GTX_GLOBAL V*)(T.col[role][c]);
 }
 
-// Read one value of every row the transaction will touch, to pull the rows
-// towards the compute unit before the transaction runs; returns an XOR of
-// the values so the loads stay live.  Values are not used for execution.
-__device__ inline int64_t txn_touch(const DevType& T, const int64_t* p) {
-    int64_t s = 0;
+// Every table cell (one column of one row, appended rows excluded) the
+// transaction may read or write, passed as f.cell(ord, ptr, may_write) with
+// the cell's value type.  ord numbers the procedure's cells; the procedure
+// names each cell it touches by the same ordinal (acc.ref(ord, ptr) below).
+// The set depends only on the parameters, and every cell lies in a row of
+// the transaction's basic operations, so under PART (no cross-partition
+// transaction) no two partitions share a cell.
+template <class F>
+__device__ __forceinline__ void txn_cells(const DevType& T, const int64_t* p, F& f) {
     switch (T.proc) {
     case GPUTX_DEBIT_CREDIT:
-        s ^= colp<const int64_t>(T, 0, 0)[p[0]];
-        s ^= colp<const int64_t>(T, 1, 0)[p[1]];
-        s ^= colp<const int64_t>(T, 2, 0)[p[2]];
+        f.cell(0, colp<int64_t>(T, 0, 0) + p[0], true);
+        f.cell(1, colp<int64_t>(T, 1, 0) + p[1], true);
+        f.cell(2, colp<int64_t>(T, 2, 0) + p[2], true);
         break;
     case GPUTX_NEW_ORDER: {
-        GTX_GLOBAL const int32_t* S = colp<const int32_t>(T, 3, 0);
+        GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0) + p[0] * T.dims[3];
 #pragma unroll
         for (int j = 0; j < 15; ++j)
-            if (j < p[3]) s ^= S[p[0] * T.dims[3] + p[4 + j]];
+            if (j < p[3]) f.cell(j, S + p[4 + j], true);
         break;
     }
     case GPUTX_PAYMENT: {
         int64_t drow = p[0] * T.dims[1] + p[1];
-        s ^= colp<const int64_t>(T, 0, 0)[p[0]];
-        s ^= colp<const int64_t>(T, 1, 0)[drow];
-        s ^= colp<const int64_t>(T, 2, 0)[drow * T.dims[2] + p[2]];
+        f.cell(0, colp<int64_t>(T, 0, 0) + p[0], true);
+        f.cell(1, colp<int64_t>(T, 1, 0) + drow, true);
+        f.cell(2, colp<int64_t>(T, 2, 0) + (drow * T.dims[2] + p[2]), true);
         break;
     }
     case GPUTX_ORDER_STATUS:
-        s ^= colp<const int64_t>(T, 2, 0)[(p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2]];
+        f.cell(0, colp<int64_t>(T, 2, 0) + ((p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2]), false);
         break;
     case GPUTX_GET_SUB:
 #pragma unroll
-        for (int f = 0; f < 14; ++f) s ^= colp<const int32_t>(T, 0, 1 + f)[p[0]];
+        for (int c = 0; c < 14; ++c) f.cell(c, colp<int32_t>(T, 0, 1 + c) + p[0], false);
         break;
     case GPUTX_UPD_SUB_FIELD:
     case GPUTX_UPD_LOC:
-        s ^= colp<const int32_t>(T, 0, 1 + (int)p[1] + (T.proc == GPUTX_UPD_LOC ? 4 : 0))[p[0]];
+        f.cell(0, colp<int32_t>(T, 0, 1 + (int)p[1] + (T.proc == GPUTX_UPD_LOC ? 4 : 0)) + p[0], true);
         break;
     case GPUTX_GET_CF:
     case GPUTX_INS_CF:
     case GPUTX_DEL_CF: {
+        const bool w = T.proc != GPUTX_GET_CF;
         int64_t slot = p[0] * 12 + p[1];
-        s ^= colp<const int32_t>(T, 1, 0)[slot];
-        s ^= colp<const int64_t>(T, 1, 2)[slot];
+        f.cell(0, colp<int32_t>(T, 1, 0) + slot, w);
+        f.cell(1, colp<int32_t>(T, 1, 1) + slot, w);
+        f.cell(2, colp<int64_t>(T, 1, 2) + slot, w);
         break;
     }
     }
-    return s;
 }
 
-// Table-cell access used by the procedures.  DirectAcc reads and writes the
-// columns in place; a serial PART wave substitutes an LDS-backed accessor
-// (kernels_exec.hip).  ld/st are cells other transactions of the bulk may
-// read; app is a row appended to an append-only table.
+// Most cells txn_cells lists for one transaction of procedure P (0: any).
+__host__ __device__ constexpr int proc_cells(int proc) {
+    return proc == GPUTX_NEW_ORDER ? 15 : proc == GPUTX_GET_SUB ? 14
+         : (proc == GPUTX_ORDER_STATUS || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 1
+         : proc == 0 ? 15 : 3;
+}
+
+// Table-cell access used by the procedures.  acc.ref(ord, ptr) names one
+// cell, ord being its ordinal in txn_cells (made after any earlier write to
+// that cell by the same transaction); get/set read and write it; ld/st are
+// one-shot forms; app writes a row appended to an append-only table.
+// DirectAcc works on the columns in place.
 struct DirectAcc {
     template <class V>
-    __device__ __forceinline__ V ld(GTX_GLOBAL V* p) { return *p; }
+    struct Ref {
+        GTX_GLOBAL V* p;
+        __device__ __forceinline__ V get() const { return *p; }
+        __device__ __forceinline__ void set(V v) const { *p = v; }
+    };
     template <class V>
-    __device__ __forceinline__ void st(GTX_GLOBAL V* p, V v) { *p = v; }
+    __device__ __forceinline__ Ref<V> ref(int, GTX_GLOBAL V* p) { return Ref<V>{p}; }
+    template <class V>
+    __device__ __forceinline__ V ld(int, GTX_GLOBAL V* p) { return *p; }
+    template <class V>
+    __device__ __forceinline__ void st(int, GTX_GLOBAL V* p, V v) { *p = v; }
     template <class V>
     __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
 };
@@ -237,17 +258,20 @@ struct DirectAcc {
 // (reads yield 0 and touch no memory), NoAppendAcc everything else.
 struct AppendOnlyAcc {
     template <class V>
-    __device__ __forceinline__ V ld(GTX_GLOBAL V*) { return V(0); }
+    struct Ref {
+        __device__ __forceinline__ V get() const { return V(0); }
+        __device__ __forceinline__ void set(V) const {}
+    };
     template <class V>
-    __device__ __forceinline__ void st(GTX_GLOBAL V*, V) {}
+    __device__ __forceinline__ Ref<V> ref(int, GTX_GLOBAL V*) { return Ref<V>{}; }
+    template <class V>
+    __device__ __forceinline__ V ld(int, GTX_GLOBAL V*) { return V(0); }
+    template <class V>
+    __device__ __forceinline__ void st(int, GTX_GLOBAL V*, V) {}
     template <class V>
     __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
 };
-struct NoAppendAcc {
-    template <class V>
-    __device__ __forceinline__ V ld(GTX_GLOBAL V* p) { return *p; }
-    template <class V>
-    __device__ __forceinline__ void st(GTX_GLOBAL V* p, V v) { *p = v; }
+struct NoAppendAcc : DirectAcc {
     template <class V>
     __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}
 };
@@ -259,6 +283,13 @@ __host__ __device__ constexpr int proc_params(int proc) {
          : (proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 2
          : (proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 3 : proc == GPUTX_INS_CF ? 4 : 34;
 }
+// Results procedure P can write (0: any procedure).
+__host__ __device__ constexpr int proc_results(int proc) {
+    return proc == GPUTX_NEW_ORDER ? 16 : proc == GPUTX_GET_SUB ? 14
+         : (proc == GPUTX_ORDER_STATUS || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC ||
+            proc == GPUTX_INS_CF) ? 1
+         : proc == 0 ? GTX_MAX_RESULTS : 3;
+}
 // Run one valid transaction of procedure P (one case of the switch of
 // Section 3.2) through accessor acc.  app0/app1 are the rows its appends
 // occupy.  Returns its status, fills res[0..15].
@@ -269,15 +300,15 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
     for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
     switch (P) {
     case GPUTX_DEBIT_CREDIT: {
-        GTX_GLOBAL int64_t* A = colp<int64_t>(T, 0, 0) + p[0];
-        GTX_GLOBAL int64_t* Tl = colp<int64_t>(T, 1, 0) + p[1];
-        GTX_GLOBAL int64_t* B = colp<int64_t>(T, 2, 0) + p[2];
-        int64_t a = wrap_add(acc.ld(A), p[3]);
-        int64_t t = wrap_add(acc.ld(Tl), p[3]);
-        int64_t b = wrap_add(acc.ld(B), p[3]);
-        acc.st(A, a);
-        acc.st(Tl, t);
-        acc.st(B, b);
+        auto A = acc.ref(0, colp<int64_t>(T, 0, 0) + p[0]);
+        auto Tl = acc.ref(1, colp<int64_t>(T, 1, 0) + p[1]);
+        auto B = acc.ref(2, colp<int64_t>(T, 2, 0) + p[2]);
+        int64_t a = wrap_add(A.get(), p[3]);
+        int64_t t = wrap_add(Tl.get(), p[3]);
+        int64_t b = wrap_add(B.get(), p[3]);
+        A.set(a);
+        Tl.set(t);
+        B.set(b);
         acc.app(colp<int64_t>(T, 3, 0) + app0, p[0]);
         acc.app(colp<int64_t>(T, 3, 1) + app0, p[1]);
         acc.app(colp<int64_t>(T, 3, 2) + app0, p[2]);
@@ -294,11 +325,11 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
 #pragma unroll
         for (int j = 0; j < 15; ++j) {
             if (j < k) {
-                GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0) + (p[0] * T.dims[3] + p[4 + j]);
-                int64_t s = (int64_t)acc.ld(S) - p[19 + j];
+                auto S = acc.ref(j, colp<int32_t>(T, 3, 0) + (p[0] * T.dims[3] + p[4 + j]));
+                int64_t s = (int64_t)S.get() - p[19 + j];
                 if (s < 10) s += 91;
                 int32_t s32 = to_i32(s);
-                acc.st(S, s32);
+                S.set(s32);
                 res[1 + j] = s32;
                 int64_t r = app1 + j;
                 acc.app(colp<int64_t>(T, 5, 0) + r, ts);
@@ -318,15 +349,15 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
     case GPUTX_PAYMENT: {
         int64_t drow = p[0] * T.dims[1] + p[1];
         int64_t crow = drow * T.dims[2] + p[2];
-        GTX_GLOBAL int64_t* Wb = colp<int64_t>(T, 0, 0) + p[0];
-        GTX_GLOBAL int64_t* Db = colp<int64_t>(T, 1, 0) + drow;
-        GTX_GLOBAL int64_t* Cb = colp<int64_t>(T, 2, 0) + crow;
-        int64_t w = wrap_add(acc.ld(Wb), p[3]);
-        int64_t d = wrap_add(acc.ld(Db), p[3]);
-        int64_t c = wrap_add(acc.ld(Cb), p[3]);
-        acc.st(Wb, w);
-        acc.st(Db, d);
-        acc.st(Cb, c);
+        auto Wb = acc.ref(0, colp<int64_t>(T, 0, 0) + p[0]);
+        auto Db = acc.ref(1, colp<int64_t>(T, 1, 0) + drow);
+        auto Cb = acc.ref(2, colp<int64_t>(T, 2, 0) + crow);
+        int64_t w = wrap_add(Wb.get(), p[3]);
+        int64_t d = wrap_add(Db.get(), p[3]);
+        int64_t c = wrap_add(Cb.get(), p[3]);
+        Wb.set(w);
+        Db.set(d);
+        Cb.set(c);
         res[0] = w;
         res[1] = d;
         res[2] = c;
@@ -334,50 +365,52 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
     }
     case GPUTX_ORDER_STATUS: {
         int64_t crow = (p[0] * T.dims[1] + p[1]) * T.dims[2] + p[2];
-        res[0] = acc.ld(colp<int64_t>(T, 2, 0) + crow);
+        res[0] = acc.ld(0, colp<int64_t>(T, 2, 0) + crow);
         return GPUTX_COMMIT;
     }
     case GPUTX_GET_SUB: {
 #pragma unroll
-        for (int f = 0; f < 14; ++f) res[f] = acc.ld(colp<int32_t>(T, 0, 1 + f) + p[0]);
+        for (int f = 0; f < 14; ++f) res[f] = acc.ld(f, colp<int32_t>(T, 0, 1 + f) + p[0]);
         return GPUTX_COMMIT;
     }
     case GPUTX_GET_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        res[0] = acc.ld(colp<int32_t>(T, 1, 0) + slot);
-        res[1] = acc.ld(colp<int32_t>(T, 1, 1) + slot);
-        res[2] = acc.ld(colp<int64_t>(T, 1, 2) + slot);
+        res[0] = acc.ld(0, colp<int32_t>(T, 1, 0) + slot);
+        res[1] = acc.ld(1, colp<int32_t>(T, 1, 1) + slot);
+        res[2] = acc.ld(2, colp<int64_t>(T, 1, 2) + slot);
         return GPUTX_COMMIT;
     }
     case GPUTX_UPD_SUB_FIELD:
     case GPUTX_UPD_LOC: {
         int c = 1 + (int)p[1] + (P == GPUTX_UPD_LOC ? 4 : 0);
-        GTX_GLOBAL int32_t* F = colp<int32_t>(T, 0, c) + p[0];
-        res[0] = acc.ld(F);
-        acc.st(F, to_i32(p[2]));
+        auto F = acc.ref(0, colp<int32_t>(T, 0, c) + p[0]);
+        res[0] = F.get();
+        F.set(to_i32(p[2]));
         return GPUTX_COMMIT;
     }
     case GPUTX_INS_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0) + slot;
-        int32_t o = acc.ld(occ);
+        auto occ = acc.ref(0, colp<int32_t>(T, 1, 0) + slot);
+        int32_t o = occ.get();
         res[0] = o;
         if (o) return GPUTX_ABORT;  // read phase decides; nothing written
-        acc.st(occ, (int32_t)1);
-        acc.st(colp<int32_t>(T, 1, 1) + slot, to_i32(p[2]));
-        acc.st(colp<int64_t>(T, 1, 2) + slot, p[3]);
+        occ.set((int32_t)1);
+        acc.st(1, colp<int32_t>(T, 1, 1) + slot, to_i32(p[2]));
+        acc.st(2, colp<int64_t>(T, 1, 2) + slot, p[3]);
         return GPUTX_COMMIT;
     }
     case GPUTX_DEL_CF: {
         int64_t slot = p[0] * 12 + p[1];
-        GTX_GLOBAL int32_t* occ = colp<int32_t>(T, 1, 0) + slot;
-        if (!acc.ld(occ)) return GPUTX_ABORT;
+        auto occ = acc.ref(0, colp<int32_t>(T, 1, 0) + slot);
+        if (!occ.get()) return GPUTX_ABORT;
+        auto num = acc.ref(1, colp<int32_t>(T, 1, 1) + slot);
+        auto end = acc.ref(2, colp<int64_t>(T, 1, 2) + slot);
         res[0] = 1;
-        res[1] = acc.ld(colp<int32_t>(T, 1, 1) + slot);
-        res[2] = acc.ld(colp<int64_t>(T, 1, 2) + slot);
-        acc.st(occ, (int32_t)0);
-        acc.st(colp<int32_t>(T, 1, 1) + slot, (int32_t)0);
-        acc.st(colp<int64_t>(T, 1, 2) + slot, (int64_t)0);
+        res[1] = num.get();
+        res[2] = end.get();
+        occ.set((int32_t)0);
+        num.set((int32_t)0);
+        end.set((int64_t)0);
         return GPUTX_COMMIT;
     }
     }

@@ -52,6 +52,8 @@ extern "C" int gputx_default_options(gputx_options* o) {
     o->kset_narrow = 256;
     o->spin_limit_ms = 5000;
     o->grid_blocks = 0;
+    o->part_pipeline = 1;
+    o->reserved = 0;
     return GPUTX_OK;
 }
 
@@ -461,8 +463,23 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     a.c_bar = h->opt.c_bar;
     a.d_bar = h->opt.d_bar;
     a.kset_narrow = h->opt.kset_narrow;
+    a.part_pipeline = h->opt.part_pipeline;
     a.grid_blocks = grid_blocks;
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
+    // PART cell table: at most half full when every lane of a chunk stages
+    // the most cells any registered procedure lists
+    a.cells_max = 1;
+    a.prm_rows = 1;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
+        if (!h->type_present[i]) continue;
+        a.cells_max = std::max(a.cells_max, proc_cells(h->types[i].proc));
+        a.prm_rows = std::max(a.prm_rows, proc_params(h->types[i].proc));
+    }
+    a.cell_bits = 1;
+    while ((1 << a.cell_bits) < 2 * 64 * a.cells_max) ++a.cell_bits;
+    // the pipelined form keeps cells across chunks: room for several chunks
+    a.pipe_bits = a.cell_bits;
+    while ((1 << a.pipe_bits) < 8 * 64 * a.cells_max && a.pipe_bits < 12) ++a.pipe_bits;
     *out = a;
     return GPUTX_OK;
 }

@@ -21,8 +21,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgputx.so")
 
-OK, E_ARG, E_TYPE, E_DUP_TS, E_CAPACITY, E_HIP, E_STATE, E_DEADLOCK, E_UNSORTED = (
-    0, -1, -2, -3, -4, -5, -6, -7, -8)
+OK, E_ARG, E_TYPE, E_DUP_TS, E_CAPACITY, E_HIP, E_STATE, E_DEADLOCK, E_UNSORTED, E_INTERNAL = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9)
 AUTO, TPL, PART, KSET = 0, 1, 2, 3
 STRATEGY = {"AUTO": AUTO, "TPL": TPL, "PART": PART, "KSET": KSET}
 STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
@@ -36,7 +36,8 @@ MAX_TYPES, MAX_TABLES, MAX_COLS, MAX_ROLES = 16, 32, 16, 8
 class Options(ctypes.Structure):
     _fields_ = [("w0_bar", c_int64), ("c_bar", c_int64), ("d_bar", c_int64),
                 ("part_size", c_int64), ("group_by_type", c_int32), ("kset_narrow", c_int32),
-                ("spin_limit_ms", c_int32), ("grid_blocks", c_int32)]
+                ("spin_limit_ms", c_int32), ("grid_blocks", c_int32), ("part_pipeline", c_int32),
+                ("reserved", c_int32)]
 
 
 class TableDesc(ctypes.Structure):

@@ -121,6 +121,28 @@ def test_subscriber_with_aborts(strategy):
     check_features(s, tabs, types, bulk, part_size=16)
 
 
+@pytest.mark.parametrize("pipeline", [0, 1])
+@pytest.mark.parametrize("workload", ["bank", "order", "sub"])
+def test_part_forms(workload, pipeline):
+    """Both PART kernels: one wave per partition, and the pipelined pair of
+    waves whose LDS cell table persists across chunks (the order and
+    subscriber bulks fill it within a few chunks, so it is flushed often)."""
+    if workload == "bank":
+        tabs, types, bulk = util.small_bank(61, 20_000, n_branch=8, tpb=10, apt=300, theta=0.8)
+        width, ps = 3, 1
+    elif workload == "order":
+        tabs, types, bulk = util.small_order(62, 20_000, n_wh=4, d_per_w=10, c_per_d=30,
+                                             items_per_w=500)
+        width, ps = 16, 1
+    else:
+        tabs, types, bulk = util.small_sub(63, 20_000, n_sub=2000, theta=0.8)
+        width, ps = 14, 16
+    _say("part form", workload, pipeline)
+    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline)
+    assert s.chosen == 2, s.as_dict()
+    assert_parity(s, g, o, bulk)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 63, 4097])
 def test_small_and_empty_bulks(n):
     tabs, types, bulk = util.small_bank(24, max(n, 1), n_branch=2, tpb=2, apt=5)
