@@ -96,7 +96,7 @@ def phase_bytes(workload: str, n: int, m: int, key_passes: int, committed: int):
         "prepare": n * (32 + 4 + 4 + 8 + 8) + 2 * 2 * 8 * n,
         "emit": n * (32 + 8 + 8) + m * 12,
         "op_sort": m * (4 + 16 * key_passes),
-        "rank": m * 44,
+        "rank": m * 40,
         "features": n * 8,
         "part": committed * exec_per_txn,
         "tpl": committed * exec_per_txn,
@@ -371,7 +371,8 @@ def main():
     dom = max((k for k in phases if k in pb), key=lambda k: phases[k])
     dom_ms = phases[dom] / max(nb, 1)
     achieved = pb[dom] / (dom_ms / 1e3) / 1e9 if dom_ms > 0 else 0.0
-    kernel_of = {"part": "k_part_wave", "tpl": "k_tpl", "kset": "k_kset", "rank": "k_rank_down",
+    kernel_of = {"part": "k_part_pipe" if args.part_pipeline else "k_part_wave",
+                 "tpl": "k_tpl", "kset": "k_kset", "rank": "k_rank_down",
                  "op_sort": "k_sort_pass", "prepare": "k_prepare", "emit": "k_emit"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6),

@@ -36,7 +36,8 @@ struct GtxState {
     int32_t narrow_done;  // K-SET: narrow mode ran the last wave
     int64_t narrow_k;     // K-SET: next wave after narrow mode
     int64_t narrow_prog;  // K-SET: waves finished in narrow mode (watchdog progress)
-    int32_t pad[2];
+    int32_t n_heads;      // PART: non-empty partitions
+    int32_t pad;
 };
 
 namespace gtx {

@@ -45,6 +45,8 @@ struct Ws {
     int32_t* grp_cnt;    // [mcap] per-group completion counters
     uint32_t* qk[2];     // [n] PART sort: partition id
     uint32_t* qv[2];     // [n] PART sort: serial position
+    int32_t* heads;      // [n + 1] PART: first sorted position of each non-empty partition
+    int32_t* heads_tmp;  // [head blocks] PART: per-block head counts, then offsets
     int32_t* front[2];   // [n] K-SET frontiers
     uint32_t* sort_hist; // [8][256]
     uint32_t* sort_status;
@@ -84,12 +86,13 @@ struct BulkArgs {
     int32_t prm_rows;       // PART LDS parameter rows: widest registered procedure
     int32_t pipe_bits;      // pipelined PART cell table: 1 << pipe_bits slots
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
-    int32_t pad_;
+    int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane
     Ws ws;
 };
 
 constexpr int kPrepBlocks = 1024;
-constexpr int kPartLdsMax = 120 * 1024;  // dynamic LDS cap of one PART wave
+constexpr int kPartLdsMax = 120 * 1024;  // dynamic LDS cap of one PART workgroup
+constexpr int kLongPart = 32;            // PART: shortest partition given a workgroup
 constexpr int kScanItems = 8;
 constexpr int kScanTile = GTX_BLOCK * kScanItems;
 constexpr int kRankItems = 8;

@@ -11,9 +11,14 @@
 //              target, the transaction runs, every counter is incremented.
 //              Workgroups claim 256-transaction windows in timestamp order
 //              and group each window by type.
-//   k_part     PART (Section 5.2): one lane per partition; binary search of
-//              the partition's range in the partition-sorted transactions,
-//              then its transactions run one after another.
+//   k_part_pipe PART (Section 5.2), few long partitions: one workgroup per
+//              partition; a staging wave puts each chunk's cells in an LDS
+//              table while lane 0 of the serial wave runs the previous chunk
+//              against it, one transaction after another.  k_part_wave is the
+//              one-wave form (stage, then run).
+//   k_part     PART, many small partitions: one lane per partition; binary
+//              search of the partition's range in the partition-sorted
+//              transactions, then its transactions run one after another.
 //   k_finalize batched update (Section 3.2): advance append-table row counts;
 //              publish statistics.
 #include "engine.h"
@@ -196,6 +201,36 @@ __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* 
                 const int32_t q2 = a.ws.srt_txn[j];
                 if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
             }
+        }
+    }
+}
+
+// Only when K-SET runs: the transaction of each operation in item-sorted
+// order (the read runs K-SET releases) ...
+__global__ __launch_bounds__(GTX_BLOCK) void k_kset_sorted_txn(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
+    const int64_t m = st->m;
+    const uint32_t* val = a.ws.pv[a.key_passes & 1];
+    for (int64_t i = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * GTX_BLOCK)
+        a.ws.srt_txn[i] = a.ws.op_txn[val[i] >> 1];
+}
+
+// ... and each operation's first successor transaction and its type, so a
+// wave releases successors without gathers on its own path.
+__global__ __launch_bounds__(GTX_BLOCK) void k_kset_succ(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
+    const int64_t m = st->m;
+    for (int64_t o = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; o < m;
+         o += (int64_t)gridDim.x * GTX_BLOCK) {
+        OpInfo& inf = a.ws.op_info[o];
+        const int32_t slo = inf.slo, shi = inf.shi;
+        if (slo < shi) {
+            const int32_t q = a.ws.srt_txn[slo];
+            inf.s0 = q;
+            inf.s0ty = a.ws.tty[q];
         }
     }
 }
@@ -441,23 +476,75 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
 // ---------------------------------------------------------------------------
 // PART
 
-__device__ __forceinline__ void part_range(const BulkArgs& a, const uint32_t* key, int64_t q,
-                                           int64_t* lo_out, int64_t* end_out) {
-    // the partition's range in the partition-sorted bulk, by binary search
-    int64_t lo = 0, hi = a.n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (key[mid] < (uint32_t)q) lo = mid + 1;
-        else hi = mid;
+// ---- PART partitions ------------------------------------------------------
+// After the partition sort, the non-empty partitions are listed in order:
+// heads[b] is the first sorted position of the b-th one and heads[b + 1] its
+// end (heads[n_heads] is where the transactions PART does not run begin).
+constexpr int kHeadItems = 8;
+constexpr int kHeadTile = GTX_BLOCK * kHeadItems;
+
+__device__ __forceinline__ bool part_head(const uint32_t* key, int64_t i, uint32_t sentinel) {
+    const uint32_t k = key[i];
+    return k < sentinel && (i == 0 || key[i - 1] != k);
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_heads_up(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    __shared__ int lds[GTX_WAVES + 1];
+    const uint32_t* key = a.ws.qk[a.part_passes & 1];
+    const int64_t i0 = (int64_t)blockIdx.x * kHeadTile + (int64_t)threadIdx.x * kHeadItems;
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < kHeadItems; ++j)
+        if (i0 + j < a.n) c += part_head(key, i0 + j, (uint32_t)a.n_parts);
+    int tot;
+    (void)block_excl_sum(c, &tot, lds);
+    if (threadIdx.x == 0) a.ws.heads_tmp[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_heads_mid(BulkArgs a, int nb) {
+    GtxState* st = a.ws.st;
+    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    __shared__ int lds[GTX_WAVES + 1];
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += GTX_BLOCK) {
+        const int b = b0 + (int)threadIdx.x;
+        const int v = b < nb ? a.ws.heads_tmp[b] : 0;
+        int tot;
+        const int ex = block_excl_sum(v, &tot, lds);
+        if (b < nb) a.ws.heads_tmp[b] = carry + ex;
+        carry += tot;
     }
-    int64_t end = lo, hi2 = a.n;
-    while (end < hi2) {
-        int64_t mid = (end + hi2) >> 1;
-        if (key[mid] <= (uint32_t)q) end = mid + 1;
-        else hi2 = mid;
+    if (threadIdx.x == 0) {
+        st->n_heads = carry;
+        a.ws.heads[carry] = (int32_t)a.n;  // no transaction outside PART
     }
-    *lo_out = lo;
-    *end_out = end;
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_heads_down(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    __shared__ int lds[GTX_WAVES + 1];
+    const uint32_t* key = a.ws.qk[a.part_passes & 1];
+    const uint32_t sentinel = (uint32_t)a.n_parts;
+    const int64_t i0 = (int64_t)blockIdx.x * kHeadTile + (int64_t)threadIdx.x * kHeadItems;
+    bool h[kHeadItems];
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < kHeadItems; ++j) {
+        const int64_t i = i0 + j;
+        h[j] = i < a.n && part_head(key, i, sentinel);
+        c += h[j];
+        // first transaction PART does not run: the end of the last partition
+        if (i < a.n && key[i] == sentinel && (i == 0 || key[i - 1] != sentinel))
+            a.ws.heads[st->n_heads] = (int32_t)i;
+    }
+    int tot;
+    int at = a.ws.heads_tmp[blockIdx.x] + block_excl_sum(c, &tot, lds);
+#pragma unroll
+    for (int j = 0; j < kHeadItems; ++j)
+        if (h[j]) a.ws.heads[at++] = (int32_t)(i0 + j);
 }
 
 __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int64_t aborted) {
@@ -468,18 +555,20 @@ __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int6
     }
 }
 
-// One lane per partition: for many small partitions.
+// One lane per short partition (fewer than a.long_part transactions): its
+// transactions run one after another, in place.
 __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
-    const int64_t q = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x;
-    const int src = a.part_passes & 1;
+    const int nh = st->n_heads;
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     int64_t committed = 0, aborted = 0;
-    if (q < a.n_parts) {
-        int64_t lo, end;
-        part_range(a, a.ws.qk[src], q, &lo, &end);
+    for (int64_t b = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; b < nh;
+         b += (int64_t)gridDim.x * GTX_BLOCK) {
+        const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
+        if (end - lo >= a.long_part) continue;  // a workgroup runs it
         for (int64_t i = lo; i < end; ++i) {
-            const int32_t p = (int32_t)a.ws.qv[src][i];
+            const int32_t p = (int32_t)pos[i];
             const int32_t s = run_at(a, p, a.ws.tty[p]);
             committed += s == GPUTX_COMMIT;
             aborted += s == GPUTX_ABORT;
@@ -499,7 +588,7 @@ struct PartChunk {
     int32_t* t;     // [64] type
     int32_t* np;    // [64] parameters loaded
     int32_t* st;    // [64] status
-    uint16_t* cs;   // [cells][64] cell table slot of each of the transaction's cells
+    uint32_t* cs;   // [cells][64] LDS address of each of the transaction's staged cells
 };
 
 // The chunk's table cells, staged in LDS: an open-addressing hash table keyed
@@ -513,11 +602,16 @@ struct __attribute__((aligned(16))) CellSlot {
     int64_t val;
 };
 struct CellTab {
-    GTX_LDS CellSlot* slot;  // [1 << bits]
+    GTX_LDS CellSlot* slot;  // [1 << bits], then one sink slot outside the table
     GTX_LDS int32_t* list;   // claimed slots
     GTX_LDS int32_t* nlist;
     int bits;
 };
+// LDS address of a slot's value (16-byte slots: bit 3 is set), and of the
+// sink slot's key (bit 3 clear), which stands for an ordinal no cell backs.
+__device__ __forceinline__ uint32_t lds_addr(GTX_LDS const void* p) { return (uint32_t)(uintptr_t)p; }
+__device__ __forceinline__ uint32_t cell_val_addr(const CellTab& t, uint32_t h) { return lds_addr(&t.slot[h].val); }
+__device__ __forceinline__ uint32_t cell_sink_addr(const CellTab& t) { return lds_addr(&t.slot[1u << t.bits].key); }
 template <class V>
 __device__ __forceinline__ uint64_t cell_key(GTX_GLOBAL V* p) {
     return (uint64_t)p | (sizeof(V) == 8 ? 2u : 0u);
@@ -526,20 +620,20 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
     return ((uint32_t)(key >> 2) * 0x9E3779B1u) >> (32 - bits);
 }
 
-// Fetch side: each lane claims the cells of its transaction and records the
-// slot of each of its cell ordinals.  The first claimant of a cell loads it
+// Fetch side: each lane claims the cells of its transaction and records,
+// per cell ordinal, the LDS address of the cell's staged value.  The first claimant of a cell loads it
 // from global memory into the slot; a cell the procedure may write is marked
 // written (bit 0), so it is stored back when the table is flushed.
 struct CellClaim {
     CellTab tab;
-    uint16_t* cs;  // the lane's column of slot ids
+    uint32_t* cs;  // the lane's column of cell addresses
     template <class V>
     __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
         const V v = *p;  // issued before the claim; kept only by the winner
         const uint64_t key = cell_key(p);
         const uint32_t mask = (1u << tab.bits) - 1;
         uint32_t h = cell_hash(key, tab.bits);
-        uint32_t got = 0xffff;  // no free slot: the serial side reports the miss
+        uint32_t got = cell_sink_addr(tab);  // no free slot: the serial side reports the miss
         for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1) & mask) {
             uint64_t prev = 0;
             __hip_atomic_compare_exchange_strong(&tab.slot[h].key, &prev, key | (w ? 1u : 0u),
@@ -550,47 +644,46 @@ struct CellClaim {
                 const int e = __hip_atomic_fetch_add(tab.nlist, 1, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
                 tab.list[e] = (int32_t)h;
-                got = h;
+                got = cell_val_addr(tab, h);
                 break;
             }
             if ((prev & ~(uint64_t)1) == key) {  // staged already
                 if (w && !(prev & 1))
                     __hip_atomic_fetch_or(&tab.slot[h].key, (uint64_t)1, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-                got = h;
+                got = cell_val_addr(tab, h);
                 break;
             }
         }
-        cs[ord * 64] = (uint16_t)got;
+        cs[ord * 64] = got;
     }
 };
 
 // Serial side: the procedures' accessor over the staged cells.  The fetch
-// lanes resolved every cell ordinal of the transaction to its slot, so a
-// reference is one LDS read and a write one LDS store: no address or hash
-// arithmetic on the serial path, and no global access (no store can then
-// alias the type descriptor, whose fields stay in registers).  An ordinal
-// the cell list did not name carries slot id 0xffff; it is recorded in miss
-// (bit 16) and fails the bulk with GPUTX_E_INTERNAL.
+// lanes resolved every cell ordinal of the transaction to the LDS address
+// of its staged value, so a reference is one LDS read and a write one LDS
+// store: no address or hash arithmetic on the serial path, and no global
+// access (no store can then alias the type descriptor, whose fields stay in
+// registers).  An ordinal the cell list did not name points at the sink
+// slot; its bit 3 is clear, which the AND of all addresses in *seen shows,
+// and the bulk fails with GPUTX_E_INTERNAL.
 struct LdsAcc {
-    GTX_LDS CellSlot* slot;
-    uint32_t mask;
-    const uint32_t* ids;  // slot id per cell ordinal (registers)
-    uint32_t* miss;
+    const uint32_t* ids;  // LDS address per cell ordinal (registers)
+    uint32_t* seen;
     template <class V>
     struct Ref {
-        GTX_LDS CellSlot* s;
+        GTX_LDS int64_t* s;
         int64_t v;
         __device__ __forceinline__ V get() const { return (V)v; }
-        __device__ __forceinline__ void set(V x) { s->val = (int64_t)x; v = (int64_t)x; }
+        __device__ __forceinline__ void set(V x) { *s = (int64_t)x; v = (int64_t)x; }
     };
     template <class V>
     __device__ __forceinline__ Ref<V> ref(int ord, GTX_GLOBAL V*) {
-        const uint32_t id = ids[ord];
-        *miss |= id + 1;
+        const uint32_t at = ids[ord];
+        *seen &= at;
         Ref<V> r;
-        r.s = slot + (id & mask);
-        r.v = r.s->val;
+        r.s = (GTX_LDS int64_t*)(uintptr_t)at;
+        r.v = *r.s;
         return r;
     }
     template <class V>
@@ -617,7 +710,8 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4;
     if (lane_id() != 0) return;
     const int rows = a.prm_rows;
-    uint32_t miss = 0;
+    const uint32_t sink = cell_sink_addr(tab);
+    uint32_t seen = ~0u;
     int64_t nxt[NP];
     uint32_t nid[NC];
     if constexpr (ahead) {
@@ -646,9 +740,9 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
             for (int r = 0; r < NP; ++r)
                 if (P != 0 || r < rows) prm[r] = c.prm[r * 64 + k];
 #pragma unroll
-            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * 64 + k] : 0xffffu;
+            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * 64 + k] : sink;
         }
-        LdsAcc acc{tab.slot, (1u << tab.bits) - 1, ids, &miss};
+        LdsAcc acc{ids, &seen};
         int64_t res[GTX_MAX_RESULTS];
         int32_t s;
         if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
@@ -659,21 +753,21 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
         committed += s == GPUTX_COMMIT;
         aborted += s == GPUTX_ABORT;
     }
-    if (miss & 0x10000u) fail(a.ws.st, GPUTX_E_INTERNAL);
+    if (!(seen & 8u)) fail(a.ws.st, GPUTX_E_INTERNAL);
 }
 
 // LDS of the PART kernels: chunk buffers, then the cell table and its list.
 __host__ __device__ inline size_t part_chunk_bytes(int rows, int cells) {
     return (size_t)64 * 8 * (GTX_MAX_RESULTS + rows + 4) + (size_t)64 * 4 * 3 +
-           (size_t)64 * 2 * ((cells + 7) & ~7);
+           (size_t)64 * 4 * cells;
 }
 size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.cell_bits) +
-           (size_t)4 * (64 * a.cells_max + 4);
+           sizeof(CellSlot) + (size_t)4 * (64 * a.cells_max + 4);
 }
 size_t part_pipe_lds(const BulkArgs& a) {
     return 2 * part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.pipe_bits) +
-           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
+           sizeof(CellSlot) + (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
 }
 
 __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, int rows) {
@@ -687,7 +781,7 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, int rows
     c.t = reinterpret_cast<int32_t*>(c.idx + 64);
     c.np = c.t + 64;
     c.st = c.np + 64;
-    c.cs = reinterpret_cast<uint16_t*>(c.st + 64);
+    c.cs = reinterpret_cast<uint32_t*>(c.st + 64);
     return c;
 }
 
@@ -714,7 +808,7 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     c.idx[lane] = x.i;
     c.t[lane] = t;
     c.np[lane] = x.np;
-    for (int r = 0; r < a.cells_max; ++r) c.cs[r * 64 + lane] = 0xffff;
+    for (int r = 0; r < a.cells_max; ++r) c.cs[r * 64 + lane] = cell_sink_addr(tab);
     CellClaim claim{tab, c.cs + lane};
     txn_cells(a.types[t], x.prm, claim);
     AppendOnlyAcc ap;
@@ -785,22 +879,20 @@ __device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, 
     CellTab tab;
     tab.bits = bits;
     tab.slot = (GTX_LDS CellSlot*)base;
-    tab.list = (GTX_LDS int32_t*)(tab.slot + (1 << bits));
+    tab.list = (GTX_LDS int32_t*)(tab.slot + (1 << bits) + 1);
     tab.nlist = tab.list + list_cap;
     return tab;
 }
 
-// One wave per partition, still one serial thread of control (Section 5.2).
-// For each chunk of 64 of the partition's transactions the lanes load the
-// signatures into LDS, write their appended rows and stage every cell the
+// One wave per long partition, still one serial thread of control (Section
+// 5.2).  For each chunk of 64 of the partition's transactions the lanes load
+// the signatures into LDS, write their appended rows and stage every cell the
 // chunk may use in the LDS cell table; lane 0 then runs the 64 in order
 // against the table; finally the owning lanes write statuses, results and
-// the cells that were written.
+// the cells that were written.  Workgroups take long partitions in turn.
 __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     GtxState* st = a.ws.st;
-    if (failed(st) || st->chosen != GPUTX_PART) return;
-    const int64_t q = blockIdx.x;
-    if (q >= a.n_parts) return;
+    if (failed(st) || st->chosen != GPUTX_PART || (int)blockIdx.x >= st->n_heads) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int lane = lane_id();
     const PartChunk c = part_chunk_at(part_lds, a.prm_rows);
@@ -810,36 +902,37 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
 
-    const int src = a.part_passes & 1;
-    const uint32_t* pos = a.ws.qv[src];
-    int64_t lo, end;
-    part_range(a, a.ws.qk[src], q, &lo, &end);
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
+    const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
-    for (int64_t c0 = lo; c0 < end; c0 += 64) {
-        part_fetch(a, c, tab, pos, c0, end, lane);
-        __syncthreads();
-        part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
-        __syncthreads();
-        part_writeout(a, c, c0, end, lane);
-        part_flush(tab, lane, 64);
-        __syncthreads();
-        if (lane == 0) *tab.nlist = 0;
-        __syncthreads();
+    for (int b = blockIdx.x; b < nh; b += gridDim.x) {
+        const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
+        if (end - lo < a.long_part) continue;  // a lane of k_part runs it
+        for (int64_t c0 = lo; c0 < end; c0 += 64) {
+            part_fetch(a, c, tab, pos, c0, end, lane);
+            __syncthreads();
+            part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+            __syncthreads();
+            part_writeout(a, c, c0, end, lane);
+            part_flush(tab, lane, 64);
+            __syncthreads();
+            if (lane == 0) *tab.nlist = 0;
+            __syncthreads();
+        }
     }
     add_counts(st, committed, aborted);
 }
 
-// Pipelined PART: one 128-thread workgroup per partition.  Wave 0 (lane 0)
-// runs chunk k serially while wave 1 writes out chunk k-1 and stages chunk
-// k+1 in the other buffer.  The cell table persists across chunks (a cell
-// chunk k+1 shares with chunk k is found staged, with chunk k's writes
-// applied by the time chunk k+1 runs); it is flushed and emptied when a
-// further chunk might fill it past half, at a point where no wave probes it,
-// so linear probing never sees a deleted slot.
+// Pipelined PART: one 128-thread workgroup per long partition at a time.
+// Wave 0 (lane 0) runs chunk k serially while wave 1 writes out chunk k-1
+// and stages chunk k+1 in the other buffer.  The cell table persists across
+// chunks (a cell chunk k+1 shares with chunk k is found staged, with chunk
+// k's writes applied by the time chunk k+1 runs); it is flushed and emptied
+// when a further chunk might fill it past half, and at the end of each
+// partition, at points where no wave probes it, so linear probing never
+// sees a deleted slot.
 __global__ __launch_bounds__(128) void k_part_pipe(BulkArgs a) {
     GtxState* st = a.ws.st;
-    const int64_t q = blockIdx.x;
-    if (q >= a.n_parts) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -851,47 +944,51 @@ __global__ __launch_bounds__(128) void k_part_pipe(BulkArgs a) {
     GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk
     // one decision for the whole workgroup (another workgroup may fail the
     // bulk meanwhile; both waves must still meet at every barrier)
-    if (tid == 0) flag[0] = !failed(st) && st->chosen == GPUTX_PART;
+    if (tid == 0) flag[0] = !failed(st) && st->chosen == GPUTX_PART && (int)blockIdx.x < st->n_heads;
     __syncthreads();
     if (!flag[0]) return;
     for (int s = tid; s < cap; s += 128) tab.slot[s].key = 0;
     if (tid == 0) *tab.nlist = 0;
 
-    const int src = a.part_passes & 1;
-    const uint32_t* pos = a.ws.qv[src];
-    int64_t lo, end;
-    part_range(a, a.ws.qk[src], q, &lo, &end);
-    const int64_t nch = (end - lo + 63) / 64;
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
+    const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
     __syncthreads();
-    if (wave == 1) part_fetch(a, buf(0), tab, pos, lo, end, lane);
-    __syncthreads();
-    for (int64_t k = 0; k < nch; ++k) {
-        const int64_t c0 = lo + 64 * k;
-        if (wave == 0) {
-            part_run_chunk(a, buf(k), tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
-        } else {
-            if (k > 0) part_writeout(a, buf(k - 1), c0 - 64, end, lane);
-            bool flush = false;
-            if (k + 1 < nch) {
-                flush = *tab.nlist + 64 * a.cells_max > cap / 2;
-                if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
-            }
-            if (lane == 0) flag[k & 1] = flush;
-        }
+    for (int b = blockIdx.x; b < nh; b += gridDim.x) {
+        const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
+        if (end - lo < a.long_part) continue;  // a lane of k_part runs it
+        const int64_t nch = (end - lo + 63) / 64;
+        if (wave == 1) part_fetch(a, buf(0), tab, pos, lo, end, lane);
         __syncthreads();
-        if (flag[k & 1]) {  // same value in every wave
-            part_flush(tab, tid, 128);
+        for (int64_t k = 0; k < nch; ++k) {
+            const int64_t c0 = lo + 64 * k;
+            if (wave == 0) {
+                part_run_chunk(a, buf(k), tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+            } else {
+                if (k > 0) part_writeout(a, buf(k - 1), c0 - 64, end, lane);
+                bool flush = false;
+                if (k + 1 < nch) {
+                    flush = *tab.nlist + 64 * a.cells_max > cap / 2;
+                    if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+                }
+                if (lane == 0) flag[k & 1] = flush;
+            }
             __syncthreads();
-            if (tid == 0) *tab.nlist = 0;
-            __syncthreads();
-            if (wave == 1) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
-            __syncthreads();
+            if (flag[k & 1]) {  // same value in every wave
+                part_flush(tab, tid, 128);
+                __syncthreads();
+                if (tid == 0) *tab.nlist = 0;
+                __syncthreads();
+                if (wave == 1) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+                __syncthreads();
+            }
         }
-    }
-    if (nch > 0) {
+        // the last chunk's outcomes and every staged cell; the table is empty after
         if (wave == 1) part_writeout(a, buf(nch - 1), lo + 64 * (nch - 1), end, lane);
         part_flush(tab, tid, 128);
+        __syncthreads();
+        if (tid == 0) *tab.nlist = 0;
+        __syncthreads();
     }
     add_counts(st, committed, aborted);
 }
@@ -980,23 +1077,38 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         sp.gate = &a.ws.st->run_part; sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
         sort_pairs(sp, s);
     }
+    if (part) {
+        const unsigned nbh = (unsigned)std::max<int64_t>(1, (a.n + kHeadTile - 1) / kHeadTile);
+        hipLaunchKernelGGL(k_heads_up, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_heads_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, (int)nbh);
+        hipLaunchKernelGGL(k_heads_down, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+    }
     pm.mark(PH_PARTSORT, s);
     if (part) {
-        if (a.part_pipeline && a.n_parts <= 8192 && part_pipe_lds(a) <= (size_t)kPartLdsMax) {
-            hipLaunchKernelGGL(k_part_pipe, dim3((unsigned)a.n_parts), dim3(128), part_pipe_lds(a), s, a);
-        } else if (a.n_parts <= 8192 && part_wave_lds(a) <= (size_t)kPartLdsMax) {  // one wave each
-            hipLaunchKernelGGL(k_part_wave, dim3((unsigned)a.n_parts), dim3(64), part_wave_lds(a), s, a);
-        } else {
-            const unsigned blocks = (unsigned)std::max<int64_t>(1, (a.n_parts + GTX_BLOCK - 1) / GTX_BLOCK);
-            hipLaunchKernelGGL(k_part, dim3(blocks), dim3(GTX_BLOCK), 0, s, a);
-        }
+        // long partitions: a workgroup each with the LDS cell table; short
+        // ones: a lane each
+        BulkArgs b = a;
+        const bool pipe = a.part_pipeline && part_pipe_lds(a) <= (size_t)kPartLdsMax;
+        const bool wave = !pipe && part_wave_lds(a) <= (size_t)kPartLdsMax;
+        b.long_part = (pipe || wave) ? kLongPart : INT32_MAX;
+        const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
+        if (pipe)
+            hipLaunchKernelGGL(k_part_pipe, dim3(groups), dim3(128), part_pipe_lds(a), s, b);
+        else if (wave)
+            hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
+        const unsigned lanes = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((std::min<int64_t>(a.n, a.n_parts) + GTX_BLOCK - 1) / GTX_BLOCK, 4096));
+        hipLaunchKernelGGL(k_part, dim3(lanes), dim3(GTX_BLOCK), 0, s, b);
     }
     pm.mark(PH_PART, s);
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_TPL || a.strategy == GPUTX_PART)
         hipLaunchKernelGGL(k_tpl, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_TPL, s);
-    if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_KSET)
+    if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_KSET) {
+        hipLaunchKernelGGL(k_kset_sorted_txn, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_kset_succ, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
+    }
     pm.mark(PH_KSET, s);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
     pm.mark(PH_FINAL, s);

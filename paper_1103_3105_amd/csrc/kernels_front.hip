@@ -125,11 +125,14 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_scan_up(BulkArgs a, int K, int nb
     }
 }
 
+// Block k < K scans row k of the per-block sums; block K adds up the
+// per-block type counts.  The rows are independent, so they run side by side.
 __global__ __launch_bounds__(GTX_BLOCK) void k_scan_mid(BulkArgs a, int K, int nb) {
     GtxState* st = a.ws.st;
     if (bulk_failed(st)) return;
     __shared__ int lds[GTX_WAVES + 1];
-    for (int k = 0; k < K; ++k) {
+    const int k = blockIdx.x;
+    if (k < K) {
         int64_t running = 0;
         for (int c0 = 0; c0 < nb; c0 += GTX_BLOCK) {
             int idx = c0 + threadIdx.x;
@@ -140,31 +143,31 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_scan_mid(BulkArgs a, int K, int n
             running += tot;
         }
         if (threadIdx.x == 0) {
-            if (k == 0) st->m = running;
-            else st->app_total[k - 1] = running;
+            if (k == 0) {
+                st->m = running;
+                // (append capacity depends on the tables' row counts, so it is
+                // checked at the start of execution, not here)
+                if (running > a.mcap) set_error(st, GPUTX_E_CAPACITY);
+            } else {
+                st->app_total[k - 1] = running;
+            }
         }
+        return;
     }
-    {
-        // type counts: 16 threads per type, each over a stride of the blocks
-        __shared__ int part[GTX_BLOCK];
-        const int nblk = (int)std::min<int64_t>(kPrepBlocks, (a.n + GTX_BLOCK - 1) / GTX_BLOCK);
-        const int ty = threadIdx.x % GPUTX_MAX_TYPES, lane16 = threadIdx.x / GPUTX_MAX_TYPES;
-        int c = 0;
-        for (int b = lane16; b < nblk; b += GTX_BLOCK / GPUTX_MAX_TYPES)
-            c += a.ws.tcnt_tmp[b * GPUTX_MAX_TYPES + ty];
-        part[threadIdx.x] = c;
-        __syncthreads();
-        if (threadIdx.x < GPUTX_MAX_TYPES) {
-            int tot = 0;
-            for (int k = 0; k < GTX_BLOCK / GPUTX_MAX_TYPES; ++k) tot += part[k * GPUTX_MAX_TYPES + threadIdx.x];
-            st->type_count[threadIdx.x] = tot;
-        }
-    }
+    // type counts: 16 threads per type, each over a stride of the blocks
+    __shared__ int part[GTX_BLOCK];
+    const int nblk = (int)std::min<int64_t>(kPrepBlocks, (a.n + GTX_BLOCK - 1) / GTX_BLOCK);
+    const int ty = threadIdx.x % GPUTX_MAX_TYPES, lane16 = threadIdx.x / GPUTX_MAX_TYPES;
+    constexpr int kStride = GTX_BLOCK / GPUTX_MAX_TYPES;
+    int c = 0;
+#pragma unroll 8
+    for (int b = lane16; b < nblk; b += kStride) c += a.ws.tcnt_tmp[b * GPUTX_MAX_TYPES + ty];
+    part[threadIdx.x] = c;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // (append capacity depends on the tables' row counts, so it is checked
-        // at the start of execution, not here)
-        if (st->m > a.mcap) set_error(st, GPUTX_E_CAPACITY);
+    if (threadIdx.x < GPUTX_MAX_TYPES) {
+        int tot = 0;
+        for (int j = 0; j < kStride; ++j) tot += part[j * GPUTX_MAX_TYPES + threadIdx.x];
+        st->type_count[threadIdx.x] = tot;
     }
 }
 
@@ -438,7 +441,6 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
         const int32_t rank = cur.segs;
         const bool w = val[j] & 1u;
         const int32_t o = (int32_t)(val[j] >> 1);
-        const int32_t txn = a.ws.op_txn[o];
         const int32_t rs = max(gs, Aex);  // start of the read run that ends at i
         const int32_t rel = (int32_t)i - gs;
         // lock target: completed ops of the group this op waits for
@@ -460,7 +462,6 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
             }
             in_c = Aex > gs ? 1 : 0;
         }
-        a.ws.srt_txn[i] = txn;
         OpInfo inf;
         inf.grp = g;
         inf.tgt = tgt;
@@ -468,12 +469,8 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
         inf.shi = shi;
         inf.rank = rank;
         inf.in = in_c;
-        inf.s0 = -1;
+        inf.s0 = -1;    // filled by k_kset_succ when K-SET runs
         inf.s0ty = -1;
-        if (slo < shi) {  // first successor's transaction, so K-SET needs no gather
-            inf.s0 = a.ws.op_txn[in.val[slo] >> 1];
-            inf.s0ty = a.ws.tty[inf.s0];
-        }
         a.ws.op_info[o] = inf;
         if (i == gs) a.ws.grp_cnt[g] = 0;
     }
@@ -564,7 +561,7 @@ void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     const int K = 1 + a.n_app;
     const int nb = (int)blocks_for(a.n, kScanTile);
     hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
-    hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, K, nb);
+    hipLaunchKernelGGL(k_scan_mid, dim3(K + 1), dim3(GTX_BLOCK), 0, s, a, K, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
     pm.mark(PH_PREPARE, s);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);

@@ -390,6 +390,8 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.grp_cnt = L.take<int32_t>(mcap);
     w.qk[0] = L.take<uint32_t>(n); w.qk[1] = L.take<uint32_t>(n);
     w.qv[0] = L.take<uint32_t>(n); w.qv[1] = L.take<uint32_t>(n);
+    w.heads = L.take<int32_t>(n + 1);
+    w.heads_tmp = L.take<int32_t>(std::max<int64_t>(1, (n + 2047) / 2048));
     w.front[0] = L.take<int32_t>(n); w.front[1] = L.take<int32_t>(n);
     w.sort_hist = L.take<uint32_t>(8 * 256);
     size_t sw = std::max({sort_status_words(n, 8), sort_status_words(mcap, h->key_passes),

@@ -143,6 +143,29 @@ def test_part_forms(workload, pipeline):
     assert_parity(s, g, o, bulk)
 
 
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_part_partition_lengths(pipeline):
+    """Partitions of 1, 31, 32, 33, 64, 65 and 200 transactions in one bulk
+    (interleaved in timestamp order): the short ones run one per lane, the
+    long ones (32 and more) one per workgroup with the LDS cell table."""
+    counts = [1, 31, 32, 33, 64, 65, 200]
+    nb, tpb, apt = len(counts), 3, 4
+    rng = np.random.default_rng(64)
+    n = sum(counts)
+    tabs = wl.bank_tables(rng, nb, nb * tpb, nb * tpb * apt, history_capacity=n)
+    branch = np.repeat(np.arange(nb), counts)
+    rng.shuffle(branch)
+    teller = branch * tpb + rng.integers(0, tpb, n)
+    acct = teller * apt + rng.integers(0, apt, n)
+    delta = rng.integers(-99_999, 100_000, n)
+    bulk = wl.Bulk(np.zeros(n, np.int32), np.stack([acct, teller, branch, delta]).astype(np.int64),
+                   np.arange(n, dtype=np.int64))
+    _say("part lengths", pipeline)
+    s, g, o = run_both(tabs, wl.bank_types(), bulk, 3, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2, s.as_dict()
+    assert_parity(s, g, o, bulk)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 63, 4097])
 def test_small_and_empty_bulks(n):
     tabs, types, bulk = util.small_bank(24, max(n, 1), n_branch=2, tpb=2, apt=5)
