@@ -87,11 +87,13 @@ struct BulkArgs {
     int32_t pipe_bits;      // pipelined PART cell table: 1 << pipe_bits slots
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
     int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane
+    int32_t res_rows;       // PART LDS result rows: most results of a registered procedure
+    int32_t pad_;
     Ws ws;
 };
 
 constexpr int kPrepBlocks = 1024;
-constexpr int kPartLdsMax = 120 * 1024;  // dynamic LDS cap of one PART workgroup
+constexpr int kPartLdsMax = 160 * 1024;  // dynamic LDS cap of one PART workgroup (gfx950: 160 KB per CU)
 constexpr int kLongPart = 32;            // PART: shortest partition given a workgroup
 constexpr int kScanItems = 8;
 constexpr int kScanTile = GTX_BLOCK * kScanItems;
@@ -120,6 +122,6 @@ int exec_resident_blocks_per_cu();
 size_t part_wave_lds(const BulkArgs& a);
 size_t part_pipe_lds(const BulkArgs& a);
 // one-time kernel attributes (large dynamic LDS for PART)
-void exec_init_attributes();
+void exec_init_attributes(int dev);
 
 }  // namespace gtx

@@ -577,18 +577,20 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Signatures of one PART chunk staged in LDS, one column per transaction.
+// Signatures of one PART chunk of cw transactions staged in LDS, one column
+// per transaction.
 struct PartChunk {
-    int64_t* res;   // [16][64] results
-    int64_t* prm;   // [npb][64] parameters
-    int64_t* ts;    // [64]
-    int64_t* app0;  // [64]
-    int64_t* app1;  // [64]
-    int64_t* idx;   // [64] input index (status / results slot)
-    int32_t* t;     // [64] type
-    int32_t* np;    // [64] parameters loaded
-    int32_t* st;    // [64] status
-    uint32_t* cs;   // [cells][64] LDS address of each of the transaction's staged cells
+    int64_t* res;   // [res rows][cw] results
+    int64_t* prm;   // [parameter rows][cw] parameters
+    int64_t* ts;    // [cw]
+    int64_t* app0;  // [cw]
+    int64_t* app1;  // [cw]
+    int64_t* idx;   // [cw] input index (status / results slot)
+    int32_t* t;     // [cw] type
+    int32_t* np;    // [cw] parameters loaded
+    int32_t* st;    // [cw] status
+    uint32_t* cs;   // [cells][cw] LDS address of each of the transaction's staged cells
+    int cw;
 };
 
 // The chunk's table cells, staged in LDS: an open-addressing hash table keyed
@@ -627,6 +629,7 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 struct CellClaim {
     CellTab tab;
     uint32_t* cs;  // the lane's column of cell addresses
+    int cw;        // its stride
     template <class V>
     __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
         const V v = *p;  // issued before the claim; kept only by the winner
@@ -655,7 +658,7 @@ struct CellClaim {
                 break;
             }
         }
-        cs[ord * 64] = got;
+        cs[ord * cw] = got;
     }
 };
 
@@ -698,90 +701,104 @@ struct LdsAcc {
 // cells.  Statuses and results go to LDS; the owning lanes write them out
 // after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
 // mixed types.  The LDS parameter rows past a transaction's own are zero, so
-// they are read without a bound; for narrow procedures the next
-// transaction's parameters and slot ids are read while the current one runs.
+// they are read without a bound.  For narrow procedures the next
+// transaction's parameters and cell addresses are read while the current
+// one runs.
 template <int P>
 __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
                                             const CellTab& tab, int cnt, int64_t& committed,
                                             int64_t& aborted) {
     constexpr int NP = proc_params(P);  // parameters the procedure can read
-    constexpr int NR = proc_results(P); // results it can write
+    constexpr int NR = proc_results(P); // results it can write (P == 0: up to res_rows)
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4;
     if (lane_id() != 0) return;
     const int rows = a.prm_rows;
+    const int cw = c.cw;
     const uint32_t sink = cell_sink_addr(tab);
     uint32_t seen = ~0u;
-    int64_t nxt[NP];
-    uint32_t nid[NC];
     if constexpr (ahead) {
+        int64_t nxt[NP];
+        uint32_t nid[NC];
 #pragma unroll
-        for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * 64];
+        for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * cw];
 #pragma unroll
-        for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * 64];
-    }
-    for (int k = 0; k < cnt; ++k) {
-        int64_t prm[GTX_MAX_PARAMS];
-        uint32_t ids[NC];
+        for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * cw];
+        for (int k = 0; k < cnt; ++k) {
+            int64_t prm[GTX_MAX_PARAMS];
+            uint32_t ids[NC];
 #pragma unroll
-        for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = 0;
-        if constexpr (ahead) {
-#pragma unroll
-            for (int r = 0; r < NP; ++r) prm[r] = nxt[r];
+            for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? nxt[r] : 0;
 #pragma unroll
             for (int r = 0; r < NC; ++r) ids[r] = nid[r];
             const int kn = k + 1 < cnt ? k + 1 : k;
 #pragma unroll
-            for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * 64 + kn];
+            for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * cw + kn];
 #pragma unroll
-            for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * 64 + kn];
-        } else {
+            for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * cw + kn];
+            LdsAcc acc{ids, &seen};
+            int64_t res[GTX_MAX_RESULTS];
+            const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+            c.st[k] = s;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
+            committed += s == GPUTX_COMMIT;
+            aborted += s == GPUTX_ABORT;
+        }
+    } else {
+        for (int k = 0; k < cnt; ++k) {
+            int64_t prm[GTX_MAX_PARAMS];
+            uint32_t ids[NC];
+#pragma unroll
+            for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = 0;
 #pragma unroll
             for (int r = 0; r < NP; ++r)
-                if (P != 0 || r < rows) prm[r] = c.prm[r * 64 + k];
+                if (P != 0 || r < rows) prm[r] = c.prm[r * cw + k];
 #pragma unroll
-            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * 64 + k] : sink;
+            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * cw + k] : sink;
+            LdsAcc acc{ids, &seen};
+            int64_t res[GTX_MAX_RESULTS];
+            int32_t s;
+            if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+            else s = txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
+            c.st[k] = s;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+                if (P != 0 || r < a.res_rows) c.res[r * cw + k] = res[r];
+            committed += s == GPUTX_COMMIT;
+            aborted += s == GPUTX_ABORT;
         }
-        LdsAcc acc{ids, &seen};
-        int64_t res[GTX_MAX_RESULTS];
-        int32_t s;
-        if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
-        else s = txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
-        c.st[k] = s;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) c.res[r * 64 + k] = res[r];
-        committed += s == GPUTX_COMMIT;
-        aborted += s == GPUTX_ABORT;
     }
     if (!(seen & 8u)) fail(a.ws.st, GPUTX_E_INTERNAL);
 }
 
-// LDS of the PART kernels: chunk buffers, then the cell table and its list.
-__host__ __device__ inline size_t part_chunk_bytes(int rows, int cells) {
-    return (size_t)64 * 8 * (GTX_MAX_RESULTS + rows + 4) + (size_t)64 * 4 * 3 +
-           (size_t)64 * 4 * cells;
+constexpr int kPipeChunk = 128;  // transactions per chunk of the pipelined form (two staging waves)
+
+__host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
+    return (size_t)cw * (8 * (a.res_rows + a.prm_rows + 4) + 4 * 3 + 4 * a.cells_max);
 }
 size_t part_wave_lds(const BulkArgs& a) {
-    return part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.cell_bits) +
-           sizeof(CellSlot) + (size_t)4 * (64 * a.cells_max + 4);
+    return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
+           (size_t)4 * (64 * a.cells_max + 4);
 }
 size_t part_pipe_lds(const BulkArgs& a) {
-    return 2 * part_chunk_bytes(a.prm_rows, a.cells_max) + ((size_t)sizeof(CellSlot) << a.pipe_bits) +
+    return 2 * part_chunk_bytes(a, kPipeChunk) + ((size_t)sizeof(CellSlot) << a.pipe_bits) +
            sizeof(CellSlot) + (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
 }
 
-__device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, int rows) {
+__device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const BulkArgs& a, int cw) {
     PartChunk c;
+    c.cw = cw;
     c.res = reinterpret_cast<int64_t*>(base);
-    c.prm = c.res + 64 * GTX_MAX_RESULTS;
-    c.ts = c.prm + 64 * rows;
-    c.app0 = c.ts + 64;
-    c.app1 = c.app0 + 64;
-    c.idx = c.app1 + 64;
-    c.t = reinterpret_cast<int32_t*>(c.idx + 64);
-    c.np = c.t + 64;
-    c.st = c.np + 64;
-    c.cs = reinterpret_cast<uint32_t*>(c.st + 64);
+    c.prm = c.res + cw * a.res_rows;
+    c.ts = c.prm + cw * a.prm_rows;
+    c.app0 = c.ts + cw;
+    c.app1 = c.app0 + cw;
+    c.idx = c.app1 + cw;
+    c.t = reinterpret_cast<int32_t*>(c.idx + cw);
+    c.np = c.t + cw;
+    c.st = c.np + cw;
+    c.cs = reinterpret_cast<uint32_t*>(c.st + cw);
     return c;
 }
 
@@ -799,17 +816,18 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     const int rows = a.prm_rows;
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-        if (k < rows) c.prm[k * 64 + lane] = k < x.np ? x.prm[k] : 0;
+        if (k < rows) c.prm[k * c.cw + lane] = k < x.np ? x.prm[k] : 0;
 #pragma unroll
-    for (int r = 0; r < GTX_MAX_RESULTS; ++r) c.res[r * 64 + lane] = 0;
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+        if (r < a.res_rows) c.res[r * c.cw + lane] = 0;
     c.ts[lane] = x.ts;
     c.app0[lane] = x.app0;
     c.app1[lane] = x.app1;
     c.idx[lane] = x.i;
     c.t[lane] = t;
     c.np[lane] = x.np;
-    for (int r = 0; r < a.cells_max; ++r) c.cs[r * 64 + lane] = cell_sink_addr(tab);
-    CellClaim claim{tab, c.cs + lane};
+    for (int r = 0; r < a.cells_max; ++r) c.cs[r * c.cw + lane] = cell_sink_addr(tab);
+    CellClaim claim{tab, c.cs + lane, c.cw};
     txn_cells(a.types[t], x.prm, claim);
     AppendOnlyAcc ap;
     int64_t unused[GTX_MAX_RESULTS];
@@ -825,7 +843,7 @@ __device__ __forceinline__ void part_writeout(const BulkArgs& a, const PartChunk
     int64_t* out = a.results + i * a.width;
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r)
-        if (r < a.width) out[r] = c.res[r * 64 + lane];
+        if (r < a.width) out[r] = r < a.res_rows ? c.res[r * c.cw + lane] : 0;
     for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
 }
 
@@ -850,9 +868,10 @@ __device__ __forceinline__ void part_flush(const CellTab& tab, int tid, int nthr
 // when every transaction of the chunk has the same type.
 __device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                int cnt, int lane, int64_t& committed, int64_t& aborted) {
-    const int32_t t = lane < cnt ? c.t[lane] : -1;
-    const int t0 = __builtin_amdgcn_readfirstlane(t);
-    const bool uniform = __ballot(lane < cnt && t != t0) == 0;
+    const int t0 = __builtin_amdgcn_readfirstlane(c.t[0]);
+    bool differ = false;
+    for (int e = lane; e < cnt; e += 64) differ = differ || c.t[e] != t0;
+    const bool uniform = __ballot(differ) == 0;
     const int proc = uniform ? a.types[t0].proc : 0;
     switch (proc) {
 #define GTX_PART_CASE(P)                                                   \
@@ -895,9 +914,8 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (failed(st) || st->chosen != GPUTX_PART || (int)blockIdx.x >= st->n_heads) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int lane = lane_id();
-    const PartChunk c = part_chunk_at(part_lds, a.prm_rows);
-    const CellTab tab = part_table_at(part_lds + part_chunk_bytes(a.prm_rows, a.cells_max), a.cell_bits,
-                                      64 * a.cells_max);
+    const PartChunk c = part_chunk_at(part_lds, a, 64);
+    const CellTab tab = part_table_at(part_lds + part_chunk_bytes(a, 64), a.cell_bits, 64 * a.cells_max);
     for (int s = lane; s < (1 << a.cell_bits); s += 64) tab.slot[s].key = 0;
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
@@ -923,31 +941,34 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Pipelined PART: one 128-thread workgroup per long partition at a time.
-// Wave 0 (lane 0) runs chunk k serially while wave 1 writes out chunk k-1
-// and stages chunk k+1 in the other buffer.  The cell table persists across
-// chunks (a cell chunk k+1 shares with chunk k is found staged, with chunk
-// k's writes applied by the time chunk k+1 runs); it is flushed and emptied
-// when a further chunk might fill it past half, and at the end of each
-// partition, at points where no wave probes it, so linear probing never
-// sees a deleted slot.
-__global__ __launch_bounds__(128) void k_part_pipe(BulkArgs a) {
+// Pipelined PART: one 192-thread workgroup per long partition at a time.
+// Lane 0 of wave 0 runs chunk k (128 transactions) serially while waves 1-2,
+// one lane per transaction, write out chunk k-1 and stage chunk k+1 in the
+// other buffer.  The cell table persists across chunks (a cell chunk k+1
+// shares with chunk k is found staged, with chunk k's writes applied by the
+// time chunk k+1 runs); it is flushed and emptied when a further chunk might
+// fill it past half, and at the end of each partition, at points where no
+// wave probes it, so linear probing never sees a deleted slot.
+__global__ __launch_bounds__(192) void k_part_pipe(BulkArgs a) {
+    constexpr int cw = kPipeChunk;
+    constexpr int nthr = 64 + cw;
     GtxState* st = a.ws.st;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const bool serial = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
     const int lane = tid & 63;
-    const size_t cb = part_chunk_bytes(a.prm_rows, a.cells_max);
-    auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a.prm_rows); };
+    const int sl = tid - 64;  // staging lane: the transaction's column in the chunk
+    const size_t cb = part_chunk_bytes(a, cw);
+    auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a, cw); };
     const int cap = 1 << a.pipe_bits;
     const CellTab tab = part_table_at(part_lds + 2 * cb, a.pipe_bits, cap / 2);
     GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk
     // one decision for the whole workgroup (another workgroup may fail the
-    // bulk meanwhile; both waves must still meet at every barrier)
+    // bulk meanwhile; all waves must still meet at every barrier)
     if (tid == 0) flag[0] = !failed(st) && st->chosen == GPUTX_PART && (int)blockIdx.x < st->n_heads;
     __syncthreads();
     if (!flag[0]) return;
-    for (int s = tid; s < cap; s += 128) tab.slot[s].key = 0;
+    for (int s = tid; s < cap; s += nthr) tab.slot[s].key = 0;
     if (tid == 0) *tab.nlist = 0;
 
     const uint32_t* pos = a.ws.qv[a.part_passes & 1];
@@ -957,35 +978,35 @@ __global__ __launch_bounds__(128) void k_part_pipe(BulkArgs a) {
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
-        const int64_t nch = (end - lo + 63) / 64;
-        if (wave == 1) part_fetch(a, buf(0), tab, pos, lo, end, lane);
+        const int64_t nch = (end - lo + cw - 1) / cw;
+        if (!serial) part_fetch(a, buf(0), tab, pos, lo, end, sl);
         __syncthreads();
         for (int64_t k = 0; k < nch; ++k) {
-            const int64_t c0 = lo + 64 * k;
-            if (wave == 0) {
-                part_run_chunk(a, buf(k), tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+            const int64_t c0 = lo + cw * k;
+            if (serial) {
+                part_run_chunk(a, buf(k), tab, (int)min<int64_t>(cw, end - c0), lane, committed, aborted);
             } else {
-                if (k > 0) part_writeout(a, buf(k - 1), c0 - 64, end, lane);
+                if (k > 0) part_writeout(a, buf(k - 1), c0 - cw, end, sl);
                 bool flush = false;
                 if (k + 1 < nch) {
-                    flush = *tab.nlist + 64 * a.cells_max > cap / 2;
-                    if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+                    flush = *tab.nlist + cw * a.cells_max > cap / 2;
+                    if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
                 }
-                if (lane == 0) flag[k & 1] = flush;
+                if (sl == 0) flag[k & 1] = flush;
             }
             __syncthreads();
             if (flag[k & 1]) {  // same value in every wave
-                part_flush(tab, tid, 128);
+                part_flush(tab, tid, nthr);
                 __syncthreads();
                 if (tid == 0) *tab.nlist = 0;
                 __syncthreads();
-                if (wave == 1) part_fetch(a, buf(k + 1), tab, pos, c0 + 64, end, lane);
+                if (!serial) part_fetch(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
                 __syncthreads();
             }
         }
         // the last chunk's outcomes and every staged cell; the table is empty after
-        if (wave == 1) part_writeout(a, buf(nch - 1), lo + 64 * (nch - 1), end, lane);
-        part_flush(tab, tid, 128);
+        if (!serial) part_writeout(a, buf(nch - 1), lo + cw * (nch - 1), end, sl);
+        part_flush(tab, tid, nthr);
         __syncthreads();
         if (tid == 0) *tab.nlist = 0;
         __syncthreads();
@@ -1042,14 +1063,24 @@ void launch_empty(const BulkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
 }
 
-void exec_init_attributes() {
+// Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
+// limit (160 KB on gfx950), or the default 64 KB if raising it fails.
+static size_t g_part_lds_limit = 64 * 1024;
+
+void exec_init_attributes(int dev) {
     static bool done = false;
     if (done) return;
     done = true;
-    (void)hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kPartLdsMax);
-    (void)hipFuncSetAttribute((const void*)k_part_pipe, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kPartLdsMax);
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || optin <= 0)
+        optin = 64 * 1024;
+    const int want = std::min(optin, kPartLdsMax);
+    if (hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
+            hipSuccess &&
+        hipFuncSetAttribute((const void*)k_part_pipe, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
+            hipSuccess)
+        g_part_lds_limit = (size_t)want;
+    (void)hipGetLastError();
 }
 
 int exec_resident_blocks_per_cu() {
@@ -1088,12 +1119,12 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         // long partitions: a workgroup each with the LDS cell table; short
         // ones: a lane each
         BulkArgs b = a;
-        const bool pipe = a.part_pipeline && part_pipe_lds(a) <= (size_t)kPartLdsMax;
-        const bool wave = !pipe && part_wave_lds(a) <= (size_t)kPartLdsMax;
+        const bool pipe = a.part_pipeline && part_pipe_lds(a) <= g_part_lds_limit;
+        const bool wave = !pipe && part_wave_lds(a) <= g_part_lds_limit;
         b.long_part = (pipe || wave) ? kLongPart : INT32_MAX;
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
         if (pipe)
-            hipLaunchKernelGGL(k_part_pipe, dim3(groups), dim3(128), part_pipe_lds(a), s, b);
+            hipLaunchKernelGGL(k_part_pipe, dim3(groups), dim3(64 + kPipeChunk), part_pipe_lds(a), s, b);
         else if (wave)
             hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
         const unsigned lanes = (unsigned)std::max<int64_t>(

@@ -86,7 +86,7 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     }
     h->ncu = ncu;
     h->wall_khz = khz > 0 ? (uint64_t)khz : 100000;
-    exec_init_attributes();
+    exec_init_attributes(dev);
     *out = h;
     return GPUTX_OK;
 }
@@ -472,16 +472,19 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     // the most cells any registered procedure lists
     a.cells_max = 1;
     a.prm_rows = 1;
+    a.res_rows = 1;
     for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
         if (!h->type_present[i]) continue;
         a.cells_max = std::max(a.cells_max, proc_cells(h->types[i].proc));
         a.prm_rows = std::max(a.prm_rows, proc_params(h->types[i].proc));
+        a.res_rows = std::max(a.res_rows, proc_results(h->types[i].proc));
     }
     a.cell_bits = 1;
     while ((1 << a.cell_bits) < 2 * 64 * a.cells_max) ++a.cell_bits;
     // the pipelined form keeps cells across chunks: room for several chunks
     a.pipe_bits = a.cell_bits;
-    while ((1 << a.pipe_bits) < 8 * 64 * a.cells_max && a.pipe_bits < 12) ++a.pipe_bits;
+    while ((1 << a.pipe_bits) < 4 * 128 * a.cells_max && a.pipe_bits < 12) ++a.pipe_bits;
+    if ((1 << a.pipe_bits) < 2 * 128 * a.cells_max) ++a.pipe_bits;  // one 128-chunk must fit in half
     *out = a;
     return GPUTX_OK;
 }
