@@ -193,11 +193,20 @@ def bench_batch(args):
 
 def bench_serve(args):
     """Served form: Poisson arrivals over 10M subscribers, a bulk every deadline."""
-    from paper_1103_3105_amd import gputx, serving, workloads as wl
+    from paper_1103_3105_amd import autotune, gputx, serving, workloads as wl
     import oracle
     log(f"[bench] generating subscriber tables ({args.n_sub}) and the arrival trace")
     tabs = wl.sub_tables(wl.rng_for(5, 0), args.n_sub)
+    # Algorithm 1's thresholds for this workload, from sample bulks of the
+    # sizes the serving loop cuts (scratch copy of the tables)
+    rng_s = wl.rng_for(5, 99)
+    samples = [(wl.sub_bulk(rng_s, m, args.n_sub, 0.8), 14, 0) for m in (1000, 5000, 20000, 131072)]
+    tuned = autotune.calibrate(tabs, wl.sub_types(), samples, log=log, engine_opts=dict(part_size=128))
+    log(f"[bench] serve calibrated: w0_bar={tuned['w0_bar']} c_bar={tuned['c_bar']} d_bar={tuned['d_bar']} "
+        f"narrow={tuned['kset_narrow']}")
     eng = gputx.Engine(tabs, wl.sub_types(), part_size=128)
+    eng.set_options(w0_bar=int(min(tuned["w0_bar"], 2**62)), c_bar=int(tuned["c_bar"]),
+                    d_bar=int(min(tuned["d_bar"], 2**62)), kset_narrow=int(tuned["kset_narrow"]))
     points = []
     parity = None
     try:
@@ -225,7 +234,9 @@ def bench_serve(args):
     return dict(workload=f"subscriber: {args.n_sub} subscribers x 12 call-forwarding slots, "
                          f"mix 60/20/8/8/2/2, sid Zipf 0.8, Poisson arrivals, "
                          f"{args.serve_seconds}s per point", points=points,
-                parity_vs_oracle=parity)
+                parity_vs_oracle=parity,
+                calibrated={k: (int(v) if isinstance(v, (int, np.integer)) else v)
+                            for k, v in tuned.items() if k != "samples"})
 
 
 def bench_grid(args):

@@ -72,9 +72,10 @@ def _time(eng, dev, strategy, width, max_ops, reps=2):
 
 
 def calibrate(tables, types, sample_bulks: Sequence[tuple], narrow=(64, 256, 1024),
-              grids=(0,), log=None) -> dict:
+              grids=(0,), log=None, engine_opts=None) -> dict:
     """sample_bulks: (Bulk, width, max_ops) tuples.  Returns the options to set
-    (w0_bar, c_bar, d_bar, kset_narrow, grid_blocks) and the samples."""
+    (w0_bar, c_bar, d_bar, kset_narrow, grid_blocks) and the samples.
+    engine_opts: options of the engine the thresholds are for (part_size ...)."""
     from . import gputx
     scratch = {k: v.copy() for k, v in tables.items()}
     for t in scratch.values():   # room for one sample run's appends (emptied between runs)
@@ -82,7 +83,7 @@ def calibrate(tables, types, sample_bulks: Sequence[tuple], narrow=(64, 256, 102
             cap = max(b.n for b, _, _ in sample_bulks) * 16
             t.cols = [np.zeros(cap, c.dtype) for c in t.cols]
             t.capacity, t.n_rows = cap, 0
-    eng = gputx.Engine(scratch, types)
+    eng = gputx.Engine(scratch, types, **(engine_opts or {}))
     samples: List[Sample] = []
     try:
         best_narrow, best_grid = None, None
