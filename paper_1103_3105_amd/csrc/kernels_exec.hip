@@ -697,13 +697,88 @@ struct LdsAcc {
     __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by the owning lanes
 };
 
+// Serial accessor over registers: the running transaction's cell values were
+// read one transaction ahead; a write goes to the staged cell and to the
+// register (so a later reference of the same transaction sees it).
+struct RegAcc {
+    const uint32_t* ids;  // LDS address of each cell ordinal's staged value
+    int64_t* vals;        // the values, read ahead
+    template <class V>
+    struct Ref {
+        GTX_LDS int64_t* s;
+        int64_t* v;
+        __device__ __forceinline__ V get() const { return (V)*v; }
+        __device__ __forceinline__ void set(V x) {
+            *s = (int64_t)x;
+            *v = (int64_t)x;
+        }
+    };
+    template <class V>
+    __device__ __forceinline__ Ref<V> ref(int ord, GTX_GLOBAL V*) {
+        return Ref<V>{(GTX_LDS int64_t*)(uintptr_t)ids[ord], &vals[ord]};
+    }
+    template <class V>
+    __device__ __forceinline__ V ld(int ord, GTX_GLOBAL V* p) { return ref(ord, p).get(); }
+    template <class V>
+    __device__ __forceinline__ void st(int ord, GTX_GLOBAL V* p, V v) { ref(ord, p).set(v); }
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by the owning lanes
+};
+
+// Cell addresses, parameters and cell values of one transaction, in registers.
+template <int NP, int NC>
+struct SerialRegs {
+    uint32_t ids[NC];
+    int64_t prm[NP];
+    int64_t val[NC];
+};
+
+// One step of the forwarding pipeline.  X holds transaction k (addresses,
+// parameters, values), Y transaction k + 1 (addresses and parameters), and
+// Z is free.  The step starts loading the addresses and parameters of
+// k + 2 into Z and the values of k + 1 into Y (before k writes), runs k,
+// then forwards k's final value wherever k + 1 names the same cell at the
+// same ordinal.  Every load has a whole step to arrive.
+template <int P, int NP, int NC, int NR>
+__device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChunk& c, int k, int cnt,
+                                                SerialRegs<NP, NC>& X, SerialRegs<NP, NC>& Y,
+                                                SerialRegs<NP, NC>& Z, int64_t& committed,
+                                                int64_t& aborted) {
+    const int cw = c.cw;
+    const int k2 = k + 2 < cnt ? k + 2 : cnt - 1;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Z.ids[r] = c.cs[r * cw + k2];
+#pragma unroll
+    for (int r = 0; r < NP; ++r) Z.prm[r] = c.prm[r * cw + k2];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) Y.val[r] = *(GTX_LDS const int64_t*)(uintptr_t)Y.ids[r];
+    int64_t prm[GTX_MAX_PARAMS];
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? X.prm[r] : 0;
+    RegAcc acc{X.ids, X.val};
+    int64_t res[GTX_MAX_RESULTS];
+    const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+    if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
+#pragma unroll
+    for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
+    committed += s == GPUTX_COMMIT;
+    aborted += s == GPUTX_ABORT;
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+        if (Y.ids[r] == X.ids[r]) Y.val[r] = X.val[r];
+}
+
 // Lane 0 runs the chunk's cnt transactions in order against the staged
 // cells.  Statuses and results go to LDS; the owning lanes write them out
 // after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
 // mixed types.  The LDS parameter rows past a transaction's own are zero, so
-// they are read without a bound.  For narrow procedures the next
-// transaction's parameters and cell addresses are read while the current
-// one runs.
+// they are read without a bound.
+//
+// Narrow procedures whose cell ordinals cannot alias across transactions
+// (proc_typed_cells) run as a forwarding pipeline (serial_fwd_step), which
+// keeps the LDS latency off the dependence chain.  Every procedure also runs
+// through the generic path, which checks that each ordinal it names was
+// staged, whenever a chunk mixes types.
 template <int P>
 __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
                                             const CellTab& tab, int cnt, int64_t& committed,
@@ -711,40 +786,36 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NP = proc_params(P);  // parameters the procedure can read
     constexpr int NR = proc_results(P); // results it can write (P == 0: up to res_rows)
     constexpr int NC = proc_cells(P);   // cells it can name
-    constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4;
+    constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
     if (lane_id() != 0) return;
     const int rows = a.prm_rows;
     const int cw = c.cw;
     const uint32_t sink = cell_sink_addr(tab);
     uint32_t seen = ~0u;
     if constexpr (ahead) {
-        int64_t nxt[NP];
-        uint32_t nid[NC];
+        SerialRegs<NP, NC> A, B;  // transactions 0 and 1
+        const int k1 = cnt > 1 ? 1 : 0;
 #pragma unroll
-        for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * cw];
-#pragma unroll
-        for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * cw];
-        for (int k = 0; k < cnt; ++k) {
-            int64_t prm[GTX_MAX_PARAMS];
-            uint32_t ids[NC];
-#pragma unroll
-            for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? nxt[r] : 0;
-#pragma unroll
-            for (int r = 0; r < NC; ++r) ids[r] = nid[r];
-            const int kn = k + 1 < cnt ? k + 1 : k;
-#pragma unroll
-            for (int r = 0; r < NP; ++r) nxt[r] = c.prm[r * cw + kn];
-#pragma unroll
-            for (int r = 0; r < NC; ++r) nid[r] = c.cs[r * cw + kn];
-            LdsAcc acc{ids, &seen};
-            int64_t res[GTX_MAX_RESULTS];
-            const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
-            c.st[k] = s;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
-            committed += s == GPUTX_COMMIT;
-            aborted += s == GPUTX_ABORT;
+        for (int r = 0; r < NC; ++r) {
+            A.ids[r] = c.cs[r * cw];
+            B.ids[r] = c.cs[r * cw + k1];
         }
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+            A.prm[r] = c.prm[r * cw];
+            B.prm[r] = c.prm[r * cw + k1];
+        }
+#pragma unroll
+        for (int r = 0; r < NC; ++r) A.val[r] = *(GTX_LDS const int64_t*)(uintptr_t)A.ids[r];
+        SerialRegs<NP, NC> C;
+        int k = 0;
+        for (; k + 2 < cnt; k += 3) {  // three steps with rotated register sets: no moves
+            serial_fwd_step<P, NP, NC, NR>(T, c, k, cnt, A, B, C, committed, aborted);
+            serial_fwd_step<P, NP, NC, NR>(T, c, k + 1, cnt, B, C, A, committed, aborted);
+            serial_fwd_step<P, NP, NC, NR>(T, c, k + 2, cnt, C, A, B, committed, aborted);
+        }
+        if (k < cnt) serial_fwd_step<P, NP, NC, NR>(T, c, k, cnt, A, B, C, committed, aborted);
+        if (k + 1 < cnt) serial_fwd_step<P, NP, NC, NR>(T, c, k + 1, cnt, B, C, A, committed, aborted);
     } else {
         for (int k = 0; k < cnt; ++k) {
             int64_t prm[GTX_MAX_PARAMS];
@@ -761,7 +832,7 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
             int32_t s;
             if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
             else s = txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
-            c.st[k] = s;
+            if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
 #pragma unroll
             for (int r = 0; r < NR; ++r)
                 if (P != 0 || r < a.res_rows) c.res[r * cw + k] = res[r];
@@ -826,6 +897,7 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     c.idx[lane] = x.i;
     c.t[lane] = t;
     c.np[lane] = x.np;
+    c.st[lane] = GPUTX_COMMIT;
     for (int r = 0; r < a.cells_max; ++r) c.cs[r * c.cw + lane] = cell_sink_addr(tab);
     CellClaim claim{tab, c.cs + lane, c.cw};
     txn_cells(a.types[t], x.prm, claim);

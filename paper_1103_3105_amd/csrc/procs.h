@@ -283,6 +283,13 @@ __host__ __device__ constexpr int proc_params(int proc) {
          : (proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 2
          : (proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 3 : proc == GPUTX_INS_CF ? 4 : 34;
 }
+// Two transactions of procedure P can share a cell only at the same cell
+// ordinal: each ordinal names one fixed column, or P has a single ordinal.
+// Not so for new-order, whose item ordinals all name the stock column, nor
+// for a mixed chunk (P == 0).
+__host__ __device__ constexpr bool proc_typed_cells(int proc) {
+    return proc != 0 && proc != GPUTX_NEW_ORDER;
+}
 // Results procedure P can write (0: any procedure).
 __host__ __device__ constexpr int proc_results(int proc) {
     return proc == GPUTX_NEW_ORDER ? 16 : proc == GPUTX_GET_SUB ? 14

@@ -166,6 +166,22 @@ def test_part_partition_lengths(pipeline):
     assert_parity(s, g, o, bulk)
 
 
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_part_mixed_type_ids(pipeline):
+    """Debit-credit registered under two type ids: chunks are not of one type,
+    so PART runs them through its generic serial path (which checks that every
+    cell a procedure names was staged) instead of the specialised one."""
+    tabs, _, bulk = util.small_bank(65, 20_000, n_branch=8, tpb=10, apt=300, theta=0.8)
+    types = [wl.TypeDesc(0, "DEBIT_CREDIT", 4, 3, wl.BANK_ROLES),
+             wl.TypeDesc(1, "DEBIT_CREDIT", 4, 3, wl.BANK_ROLES)]
+    typ = np.random.default_rng(66).integers(0, 2, bulk.n).astype(np.int32)
+    bulk = wl.Bulk(typ, bulk.params, bulk.ts)
+    _say("part mixed type ids", pipeline)
+    s, g, o = run_both(tabs, types, bulk, 3, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2, s.as_dict()
+    assert_parity(s, g, o, bulk)
+
+
 @pytest.mark.parametrize("n", [0, 1, 2, 63, 4097])
 def test_small_and_empty_bulks(n):
     tabs, types, bulk = util.small_bank(24, max(n, 1), n_branch=2, tpb=2, apt=5)
