@@ -58,6 +58,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def random_gather_ceiling(device, stream, table_rows: int = 1 << 29, gathers: int = 1 << 26,
+                          reps: int = 3) -> float:
+    """GB/s of gathered bytes for 8-byte loads at uniform random rows of a
+    4 GiB int64 table (a plain library gather): the random-access ceiling the
+    executors' scattered row accesses are measured against."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(1103)
+    tbl = torch.zeros(table_rows, dtype=torch.int64, device=device)
+    idx = torch.randint(0, table_rows, (gathers,), dtype=torch.int64, device=device, generator=g)
+    out = torch.empty(gathers, dtype=torch.int64, device=device)
+    torch.index_select(tbl, 0, idx, out=out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        torch.index_select(tbl, 0, idx, out=out)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del tbl, idx, out
+    return gathers * 8 / (ms / 1e3) / 1e9
+
+
 def make_workload(args):
     from paper_1103_3105_amd import workloads as wl
     # append capacity for every bulk this run executes (timed, PCIe, strategy comparison)
@@ -348,6 +372,11 @@ def main():
         step(args.strategy)
     torch.cuda.synchronize()
 
+    # random-access ceiling (outside timing): 8-byte gathers at uniform random
+    # rows of a 4 GiB table, far larger than the caches
+    gather_gbs = random_gather_ceiling(eng.device, stream)
+    log(f"[bench] random 8-byte gather ceiling: {gather_gbs:.1f} GB/s of gathered bytes")
+
     # a plain copy of known size (outside timing): PMC byte counters of the
     # profiled runs are scaled by what they read for it
     calib_src = torch.empty(COPY_CALIB_BYTES // 8, dtype=torch.int64, device=eng.device)
@@ -388,7 +417,9 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6),
                 "traffic": measured_traffic(kernel_of.get(dom, dom)), "kernel": dom,
-                "bytes_per_launch": pb[dom], "ms_per_launch": round(dom_ms, 4)}
+                "bytes_per_launch": pb[dom], "ms_per_launch": round(dom_ms, 4),
+                "random_gather_ceiling": round(gather_gbs, 1),
+                "frac_of_random_gather": round(achieved / gather_gbs, 6) if gather_gbs > 0 else None}
 
     # PCIe-inclusive rate: bulk H2D + status/results D2H around each bulk
     pin = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in dev.items()}

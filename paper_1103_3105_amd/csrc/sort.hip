@@ -60,20 +60,11 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_hist(const K* keys, const in
     for (int i = threadIdx.x; i < 8 * 256; i += GTX_BLOCK) (&h[0][0])[i] = 0;
     __syncthreads();
     int64_t count = count_dev ? *count_dev : count_cap;
+    int64_t tid = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * GTX_BLOCK;
-    // skewed keys share digits: lanes with equal digits are counted by one
-    // LDS atomic of their leader instead of one each
-    for (int64_t i0 = (int64_t)blockIdx.x * GTX_BLOCK; i0 < count; i0 += stride) {
-        const int64_t i = i0 + threadIdx.x;
-        const bool ok = i < count;
-        const K k = ok ? keys[i] : (K)0;
-        const uint64_t active = __ballot(ok);
-        for (int p = 0; p < npass; ++p) {
-            const uint32_t d = digit_of(k, p);
-            const uint64_t peers = match_u8(d, active);
-            if (ok && lane_id() == __ffsll((unsigned long long)peers) - 1)
-                atomicAdd(&h[p][d], (uint32_t)__popcll(peers));
-        }
+    for (int64_t i = tid; i < count; i += stride) {
+        K k = keys[i];
+        for (int p = 0; p < npass; ++p) atomicAdd(&h[p][digit_of(k, p)], 1u);
     }
     __syncthreads();
     for (int p = 0; p < npass; ++p) {

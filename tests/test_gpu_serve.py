@@ -90,3 +90,30 @@ def test_hbm_budget_limits_slots():
         _check_records(res, trace, 200_000, 1024)
     finally:
         eng.close()
+
+
+def test_served_alone_equals_in_the_mix():
+    """Continuous batching: with bulks overlapping on the device (4 slots)
+    every transaction gets the same status and results, and the tables the
+    same final state, as with bulks run one at a time (1 slot), whatever the
+    bulk boundaries the two runs cut."""
+    import torch
+    from paper_1103_3105_amd import gputx
+    rng = np.random.default_rng(33)
+    tabs = wl.sub_tables(rng, 20_000, occupancy=0.4)
+    trace = serving.make_trace(400_000, 0.1, 20_000, theta=0.8, seed=11)
+    outs = []
+    for slots in (1, 4):
+        eng = gputx.Engine(util.copy_tables(tabs), wl.sub_types(), part_size=16)
+        try:
+            res = serving.serve(eng, trace, 100, slots=slots, width=14, max_bulk=4096)
+            torch.cuda.synchronize()
+            outs.append((res, {k: eng.table_host(k) for k in ("subscriber", "call_fwd")}))
+        finally:
+            eng.close()
+    (r1, t1), (r4, t4) = outs
+    assert r4.slots_used == 4 and r1.slots_used == 1
+    assert np.array_equal(r1.status, r4.status)
+    assert np.array_equal(r1.results, r4.results)
+    for k in t1:
+        assert all(np.array_equal(x, y) for x, y in zip(t1[k], t4[k])), k
