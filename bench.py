@@ -411,7 +411,7 @@ def main():
     dom = max((k for k in phases if k in pb), key=lambda k: phases[k])
     dom_ms = phases[dom] / max(nb, 1)
     achieved = pb[dom] / (dom_ms / 1e3) / 1e9 if dom_ms > 0 else 0.0
-    kernel_of = {"part": "k_part_pipe" if args.part_pipeline else "k_part_wave",
+    kernel_of = {"part": "k_part_pipe<128>" if args.part_pipeline else "k_part_wave",
                  "tpl": "k_tpl", "kset": "k_kset", "rank": "k_rank_down",
                  "op_sort": "k_sort_pass", "prepare": "k_prepare", "emit": "k_emit"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",

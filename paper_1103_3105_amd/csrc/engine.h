@@ -120,7 +120,7 @@ void launch_empty(const BulkArgs& a, hipStream_t s);
 int exec_resident_blocks_per_cu();
 // LDS bytes of one PART workgroup for these arguments (one wave; pipelined)
 size_t part_wave_lds(const BulkArgs& a);
-size_t part_pipe_lds(const BulkArgs& a);
+size_t part_pipe_lds(const BulkArgs& a, int cw);
 // one-time kernel attributes (large dynamic LDS for PART)
 void exec_init_attributes(int dev);
 

@@ -587,7 +587,7 @@ struct PartChunk {
     int64_t* app1;  // [cw]
     int64_t* idx;   // [cw] input index (status / results slot)
     int32_t* t;     // [cw] type
-    int32_t* np;    // [cw] parameters loaded
+    int32_t* proc;  // [cw] procedure
     int32_t* st;    // [cw] status
     uint32_t* cs;   // [cells][cw] LDS address of each of the transaction's staged cells
     int cw;
@@ -768,6 +768,29 @@ __device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChun
         if (Y.ids[r] == X.ids[r]) Y.val[r] = X.val[r];
 }
 
+// One transaction k of procedure P against the staged cells (LdsAcc, which
+// checks that every cell ordinal P names was staged); returns its status.
+template <int P>
+__device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk& c, int k, uint32_t* seen) {
+    constexpr int NP = proc_params(P);
+    constexpr int NR = proc_results(P);
+    constexpr int NC = proc_cells(P);
+    const int cw = c.cw;
+    int64_t prm[GTX_MAX_PARAMS];
+    uint32_t ids[NC];
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? c.prm[r * cw + k] : 0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) ids[r] = c.cs[r * cw + k];
+    LdsAcc acc{ids, seen};
+    int64_t res[GTX_MAX_RESULTS];
+    const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+    if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
+#pragma unroll
+    for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
+    return s;
+}
+
 // Lane 0 runs the chunk's cnt transactions in order against the staged
 // cells.  Statuses and results go to LDS; the owning lanes write them out
 // after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
@@ -788,9 +811,7 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
     if (lane_id() != 0) return;
-    const int rows = a.prm_rows;
     const int cw = c.cw;
-    const uint32_t sink = cell_sink_addr(tab);
     uint32_t seen = ~0u;
     if constexpr (ahead) {
         SerialRegs<NP, NC> A, B;  // transactions 0 and 1
@@ -816,34 +837,50 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
         }
         if (k < cnt) serial_fwd_step<P, NP, NC, NR>(T, c, k, cnt, A, B, C, committed, aborted);
         if (k + 1 < cnt) serial_fwd_step<P, NP, NC, NR>(T, c, k + 1, cnt, B, C, A, committed, aborted);
-    } else {
+    } else if constexpr (P != 0) {
+        int n_commit = 0, n_abort = 0;
         for (int k = 0; k < cnt; ++k) {
-            int64_t prm[GTX_MAX_PARAMS];
-            uint32_t ids[NC];
-#pragma unroll
-            for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = 0;
-#pragma unroll
-            for (int r = 0; r < NP; ++r)
-                if (P != 0 || r < rows) prm[r] = c.prm[r * cw + k];
-#pragma unroll
-            for (int r = 0; r < NC; ++r) ids[r] = (P != 0 || r < a.cells_max) ? c.cs[r * cw + k] : sink;
-            LdsAcc acc{ids, &seen};
-            int64_t res[GTX_MAX_RESULTS];
-            int32_t s;
-            if constexpr (P != 0) s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
-            else s = txn_exec_any(acc, a.types[c.t[k]], prm, c.ts[k], c.app0[k], c.app1[k], res);
-            if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (P != 0 || r < a.res_rows) c.res[r * cw + k] = res[r];
-            committed += s == GPUTX_COMMIT;
-            aborted += s == GPUTX_ABORT;
+            const int32_t s = serial_one<P>(T, c, k, &seen);
+            n_commit += s == GPUTX_COMMIT;
+            n_abort += s == GPUTX_ABORT;
         }
+        committed += n_commit;
+        aborted += n_abort;
+    } else {
+        // mixed chunk: each transaction dispatches to its procedure's code,
+        // which reads only that procedure's parameters and cells
+        int n_commit = 0, n_abort = 0;
+        for (int k = 0; k < cnt; ++k) {
+            const DevType& Tk = a.types[c.t[k]];
+            int32_t s = GPUTX_INVALID;
+            switch (c.proc[k]) {
+#define GTX_ONE(Q)                                                    \
+    case Q:                                                           \
+        s = serial_one<Q>(Tk, c, k, &seen);                           \
+        break;
+                GTX_ONE(GPUTX_DEBIT_CREDIT)
+                GTX_ONE(GPUTX_NEW_ORDER)
+                GTX_ONE(GPUTX_PAYMENT)
+                GTX_ONE(GPUTX_ORDER_STATUS)
+                GTX_ONE(GPUTX_GET_SUB)
+                GTX_ONE(GPUTX_GET_CF)
+                GTX_ONE(GPUTX_UPD_SUB_FIELD)
+                GTX_ONE(GPUTX_UPD_LOC)
+                GTX_ONE(GPUTX_INS_CF)
+                GTX_ONE(GPUTX_DEL_CF)
+#undef GTX_ONE
+            default:
+                seen = 0;  // a staged transaction of no known procedure
+            }
+            n_commit += s == GPUTX_COMMIT;
+            n_abort += s == GPUTX_ABORT;
+        }
+        committed += n_commit;
+        aborted += n_abort;
     }
     if (!(seen & 8u)) fail(a.ws.st, GPUTX_E_INTERNAL);
 }
 
-constexpr int kPipeChunk = 128;  // transactions per chunk of the pipelined form (two staging waves)
 
 __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
     return (size_t)cw * (8 * (a.res_rows + a.prm_rows + 4) + 4 * 3 + 4 * a.cells_max);
@@ -852,9 +889,9 @@ size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
            (size_t)4 * (64 * a.cells_max + 4);
 }
-size_t part_pipe_lds(const BulkArgs& a) {
-    return 2 * part_chunk_bytes(a, kPipeChunk) + ((size_t)sizeof(CellSlot) << a.pipe_bits) +
-           sizeof(CellSlot) + (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
+size_t part_pipe_lds(const BulkArgs& a, int cw) {
+    return 2 * part_chunk_bytes(a, cw) + ((size_t)sizeof(CellSlot) << a.pipe_bits) + sizeof(CellSlot) +
+           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
 }
 
 __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const BulkArgs& a, int cw) {
@@ -867,8 +904,8 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     c.app1 = c.app0 + cw;
     c.idx = c.app1 + cw;
     c.t = reinterpret_cast<int32_t*>(c.idx + cw);
-    c.np = c.t + cw;
-    c.st = c.np + cw;
+    c.proc = c.t + cw;
+    c.st = c.proc + cw;
     c.cs = reinterpret_cast<uint32_t*>(c.st + cw);
     return c;
 }
@@ -896,7 +933,7 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     c.app1[lane] = x.app1;
     c.idx[lane] = x.i;
     c.t[lane] = t;
-    c.np[lane] = x.np;
+    c.proc[lane] = a.types[t].proc;
     c.st[lane] = GPUTX_COMMIT;
     for (int r = 0; r < a.cells_max; ++r) c.cs[r * c.cw + lane] = cell_sink_addr(tab);
     CellClaim claim{tab, c.cs + lane, c.cw};
@@ -1013,16 +1050,17 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Pipelined PART: one 192-thread workgroup per long partition at a time.
-// Lane 0 of wave 0 runs chunk k (128 transactions) serially while waves 1-2,
-// one lane per transaction, write out chunk k-1 and stage chunk k+1 in the
-// other buffer.  The cell table persists across chunks (a cell chunk k+1
+// Pipelined PART: one workgroup per long partition at a time.  Lane 0 of
+// wave 0 runs chunk k (CW transactions) serially while the CW / 64 staging
+// waves, one lane per transaction, write out chunk k-1 and stage chunk k+1 in
+// the other buffer.  The cell table persists across chunks (a cell chunk k+1
 // shares with chunk k is found staged, with chunk k's writes applied by the
 // time chunk k+1 runs); it is flushed and emptied when a further chunk might
 // fill it past half, and at the end of each partition, at points where no
 // wave probes it, so linear probing never sees a deleted slot.
-__global__ __launch_bounds__(192) void k_part_pipe(BulkArgs a) {
-    constexpr int cw = kPipeChunk;
+template <int CW>
+__global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
+    constexpr int cw = CW;
     constexpr int nthr = 64 + cw;
     GtxState* st = a.ws.st;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
@@ -1149,8 +1187,10 @@ void exec_init_attributes(int dev) {
     const int want = std::min(optin, kPartLdsMax);
     if (hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
             hipSuccess &&
-        hipFuncSetAttribute((const void*)k_part_pipe, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
-            hipSuccess)
+        hipFuncSetAttribute((const void*)k_part_pipe<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            want) == hipSuccess &&
+        hipFuncSetAttribute((const void*)k_part_pipe<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            want) == hipSuccess)
         g_part_lds_limit = (size_t)want;
     (void)hipGetLastError();
 }
@@ -1188,15 +1228,19 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     }
     pm.mark(PH_PARTSORT, s);
     if (part) {
-        // long partitions: a workgroup each with the LDS cell table; short
-        // ones: a lane each
+        // long partitions: a workgroup each with the LDS cell table (chunks of
+        // 128 transactions staged by two waves where the LDS fits, else 64,
+        // e.g. for new-order's wide signature); short ones: a lane each
         BulkArgs b = a;
-        const bool pipe = a.part_pipeline && part_pipe_lds(a) <= g_part_lds_limit;
-        const bool wave = !pipe && part_wave_lds(a) <= g_part_lds_limit;
-        b.long_part = (pipe || wave) ? kLongPart : INT32_MAX;
+        const bool pipe128 = a.part_pipeline && part_pipe_lds(a, 128) <= g_part_lds_limit;
+        const bool pipe64 = !pipe128 && a.part_pipeline && part_pipe_lds(a, 64) <= g_part_lds_limit;
+        const bool wave = !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
+        b.long_part = (pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
-        if (pipe)
-            hipLaunchKernelGGL(k_part_pipe, dim3(groups), dim3(64 + kPipeChunk), part_pipe_lds(a), s, b);
+        if (pipe128)
+            hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 + 128), part_pipe_lds(a, 128), s, b);
+        else if (pipe64)
+            hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 + 64), part_pipe_lds(a, 64), s, b);
         else if (wave)
             hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
         const unsigned lanes = (unsigned)std::max<int64_t>(

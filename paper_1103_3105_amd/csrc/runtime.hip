@@ -44,7 +44,10 @@ static int passes_for(uint64_t maxkey) {
 
 extern "C" int gputx_default_options(gputx_options* o) {
     if (!o) return GPUTX_E_ARG;
-    o->w0_bar = 16384;   // about one wave64 per SIMD of 256 CUs x 4 SIMDs x 16 (recalibrated by the autotuner)
+    // K-SET only for very wide 0-sets: on MI355X its per-wave barrier across 8
+    // XCDs costs more than TPL's locks or PART's serial chains on every measured
+    // workload (the autotuner fits all three thresholds to a workload mix)
+    o->w0_bar = 1 << 20;
     o->c_bar = 0;
     o->d_bar = 1 << 30;
     o->part_size = 1;
