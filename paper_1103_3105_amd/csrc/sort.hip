@@ -157,25 +157,45 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
         st_relaxed(my, kPrefix | tot);
     } else {
         st_relaxed(my, kAgg | tot);
+        // walk back over up to kLook predecessors per round trip: their
+        // status words are loaded together, then taken nearest first until a
+        // prefix (done) or a tile that has not published yet (wait for it)
+        constexpr int kLook = 8;
         int64_t t = tile - 1;
         uint64_t t0 = 0;
-        while (true) {
-            uint32_t s = ld_relaxed(status + ((int64_t)pass * max_tiles + t) * 256 + d);
-            if (s & kPrefix) {
-                excl += s & kCountMask;
-                break;
+        const uint32_t* col = status + (int64_t)pass * max_tiles * 256 + d;
+        bool done = false;
+        while (!done) {
+            uint32_t w[kLook];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j) w[j] = t - j >= 0 ? ld_relaxed(col + (t - j) * 256) : kPrefix;
+            int took = 0;
+            bool stalled = false;
+#pragma unroll
+            for (int j = 0; j < kLook; ++j) {
+                if (done || stalled) continue;
+                if (w[j] & kPrefix) {
+                    excl += w[j] & kCountMask;
+                    done = true;
+                } else if (w[j] & kAgg) {
+                    excl += w[j] & kCountMask;
+                    ++took;
+                } else {
+                    stalled = true;
+                }
             }
-            if (s & kAgg) {
-                excl += s & kCountMask;
-                --t;
-                continue;
+            t -= took;
+            if (done) break;
+            if (stalled) {
+                if (t0 == 0) t0 = now_ticks();
+                else if (now_ticks() - t0 > spin_ticks) {
+                    atomicCAS(&st->error, 0, GPUTX_E_DEADLOCK);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            } else {
+                t0 = 0;  // progress: restart the watchdog
             }
-            if (t0 == 0) t0 = now_ticks();
-            else if (now_ticks() - t0 > spin_ticks) {
-                atomicCAS(&st->error, 0, GPUTX_E_DEADLOCK);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
         }
         st_relaxed(my, kPrefix | (excl + tot));
     }
