@@ -577,11 +577,14 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Signatures of one PART chunk of cw transactions staged in LDS, one column
-// per transaction.
+// Signatures of one PART chunk of cw transactions staged in LDS.  Parameters,
+// cell addresses and results are stored one row per transaction (rows of a
+// 16-byte multiple), so the serial lane reads a transaction's cell addresses
+// with one LDS load; the parameter and address arrays have two spare rows so
+// reading two transactions ahead needs no bound.
 struct PartChunk {
-    int64_t* res;   // [res rows][cw] results
-    int64_t* prm;   // [parameter rows][cw] parameters
+    int64_t* res;   // [cw][rs] results
+    int64_t* prm;   // [cw + 2][ps] parameters
     int64_t* ts;    // [cw]
     int64_t* app0;  // [cw]
     int64_t* app1;  // [cw]
@@ -589,9 +592,12 @@ struct PartChunk {
     int32_t* t;     // [cw] type
     int32_t* proc;  // [cw] procedure
     int32_t* st;    // [cw] status
-    uint32_t* cs;   // [cells][cw] LDS address of each of the transaction's staged cells
-    int cw;
+    uint32_t* cs;   // [cw + 2][css] LDS address of each of the transaction's staged cells
+    int cw, ps, css, rs;
 };
+__host__ __device__ inline int part_ps(int prm_rows) { return (prm_rows + 1) & ~1; }
+__host__ __device__ inline int part_css(int cells) { return (cells + 3) & ~3; }
+__host__ __device__ inline int part_rs(int res_rows) { return (res_rows + 1) & ~1; }
 
 // The chunk's table cells, staged in LDS: an open-addressing hash table keyed
 // by cell address (bit 1: 64-bit cell, bit 0: written; key 0 = empty slot),
@@ -628,8 +634,7 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 // written (bit 0), so it is stored back when the table is flushed.
 struct CellClaim {
     CellTab tab;
-    uint32_t* cs;  // the lane's column of cell addresses
-    int cw;        // its stride
+    uint32_t* cs;  // the transaction's row of cell addresses
     template <class V>
     __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
         const V v = *p;  // issued before the claim; kept only by the winner
@@ -658,7 +663,7 @@ struct CellClaim {
                 break;
             }
         }
-        cs[ord * cw] = got;
+        cs[ord] = got;
     }
 };
 
@@ -744,12 +749,15 @@ __device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChun
                                                 SerialRegs<NP, NC>& X, SerialRegs<NP, NC>& Y,
                                                 SerialRegs<NP, NC>& Z, int64_t& committed,
                                                 int64_t& aborted) {
-    const int cw = c.cw;
-    const int k2 = k + 2 < cnt ? k + 2 : cnt - 1;
+    (void)cnt;  // rows past the chunk hold table addresses (part_init_rows)
+    {
+        const uint4 id4 = *reinterpret_cast<const uint4*>(c.cs + (k + 2) * c.css);
+        const uint32_t idv[4] = {id4.x, id4.y, id4.z, id4.w};
 #pragma unroll
-    for (int r = 0; r < NC; ++r) Z.ids[r] = c.cs[r * cw + k2];
+        for (int r = 0; r < NC; ++r) Z.ids[r] = idv[r];
+    }
 #pragma unroll
-    for (int r = 0; r < NP; ++r) Z.prm[r] = c.prm[r * cw + k2];
+    for (int r = 0; r < NP; ++r) Z.prm[r] = c.prm[(k + 2) * c.ps + r];
 #pragma unroll
     for (int r = 0; r < NC; ++r) Y.val[r] = *(GTX_LDS const int64_t*)(uintptr_t)Y.ids[r];
     int64_t prm[GTX_MAX_PARAMS];
@@ -760,7 +768,7 @@ __device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChun
     const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
     if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
 #pragma unroll
-    for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
+    for (int r = 0; r < NR; ++r) c.res[k * c.rs + r] = res[r];
     committed += s == GPUTX_COMMIT;
     aborted += s == GPUTX_ABORT;
 #pragma unroll
@@ -775,19 +783,18 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     constexpr int NP = proc_params(P);
     constexpr int NR = proc_results(P);
     constexpr int NC = proc_cells(P);
-    const int cw = c.cw;
     int64_t prm[GTX_MAX_PARAMS];
     uint32_t ids[NC];
 #pragma unroll
-    for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? c.prm[r * cw + k] : 0;
+    for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? c.prm[k * c.ps + r] : 0;
 #pragma unroll
-    for (int r = 0; r < NC; ++r) ids[r] = c.cs[r * cw + k];
+    for (int r = 0; r < NC; ++r) ids[r] = c.cs[k * c.css + r];
     LdsAcc acc{ids, seen};
     int64_t res[GTX_MAX_RESULTS];
     const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
     if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
 #pragma unroll
-    for (int r = 0; r < NR; ++r) c.res[r * cw + k] = res[r];
+    for (int r = 0; r < NR; ++r) c.res[k * c.rs + r] = res[r];
     return s;
 }
 
@@ -811,20 +818,18 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
     if (lane_id() != 0) return;
-    const int cw = c.cw;
     uint32_t seen = ~0u;
     if constexpr (ahead) {
-        SerialRegs<NP, NC> A, B;  // transactions 0 and 1
-        const int k1 = cnt > 1 ? 1 : 0;
+        SerialRegs<NP, NC> A, B;  // transactions 0 and 1 (row 1 exists even if cnt == 1)
 #pragma unroll
         for (int r = 0; r < NC; ++r) {
-            A.ids[r] = c.cs[r * cw];
-            B.ids[r] = c.cs[r * cw + k1];
+            A.ids[r] = c.cs[r];
+            B.ids[r] = c.cs[c.css + r];
         }
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-            A.prm[r] = c.prm[r * cw];
-            B.prm[r] = c.prm[r * cw + k1];
+            A.prm[r] = c.prm[r];
+            B.prm[r] = c.prm[c.ps + r];
         }
 #pragma unroll
         for (int r = 0; r < NC; ++r) A.val[r] = *(GTX_LDS const int64_t*)(uintptr_t)A.ids[r];
@@ -883,7 +888,8 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
 
 
 __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
-    return (size_t)cw * (8 * (a.res_rows + a.prm_rows + 4) + 4 * 3 + 4 * a.cells_max);
+    return (size_t)8 * part_rs(a.res_rows) * cw + (size_t)8 * part_ps(a.prm_rows) * (cw + 2) +
+           (size_t)8 * 4 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + 2);
 }
 size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
@@ -897,9 +903,12 @@ size_t part_pipe_lds(const BulkArgs& a, int cw) {
 __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const BulkArgs& a, int cw) {
     PartChunk c;
     c.cw = cw;
+    c.ps = part_ps(a.prm_rows);
+    c.css = part_css(a.cells_max);
+    c.rs = part_rs(a.res_rows);
     c.res = reinterpret_cast<int64_t*>(base);
-    c.prm = c.res + cw * a.res_rows;
-    c.ts = c.prm + cw * a.prm_rows;
+    c.prm = c.res + cw * c.rs;
+    c.ts = c.prm + (cw + 2) * c.ps;
     c.app0 = c.ts + cw;
     c.app1 = c.app0 + cw;
     c.idx = c.app1 + cw;
@@ -924,10 +933,10 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     const int rows = a.prm_rows;
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-        if (k < rows) c.prm[k * c.cw + lane] = k < x.np ? x.prm[k] : 0;
+        if (k < rows) c.prm[lane * c.ps + k] = k < x.np ? x.prm[k] : 0;
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r)
-        if (r < a.res_rows) c.res[r * c.cw + lane] = 0;
+        if (r < a.res_rows) c.res[lane * c.rs + r] = 0;
     c.ts[lane] = x.ts;
     c.app0[lane] = x.app0;
     c.app1[lane] = x.app1;
@@ -935,8 +944,8 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     c.t[lane] = t;
     c.proc[lane] = a.types[t].proc;
     c.st[lane] = GPUTX_COMMIT;
-    for (int r = 0; r < a.cells_max; ++r) c.cs[r * c.cw + lane] = cell_sink_addr(tab);
-    CellClaim claim{tab, c.cs + lane, c.cw};
+    for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
+    CellClaim claim{tab, c.cs + lane * c.css};
     txn_cells(a.types[t], x.prm, claim);
     AppendOnlyAcc ap;
     int64_t unused[GTX_MAX_RESULTS];
@@ -952,7 +961,7 @@ __device__ __forceinline__ void part_writeout(const BulkArgs& a, const PartChunk
     int64_t* out = a.results + i * a.width;
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r)
-        if (r < a.width) out[r] = r < a.res_rows ? c.res[r * c.cw + lane] : 0;
+        if (r < a.width) out[r] = r < a.res_rows ? c.res[lane * c.rs + r] : 0;
     for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
 }
 
@@ -1003,6 +1012,13 @@ __device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChun
     }
 }
 
+// Every row of a chunk's address array starts at the sink slot, so the
+// serial lane's read-ahead past the chunk's last transaction always finds an
+// address inside the table.
+__device__ __forceinline__ void part_init_rows(const PartChunk& c, const CellTab& tab, int tid, int nthreads) {
+    for (int e = tid; e < (c.cw + 2) * c.css; e += nthreads) c.cs[e] = cell_sink_addr(tab);
+}
+
 __device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, int list_cap) {
     CellTab tab;
     tab.bits = bits;
@@ -1026,6 +1042,7 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     const PartChunk c = part_chunk_at(part_lds, a, 64);
     const CellTab tab = part_table_at(part_lds + part_chunk_bytes(a, 64), a.cell_bits, 64 * a.cells_max);
     for (int s = lane; s < (1 << a.cell_bits); s += 64) tab.slot[s].key = 0;
+    part_init_rows(c, tab, lane, 64);
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
 
@@ -1079,6 +1096,8 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
     __syncthreads();
     if (!flag[0]) return;
     for (int s = tid; s < cap; s += nthr) tab.slot[s].key = 0;
+    part_init_rows(buf(0), tab, tid, nthr);
+    part_init_rows(buf(1), tab, tid, nthr);
     if (tid == 0) *tab.nlist = 0;
 
     const uint32_t* pos = a.ws.qv[a.part_passes & 1];
