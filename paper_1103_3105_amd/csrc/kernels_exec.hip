@@ -798,6 +798,61 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     return s;
 }
 
+// Cellwise procedures (proc_cellwise) run one transaction at a time, with
+// lane r handling cell ordinal r: a transaction's cells are read, updated
+// and written by one LDS instruction each (a wave's LDS instruction costs
+// about the same for one active lane as for several).  Cell addresses and
+// parameters are read two transactions ahead and cell values one ahead,
+// before the running transaction writes; a lane forwards its new value when
+// the next transaction names the same cell at its ordinal (cells of other
+// ordinals are other columns).  Lanes past the procedure's cells return.
+struct LaneRegs {
+    uint32_t id;
+    int64_t val;
+};
+template <int P, int NP>
+__device__ __forceinline__ void lanes_step(const PartChunk& c, int k, int r, LaneRegs& X, LaneRegs& Y,
+                                           LaneRegs& Z, const int64_t* xp, int64_t* zp) {
+    Z.id = c.cs[(k + 2) * c.css + r];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) zp[j] = c.prm[(k + 2) * c.ps + j];
+    Y.val = *(GTX_LDS const int64_t*)(uintptr_t)Y.id;
+    int64_t nv, res;
+    bool w;
+    int at;
+    cell_apply<P>(r, X.val, xp, nv, w, at, res);
+    if (w) *(GTX_LDS int64_t*)(uintptr_t)X.id = nv;
+    if (at >= 0) c.res[k * c.rs + at] = res;
+    if (Y.id == X.id) Y.val = nv;
+}
+
+template <int P>
+__device__ __forceinline__ void part_serial_lanes(const PartChunk& c, int cnt, int64_t& committed) {
+    constexpr int NP = proc_params(P);
+    constexpr int NC = proc_cells(P);
+    const int r = lane_id();
+    if (r >= NC) return;
+    LaneRegs A, B, C;
+    int64_t pa[NP], pb[NP], pc[NP];
+    A.id = c.cs[r];
+    B.id = c.cs[c.css + r];  // row 1 exists even if cnt == 1
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+        pa[j] = c.prm[j];
+        pb[j] = c.prm[c.ps + j];
+    }
+    A.val = *(GTX_LDS const int64_t*)(uintptr_t)A.id;
+    int k = 0;
+    for (; k + 2 < cnt; k += 3) {  // three steps with rotated registers: no moves
+        lanes_step<P, NP>(c, k, r, A, B, C, pa, pc);
+        lanes_step<P, NP>(c, k + 1, r, B, C, A, pb, pa);
+        lanes_step<P, NP>(c, k + 2, r, C, A, B, pc, pb);
+    }
+    if (k < cnt) lanes_step<P, NP>(c, k, r, A, B, C, pa, pc);
+    if (k + 1 < cnt) lanes_step<P, NP>(c, k + 1, r, B, C, A, pb, pa);
+    if (r == 0) committed += cnt;  // every cellwise procedure commits
+}
+
 // Lane 0 runs the chunk's cnt transactions in order against the staged
 // cells.  Statuses and results go to LDS; the owning lanes write them out
 // after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
@@ -817,6 +872,10 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NR = proc_results(P); // results it can write (P == 0: up to res_rows)
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
+    if constexpr (P != 0 && proc_cellwise(P) && proc_typed_cells(P) && NP <= 8 && NC <= 64) {
+        part_serial_lanes<P>(c, cnt, committed);
+        return;
+    }
     if (lane_id() != 0) return;
     uint32_t seen = ~0u;
     if constexpr (ahead) {

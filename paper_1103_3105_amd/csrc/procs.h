@@ -290,6 +290,16 @@ __host__ __device__ constexpr int proc_params(int proc) {
 __host__ __device__ constexpr bool proc_typed_cells(int proc) {
     return proc != 0 && proc != GPUTX_NEW_ORDER;
 }
+// Procedures whose effect on each of their cells depends only on that cell's
+// old value and the parameters: no cell's value decides what happens to
+// another, and each cell is named once.  Cell r's new value, whether it is
+// written, and the result it yields can then be computed by lane r alone
+// (cell_apply below restates these procedures of txn_exec_p per cell).
+__host__ __device__ constexpr bool proc_cellwise(int proc) {
+    return proc == GPUTX_DEBIT_CREDIT || proc == GPUTX_PAYMENT || proc == GPUTX_ORDER_STATUS ||
+           proc == GPUTX_GET_SUB || proc == GPUTX_GET_CF || proc == GPUTX_UPD_SUB_FIELD ||
+           proc == GPUTX_UPD_LOC;
+}
 // Results procedure P can write (0: any procedure).
 __host__ __device__ constexpr int proc_results(int proc) {
     return proc == GPUTX_NEW_ORDER ? 16 : proc == GPUTX_GET_SUB ? 14
@@ -422,6 +432,44 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
     }
     }
     return GPUTX_INVALID;
+}
+
+// Cell r of a cellwise procedure P (proc_cellwise), with old value old (an
+// int32 cell sign-extended): its new value nv, whether it is written, and
+// result res at index res_at (-1: none).  Every cellwise procedure commits.
+template <int P>
+__device__ __forceinline__ void cell_apply(int r, int64_t old, const int64_t* p, int64_t& nv, bool& w,
+                                           int& res_at, int64_t& res) {
+    static_assert(proc_cellwise(P), "cell_apply: procedure is not cellwise");
+    switch (P) {
+    case GPUTX_DEBIT_CREDIT:  // account, teller, branch balance += delta; results: the new balances
+    case GPUTX_PAYMENT:       // warehouse, district, customer balance += h; results: the new balances
+        nv = wrap_add(old, p[3]);
+        w = true;
+        res_at = r;
+        res = nv;
+        break;
+    case GPUTX_ORDER_STATUS:  // read the customer balance
+        nv = old;
+        w = false;
+        res_at = 0;
+        res = old;
+        break;
+    case GPUTX_GET_SUB:  // read every field of the subscriber row
+    case GPUTX_GET_CF:   // read the call-forwarding slot
+        nv = old;
+        w = false;
+        res_at = r;
+        res = old;
+        break;
+    case GPUTX_UPD_SUB_FIELD:  // result: the old field value; the field becomes p[2]
+    case GPUTX_UPD_LOC:
+        nv = (int64_t)to_i32(p[2]);
+        w = true;
+        res_at = 0;
+        res = old;
+        break;
+    }
 }
 
 // The combined kernel's switch on the procedure (Section 3.2), any accessor.
