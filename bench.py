@@ -323,8 +323,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how it would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the engine has no multi-GPU path "
+              "(the design notes describe how it would shard)", file=sys.stderr)
         raise SystemExit(2)
 
     import torch

@@ -12,7 +12,8 @@ LIB = os.path.join(PKG, "libgputx.so")
 SOURCES = ["runtime.hip", "serve.hip", "kernels_front.hip", "kernels_exec.hip", "sort.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # packed fp32 instructions stay off (platform notes)
+    # packed fp32 instructions stay off: some of their forms have produced
+    # wrong results with no error on gfx950
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]

@@ -580,11 +580,12 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
 // Signatures of one PART chunk of cw transactions staged in LDS.  Parameters,
 // cell addresses and results are stored one row per transaction (rows of a
 // 16-byte multiple), so the serial lane reads a transaction's cell addresses
-// with one LDS load; the parameter and address arrays have two spare rows so
-// reading two transactions ahead needs no bound.
+// with one LDS load; the parameter and address arrays have kChunkSpare spare
+// rows so reading up to three transactions ahead needs no bound.
+constexpr int kChunkSpare = 4;
 struct PartChunk {
     int64_t* res;   // [cw][rs] results
-    int64_t* prm;   // [cw + 2][ps] parameters
+    int64_t* prm;   // [cw + kChunkSpare][ps] parameters
     int64_t* ts;    // [cw]
     int64_t* app0;  // [cw]
     int64_t* app1;  // [cw]
@@ -592,7 +593,8 @@ struct PartChunk {
     int32_t* t;     // [cw] type
     int32_t* proc;  // [cw] procedure
     int32_t* st;    // [cw] status
-    uint32_t* cs;   // [cw + 2][css] LDS address of each of the transaction's staged cells
+    uint32_t* cs;   // [cw + kChunkSpare][css] LDS address of each of the transaction's staged cells
+    uint8_t* grp;   // [css][cw] per ordinal and window: sorted slot -> transaction (part_group)
     int cw, ps, css, rs;
 };
 __host__ __device__ inline int part_ps(int prm_rows) { return (prm_rows + 1) & ~1; }
@@ -612,8 +614,9 @@ struct __attribute__((aligned(16))) CellSlot {
 struct CellTab {
     GTX_LDS CellSlot* slot;  // [1 << bits], then one sink slot outside the table
     GTX_LDS int32_t* list;   // claimed slots
-    GTX_LDS int32_t* nlist;
-    int bits;
+    GTX_LDS int32_t* nlist;  // [4]: the count, then two flags of the pipelined form
+    GTX_LDS uint8_t* tag;    // [staging waves][tstride]: part_group's scratch per wave
+    int bits, tstride;
 };
 // LDS address of a slot's value (16-byte slots: bit 3 is set), and of the
 // sink slot's key (bit 3 clear), which stands for an ordinal no cell backs.
@@ -798,59 +801,114 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     return s;
 }
 
-// Cellwise procedures (proc_cellwise) run one transaction at a time, with
-// lane r handling cell ordinal r: a transaction's cells are read, updated
-// and written by one LDS instruction each (a wave's LDS instruction costs
-// about the same for one active lane as for several).  Cell addresses and
-// parameters are read two transactions ahead and cell values one ahead,
-// before the running transaction writes; a lane forwards its new value when
-// the next transaction names the same cell at its ordinal (cells of other
-// ordinals are other columns).  Lanes past the procedure's cells return.
-struct LaneRegs {
-    uint32_t id;
-    int64_t val;
-};
-template <int P, int NP>
-__device__ __forceinline__ void lanes_step(const PartChunk& c, int k, int r, LaneRegs& X, LaneRegs& Y,
-                                           LaneRegs& Z, const int64_t* xp, int64_t* zp) {
-    Z.id = c.cs[(k + 2) * c.css + r];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) zp[j] = c.prm[(k + 2) * c.ps + j];
-    Y.val = *(GTX_LDS const int64_t*)(uintptr_t)Y.id;
-    int64_t nv, res;
-    bool w;
-    int at;
-    cell_apply<P>(r, X.val, xp, nv, w, at, res);
-    if (w) *(GTX_LDS int64_t*)(uintptr_t)X.id = nv;
-    if (at >= 0) c.res[k * c.rs + at] = res;
-    if (Y.id == X.id) Y.val = nv;
+// Wave-wide inclusive scans through DPP (GFX9 controls: shift right within
+// 16-lane rows, then the broadcasts of lanes 15 and 31 that carry the scan
+// across rows).  All 64 lanes must be active.
+constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add_step(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ int wave_incl_sum_dpp(int v) {
+    v = dpp_add_step<kDppRowShr + 1, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 2, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 4, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 8, 0xf>(v);
+    v = dpp_add_step<kDppBcast15, 0xa>(v);
+    return dpp_add_step<kDppBcast31, 0xc>(v);
+}
+// Maps v -> a ? v + b : b (wrapping add; a is 0 or 1).  A lane composes its
+// map after the one it receives; lanes without a source receive the
+// identity (1, 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_affine_step(int& a, int64_t& b) {
+    const uint64_t ub = (uint64_t)b;
+    const int pa = __builtin_amdgcn_update_dpp(1, a, CTRL, ROWS, 0xf, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)ub, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(ub >> 32), CTRL, ROWS, 0xf, false);
+    const int64_t pb = (int64_t)(((uint64_t)hi << 32) | lo);
+    b = a ? wrap_add(pb, b) : b;
+    a &= pa;
+}
+__device__ __forceinline__ void wave_affine_scan(int& a, int64_t& b) {
+    dpp_affine_step<kDppRowShr + 1, 0xf>(a, b);
+    dpp_affine_step<kDppRowShr + 2, 0xf>(a, b);
+    dpp_affine_step<kDppRowShr + 4, 0xf>(a, b);
+    dpp_affine_step<kDppRowShr + 8, 0xf>(a, b);
+    dpp_affine_step<kDppBcast15, 0xa>(a, b);
+    dpp_affine_step<kDppBcast31, 0xc>(a, b);
 }
 
+__device__ __forceinline__ int64_t wave_shr1(int64_t v) {  // lane i gets lane i - 1's v, lane 0 gets 0
+    constexpr int kDppWaveShr1 = 0x138;
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, kDppWaveShr1, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), kDppWaveShr1, 0xf, 0xf, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Cellwise procedures (proc_cellwise) run a window of up to 64 transactions
+// at a time, one cell ordinal after the other (cells of different ordinals
+// are different columns, so ordinals do not interact).  A transaction's
+// effect on its cell is the map v -> a ? v + b : b (cell_affine), and such
+// maps compose into maps of the same form, so the value a transaction sees
+// -- the maps of the earlier transactions on the same cell applied in order
+// to the staged value -- is a prefix composition.  The staging wave that
+// fetched the window sorted each ordinal's transactions into groups naming
+// the same cell, each group contiguous and in timestamp order (part_group);
+// lane s takes the transaction at sorted slot s.  The group's first map is
+// replaced by the constant it yields from the staged value, so one scan over
+// the wave gives every lane the value after its transaction without anything
+// crossing a group boundary, and the lane before it holds the value before.
+// The last lane of each group writes the cell.  The result equals running
+// the window's transactions one after another.  Read-only procedures see the
+// staged values and need no grouping.
 template <int P>
-__device__ __forceinline__ void part_serial_lanes(const PartChunk& c, int cnt, int64_t& committed) {
+__device__ __forceinline__ void lanes_window(const PartChunk& c, int k0, int n) {
     constexpr int NP = proc_params(P);
     constexpr int NC = proc_cells(P);
-    const int r = lane_id();
-    if (r >= NC) return;
-    LaneRegs A, B, C;
-    int64_t pa[NP], pb[NP], pc[NP];
-    A.id = c.cs[r];
-    B.id = c.cs[c.css + r];  // row 1 exists even if cnt == 1
+    constexpr bool kW = proc_cell_writes(P);
+    const int s = lane_id();
+    const bool live = s < n;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-        pa[j] = c.prm[j];
-        pb[j] = c.prm[c.ps + j];
+    for (int r = 0; r < NC; ++r) {
+        int k = k0 + s;  // < cw: every row read exists
+        bool head = true, last = true;
+        if constexpr (kW) {
+            const uint32_t g = c.grp[r * c.cw + k0 + s];
+            k = k0 + (int)(g & 63u);
+            head = g & 64u;
+            last = g & 128u;
+        }
+        const uint32_t id = c.cs[k * c.css + r];
+        int64_t p[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) p[q] = c.prm[k * c.ps + q];
+        const int64_t init = *(GTX_LDS const int64_t*)(uintptr_t)id;
+        int64_t old = init;
+        if constexpr (kW) {
+            bool fa;
+            int64_t fb;
+            cell_affine<P>(r, p, fa, fb);
+            int a = fa;
+            int64_t b = fb;
+            if (head) {
+                b = a ? wrap_add(init, b) : b;
+                a = 0;
+            }
+            wave_affine_scan(a, b);
+            const int64_t before = wave_shr1(b);
+            old = head ? init : before;
+        }
+        int64_t nv, res;
+        bool w;
+        int at;
+        cell_apply<P>(r, old, p, nv, w, at, res);
+        if (live) {
+            if (at >= 0) c.res[k * c.rs + at] = res;
+            if (w && last) *(GTX_LDS int64_t*)(uintptr_t)id = nv;
+        }
     }
-    A.val = *(GTX_LDS const int64_t*)(uintptr_t)A.id;
-    int k = 0;
-    for (; k + 2 < cnt; k += 3) {  // three steps with rotated registers: no moves
-        lanes_step<P, NP>(c, k, r, A, B, C, pa, pc);
-        lanes_step<P, NP>(c, k + 1, r, B, C, A, pb, pa);
-        lanes_step<P, NP>(c, k + 2, r, C, A, B, pc, pb);
-    }
-    if (k < cnt) lanes_step<P, NP>(c, k, r, A, B, C, pa, pc);
-    if (k + 1 < cnt) lanes_step<P, NP>(c, k + 1, r, B, C, A, pb, pa);
-    if (r == 0) committed += cnt;  // every cellwise procedure commits
 }
 
 // Lane 0 runs the chunk's cnt transactions in order against the staged
@@ -872,8 +930,9 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NR = proc_results(P); // results it can write (P == 0: up to res_rows)
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
-    if constexpr (P != 0 && proc_cellwise(P) && proc_typed_cells(P) && NP <= 8 && NC <= 64) {
-        part_serial_lanes<P>(c, cnt, committed);
+    if constexpr (P != 0 && proc_cellwise(P) && proc_typed_cells(P) && NP <= 8) {
+        for (int k0 = 0; k0 < cnt; k0 += 64) lanes_window<P>(c, k0, min(64, cnt - k0));
+        if (lane_id() == 0) committed += cnt;  // every cellwise procedure commits
         return;
     }
     if (lane_id() != 0) return;
@@ -947,16 +1006,28 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
 
 
 __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
-    return (size_t)8 * part_rs(a.res_rows) * cw + (size_t)8 * part_ps(a.prm_rows) * (cw + 2) +
-           (size_t)8 * 4 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + 2);
+    return (size_t)8 * part_rs(a.res_rows) * cw + (size_t)8 * part_ps(a.prm_rows) * (cw + kChunkSpare) +
+           (size_t)8 * 4 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare) +
+           (size_t)part_css(a.cells_max) * cw;
 }
+// Per staging wave: 64 group masks (8 bytes each), then a tag byte per slot.
+__host__ __device__ inline int part_tstride(int bits) { return 512 + (1 << bits) + 16; }
 size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
-           (size_t)4 * (64 * a.cells_max + 4);
+           (size_t)4 * (64 * a.cells_max + 4) + part_tstride(a.cell_bits);
 }
 size_t part_pipe_lds(const BulkArgs& a, int cw) {
     return 2 * part_chunk_bytes(a, cw) + ((size_t)sizeof(CellSlot) << a.pipe_bits) + sizeof(CellSlot) +
-           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4);
+           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4) + (size_t)(cw / 64) * part_tstride(a.pipe_bits);
+}
+// Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
+// limit (160 KB on gfx950), or the default 64 KB if raising it fails.
+static size_t g_part_lds_limit = 64 * 1024;
+// The pipelined form of width cw runs when its LDS fits and one chunk's cells
+// fit in half the table (the table is flushed at half-full).
+static bool part_pipe_fits(const BulkArgs& a, int cw) {
+    return a.part_pipeline && part_pipe_lds(a, cw) <= g_part_lds_limit &&
+           (int64_t(1) << a.pipe_bits) >= int64_t(2) * cw * a.cells_max;
 }
 
 __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const BulkArgs& a, int cw) {
@@ -967,7 +1038,7 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     c.rs = part_rs(a.res_rows);
     c.res = reinterpret_cast<int64_t*>(base);
     c.prm = c.res + cw * c.rs;
-    c.ts = c.prm + (cw + 2) * c.ps;
+    c.ts = c.prm + (cw + kChunkSpare) * c.ps;
     c.app0 = c.ts + cw;
     c.app1 = c.app0 + cw;
     c.idx = c.app1 + cw;
@@ -975,6 +1046,7 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     c.proc = c.t + cw;
     c.st = c.proc + cw;
     c.cs = reinterpret_cast<uint32_t*>(c.st + cw);
+    c.grp = reinterpret_cast<uint8_t*>(c.cs + (cw + kChunkSpare) * c.css);
     return c;
 }
 
@@ -1009,6 +1081,60 @@ __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c
     AppendOnlyAcc ap;
     int64_t unused[GTX_MAX_RESULTS];
     (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+}
+
+// Staging side of the window form (lanes_window).  When the live lanes of
+// the calling wave -- one window of the chunk -- all run one cellwise
+// procedure that writes cells, each cell ordinal's lanes are grouped by the
+// cell they name and sorted, stably, by group: every lane stores its lane
+// number in the wave's tag byte of its cell's slot, and the value it reads
+// back (one of the group's lanes, the same for the whole group) names the
+// group; each lane ORs its bit into that lane's group mask, then reads the
+// mask.  For sorted slot s the window's byte grp[r][s] holds the
+// transaction's lane (bits 0-5), and whether s starts (bit 6) or ends (bit 7)
+// its group.  Lanes past the chunk's transactions are groups of their own.
+// Needs all 64 lanes of the wave.
+__device__ __forceinline__ void part_group(const PartChunk& c, const CellTab& tab, int64_t c0, int64_t end,
+                                           int lane) {
+    const int j = lane & 63;
+    const int w0 = lane - j;
+    const bool live = c0 + lane < end;
+    if (__ballot(live) == 0) return;
+    const int proc = __builtin_amdgcn_readfirstlane(c.proc[w0]);  // the window's first lane is live
+    if (__ballot(live && c.proc[lane] != proc) != 0 || !proc_cellwise(proc) || !proc_typed_cells(proc) ||
+        !proc_cell_writes(proc))
+        return;
+    GTX_LDS uint8_t* mine = tab.tag + (lane >> 6) * tab.tstride;
+    GTX_LDS uint64_t* gmask = (GTX_LDS uint64_t*)mine;
+    // volatile: the read must see whichever lane's store landed, not this lane's
+    volatile GTX_LDS uint8_t* tag = mine + 512;
+    const uint64_t below = lanemask_lt();
+    const uint32_t base = lds_addr(tab.slot);
+    const int nc = proc_cells(proc);
+    for (int r = 0; r < nc; ++r) {
+        const uint32_t h = (c.cs[lane * c.css + r] - base) >> 4;  // slot; the sink is slot 1 << bits
+        gmask[j] = 0;
+        int rep = j;
+        if (live) {
+            tag[h] = (uint8_t)j;
+            rep = tag[h];
+        }
+        __hip_atomic_fetch_or(&gmask[rep], 1ull << j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const uint64_t eq = __hip_atomic_load(&gmask[rep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int rank = __popcll(eq & below);
+        const int size = __popcll(eq);
+        const int own = rep == j ? size : 0;
+        const int pos = __shfl(wave_incl_sum_dpp(own) - own, rep) + rank;
+        c.grp[r * c.cw + w0 + pos] = (uint8_t)(j | (rank == 0 ? 64 : 0) | (rank == size - 1 ? 128 : 0));
+    }
+}
+
+// Fetch a chunk's transactions (part_fetch), then group each window's cells
+// for the window form (part_group).
+__device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
+    part_fetch(a, c, tab, pos, c0, end, lane);
+    part_group(c, tab, c0, end, lane);
 }
 
 // The owning lanes write the chunk's statuses and results.
@@ -1075,7 +1201,7 @@ __device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChun
 // serial lane's read-ahead past the chunk's last transaction always finds an
 // address inside the table.
 __device__ __forceinline__ void part_init_rows(const PartChunk& c, const CellTab& tab, int tid, int nthreads) {
-    for (int e = tid; e < (c.cw + 2) * c.css; e += nthreads) c.cs[e] = cell_sink_addr(tab);
+    for (int e = tid; e < (c.cw + kChunkSpare) * c.css; e += nthreads) c.cs[e] = cell_sink_addr(tab);
 }
 
 __device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, int list_cap) {
@@ -1084,6 +1210,8 @@ __device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, 
     tab.slot = (GTX_LDS CellSlot*)base;
     tab.list = (GTX_LDS int32_t*)(tab.slot + (1 << bits) + 1);
     tab.nlist = tab.list + list_cap;
+    tab.tag = (GTX_LDS uint8_t*)(tab.nlist + 4);
+    tab.tstride = part_tstride(bits);
     return tab;
 }
 
@@ -1112,7 +1240,7 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
-            part_fetch(a, c, tab, pos, c0, end, lane);
+            part_stage(a, c, tab, pos, c0, end, lane);
             __syncthreads();
             part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
@@ -1167,7 +1295,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        if (!serial) part_fetch(a, buf(0), tab, pos, lo, end, sl);
+        if (!serial) part_stage(a, buf(0), tab, pos, lo, end, sl);
         __syncthreads();
         for (int64_t k = 0; k < nch; ++k) {
             const int64_t c0 = lo + cw * k;
@@ -1178,7 +1306,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
                 bool flush = false;
                 if (k + 1 < nch) {
                     flush = *tab.nlist + cw * a.cells_max > cap / 2;
-                    if (!flush) part_fetch(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
+                    if (!flush) part_stage(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
                 }
                 if (sl == 0) flag[k & 1] = flush;
             }
@@ -1188,7 +1316,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
                 __syncthreads();
                 if (tid == 0) *tab.nlist = 0;
                 __syncthreads();
-                if (!serial) part_fetch(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
+                if (!serial) part_stage(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
                 __syncthreads();
             }
         }
@@ -1251,9 +1379,6 @@ void launch_empty(const BulkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
 }
 
-// Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
-// limit (160 KB on gfx950), or the default 64 KB if raising it fails.
-static size_t g_part_lds_limit = 64 * 1024;
 
 void exec_init_attributes(int dev) {
     static bool done = false;
@@ -1265,6 +1390,8 @@ void exec_init_attributes(int dev) {
     const int want = std::min(optin, kPartLdsMax);
     if (hipFuncSetAttribute((const void*)k_part_wave, hipFuncAttributeMaxDynamicSharedMemorySize, want) ==
             hipSuccess &&
+        hipFuncSetAttribute((const void*)k_part_pipe<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            want) == hipSuccess &&
         hipFuncSetAttribute((const void*)k_part_pipe<128>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             want) == hipSuccess &&
         hipFuncSetAttribute((const void*)k_part_pipe<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1307,15 +1434,18 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     pm.mark(PH_PARTSORT, s);
     if (part) {
         // long partitions: a workgroup each with the LDS cell table (chunks of
-        // 128 transactions staged by two waves where the LDS fits, else 64,
-        // e.g. for new-order's wide signature); short ones: a lane each
+        // 256 transactions staged by four waves where the LDS fits, else 128
+        // or 64, e.g. for new-order's wide signature); short ones: a lane each
         BulkArgs b = a;
-        const bool pipe128 = a.part_pipeline && part_pipe_lds(a, 128) <= g_part_lds_limit;
-        const bool pipe64 = !pipe128 && a.part_pipeline && part_pipe_lds(a, 64) <= g_part_lds_limit;
-        const bool wave = !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
-        b.long_part = (pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
+        const bool pipe256 = part_pipe_fits(a, 256);
+        const bool pipe128 = !pipe256 && part_pipe_fits(a, 128);
+        const bool pipe64 = !pipe256 && !pipe128 && part_pipe_fits(a, 64);
+        const bool wave = !pipe256 && !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
+        b.long_part = (pipe256 || pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
-        if (pipe128)
+        if (pipe256)
+            hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 + 256), part_pipe_lds(a, 256), s, b);
+        else if (pipe128)
             hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 + 128), part_pipe_lds(a, 128), s, b);
         else if (pipe64)
             hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 + 64), part_pipe_lds(a, 64), s, b);

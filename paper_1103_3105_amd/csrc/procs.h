@@ -300,6 +300,11 @@ __host__ __device__ constexpr bool proc_cellwise(int proc) {
            proc == GPUTX_GET_SUB || proc == GPUTX_GET_CF || proc == GPUTX_UPD_SUB_FIELD ||
            proc == GPUTX_UPD_LOC;
 }
+// Cellwise procedures that write their cells.
+__host__ __device__ constexpr bool proc_cell_writes(int proc) {
+    return proc == GPUTX_DEBIT_CREDIT || proc == GPUTX_PAYMENT || proc == GPUTX_UPD_SUB_FIELD ||
+           proc == GPUTX_UPD_LOC;
+}
 // Results procedure P can write (0: any procedure).
 __host__ __device__ constexpr int proc_results(int proc) {
     return proc == GPUTX_NEW_ORDER ? 16 : proc == GPUTX_GET_SUB ? 14
@@ -432,6 +437,33 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
     }
     }
     return GPUTX_INVALID;
+}
+
+// The same per-cell effect as a map of the cell's old value,
+// v -> a ? v + b : b (wrapping add): cell_apply's new value for every old
+// value.  Two such maps compose into one of the same form.
+template <int P>
+__device__ __forceinline__ void cell_affine(int r, const int64_t* p, bool& a, int64_t& b) {
+    static_assert(proc_cellwise(P), "cell_affine: procedure is not cellwise");
+    (void)r;
+    switch (P) {
+    case GPUTX_DEBIT_CREDIT:
+    case GPUTX_PAYMENT:
+        a = true;
+        b = p[3];
+        break;
+    case GPUTX_ORDER_STATUS:
+    case GPUTX_GET_SUB:
+    case GPUTX_GET_CF:
+        a = true;
+        b = 0;
+        break;
+    case GPUTX_UPD_SUB_FIELD:
+    case GPUTX_UPD_LOC:
+        a = false;
+        b = (int64_t)to_i32(p[2]);
+        break;
+    }
 }
 
 // Cell r of a cellwise procedure P (proc_cellwise), with old value old (an

@@ -486,8 +486,10 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     while ((1 << a.cell_bits) < 2 * 64 * a.cells_max) ++a.cell_bits;
     // the pipelined form keeps cells across chunks: room for several chunks
     a.pipe_bits = a.cell_bits;
-    while ((1 << a.pipe_bits) < 4 * 128 * a.cells_max && a.pipe_bits < 12) ++a.pipe_bits;
-    if ((1 << a.pipe_bits) < 2 * 128 * a.cells_max) ++a.pipe_bits;  // one 128-chunk must fit in half
+    while ((1 << a.pipe_bits) < 4 * 256 * a.cells_max && a.pipe_bits < 12) ++a.pipe_bits;
+    // one chunk of the widest form that runs must fit in half the table;
+    // launch_exec picks the widest form whose LDS fits
+    while ((1 << a.pipe_bits) < 2 * 128 * a.cells_max) ++a.pipe_bits;
     *out = a;
     return GPUTX_OK;
 }

@@ -167,6 +167,35 @@ def test_part_partition_lengths(pipeline):
 
 
 @pytest.mark.parametrize("pipeline", [0, 1])
+@pytest.mark.parametrize("proc", ["PAYMENT", "ORDER_STATUS", "GET_SUB", "GET_CF",
+                                  "UPD_SUB_FIELD", "UPD_LOC"])
+def test_part_cellwise_one_procedure(proc, pipeline):
+    """Bulks of one cellwise procedure, so PART runs every chunk through the
+    window form (a scan over each cell's maps).  Hot keys put many
+    transactions on the same cells within a window: warehouse and district
+    rows under payment, a few hundred Zipf(0.99) subscribers under the
+    subscriber procedures, whose updates overwrite (maps with no old-value
+    term)."""
+    rng = np.random.default_rng(67)
+    n = 20_000
+    if proc in ("PAYMENT", "ORDER_STATUS"):
+        mix = (0.0, 1.0, 0.0) if proc == "PAYMENT" else (0.0, 0.0, 1.0)
+        bulk = wl.order_bulk(rng, n, 4, 10, 30, 500, mix=mix)
+        tabs = wl.order_tables(rng, 4, 10, 30, 500, 1, 1)
+        types, width, ps = wl.order_types(), 16, 1
+    else:
+        kinds = ["GET_SUB", "GET_CF", "UPD_SUB_FIELD", "UPD_LOC"]
+        mix = tuple(1.0 if kinds[i] == proc else 0.0 for i in range(4)) + (0.0, 0.0)
+        tabs = wl.sub_tables(rng, 300, occupancy=0.5)
+        bulk = wl.sub_bulk(rng, n, 300, 0.99, mix=mix)
+        types, width, ps = wl.sub_types(), 14, 16
+    _say("part cellwise", proc, pipeline)
+    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline)
+    assert s.chosen == 2, s.as_dict()
+    assert_parity(s, g, o, bulk)
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
 def test_part_mixed_type_ids(pipeline):
     """Debit-credit registered under two type ids: chunks are not of one type,
     so PART runs them through its generic serial path (which checks that every
