@@ -47,6 +47,10 @@ struct Ws {
     uint32_t* qv[2];     // [n] PART sort: serial position
     int32_t* heads;      // [n + 1] PART: first sorted position of each non-empty partition
     int32_t* heads_tmp;  // [head blocks] PART: per-block head counts, then offsets
+    // PART: each transaction PART runs, in partition order (k_part_gather)
+    int32_t* rec_i;      // [n] input index
+    int32_t* rec_t;      // [n] type
+    int64_t* rec_prm;    // [prm rows][n] parameters (zero past the type's own)
     int32_t* front[2];   // [n] K-SET frontiers
     uint32_t* sort_hist; // [8][256]
     uint32_t* sort_status;

@@ -11,14 +11,17 @@
 //              target, the transaction runs, every counter is incremented.
 //              Workgroups claim 256-transaction windows in timestamp order
 //              and group each window by type.
+//   k_part_gather PART: every transaction in partition order into records
+//              the partition kernels read contiguously; the appended rows.
 //   k_part_pipe PART (Section 5.2), few long partitions: one workgroup per
-//              partition; a staging wave puts each chunk's cells in an LDS
-//              table while lane 0 of the serial wave runs the previous chunk
-//              against it, one transaction after another.  k_part_wave is the
-//              one-wave form (stage, then run).
-//   k_part     PART, many small partitions: one lane per partition; binary
-//              search of the partition's range in the partition-sorted
-//              transactions, then its transactions run one after another.
+//              partition; staging waves put each chunk's cells in an LDS
+//              table while the serial wave runs the previous chunk against
+//              it, in timestamp order (one transaction at a time, or a
+//              window of 64 as a scan over each cell's updates when the
+//              procedure's effect on each cell is a map of the cell alone).
+//              k_part_wave is the one-wave form (stage, then run).
+//   k_part     PART, many small partitions: one lane per partition runs its
+//              transactions one after another.
 //   k_finalize batched update (Section 3.2): advance append-table row counts;
 //              publish statistics.
 #include "engine.h"
@@ -105,6 +108,22 @@ __device__ int32_t run_at(const BulkArgs& a, int64_t p, int32_t t) {
     TxnIn x;
     load_txn(a, p, t, x);
     return exec_txn(a, x);
+}
+
+// run_at without the transaction's appends (written beforehand).
+__device__ int32_t run_at_noapp(const BulkArgs& a, int64_t p, int32_t t) {
+    TxnIn x;
+    load_txn(a, p, t, x);
+    int64_t res[GTX_MAX_RESULTS];
+    NoAppendAcc acc;
+    const int32_t s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+    a.status[x.i] = s;
+    int64_t* out = a.results + x.i * a.width;
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+        if (r < a.width) out[r] = res[r];
+    for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
+    return s;
 }
 
 __device__ __forceinline__ void count_status(GtxState* st, bool ran, int32_t s) {
@@ -557,6 +576,33 @@ __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int6
 
 // One lane per short partition (fewer than a.long_part transactions): its
 // transactions run one after another, in place.
+// Before PART runs: every transaction it runs, in partition order, read
+// from the bulk into records the PART kernels read contiguously, and its
+// appended rows written (they depend on the signature alone).  The whole
+// device takes part; each partition's reads are otherwise scattered over
+// the bulk.
+__global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (failed(st) || st->chosen != GPUTX_PART) return;
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
+    const int64_t total = a.ws.heads[st->n_heads];
+    for (int64_t j = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; j < total;
+         j += (int64_t)gridDim.x * GTX_BLOCK) {
+        const int32_t p = (int32_t)pos[j];
+        const int32_t t = a.ws.tty[p];
+        TxnIn x;
+        load_txn(a, p, t, x);
+        a.ws.rec_i[j] = (int32_t)x.i;
+        a.ws.rec_t[j] = t;
+#pragma unroll
+        for (int k = 0; k < GTX_MAX_PARAMS; ++k)
+            if (k < a.prm_rows) a.ws.rec_prm[(int64_t)k * a.n + j] = x.prm[k];
+        AppendOnlyAcc ap;
+        int64_t unused[GTX_MAX_RESULTS];
+        (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+    }
+}
+
 __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
@@ -569,7 +615,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
         if (end - lo >= a.long_part) continue;  // a workgroup runs it
         for (int64_t i = lo; i < end; ++i) {
             const int32_t p = (int32_t)pos[i];
-            const int32_t s = run_at(a, p, a.ws.tty[p]);
+            const int32_t s = run_at_noapp(a, p, a.ws.tty[p]);
             committed += s == GPUTX_COMMIT;
             aborted += s == GPUTX_ABORT;
         }
@@ -586,9 +632,6 @@ constexpr int kChunkSpare = 4;
 struct PartChunk {
     int64_t* res;   // [cw][rs] results
     int64_t* prm;   // [cw + kChunkSpare][ps] parameters
-    int64_t* ts;    // [cw]
-    int64_t* app0;  // [cw]
-    int64_t* app1;  // [cw]
     int64_t* idx;   // [cw] input index (status / results slot)
     int32_t* t;     // [cw] type
     int32_t* proc;  // [cw] procedure
@@ -632,34 +675,38 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 }
 
 // Fetch side: each lane claims the cells of its transaction and records,
-// per cell ordinal, the LDS address of the cell's staged value.  The first claimant of a cell loads it
-// from global memory into the slot; a cell the procedure may write is marked
-// written (bit 0), so it is stored back when the table is flushed.
+// per cell ordinal, the LDS address of the cell's staged value.  A probe
+// reads the slot's key first: a cell staged already (the common case for
+// hot cells) costs no atomic, and an empty slot is taken with a CAS.  A cell
+// the procedure may write is marked written (bit 0), so it is stored back
+// when the table is flushed.  The first claimant of a cell (won, one bit per
+// ordinal) lists the slot and loads the cell's value afterwards
+// (part_claim_wave, claim_values): all of a transaction's claims go first,
+// so its loads are in flight together.
 struct CellClaim {
     CellTab tab;
     uint32_t* cs;  // the transaction's row of cell addresses
+    uint32_t won;
     template <class V>
     __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
-        const V v = *p;  // issued before the claim; kept only by the winner
         const uint64_t key = cell_key(p);
+        const uint64_t want = key | (w ? 1u : 0u);
         const uint32_t mask = (1u << tab.bits) - 1;
         uint32_t h = cell_hash(key, tab.bits);
         uint32_t got = cell_sink_addr(tab);  // no free slot: the serial side reports the miss
         for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1) & mask) {
-            uint64_t prev = 0;
-            __hip_atomic_compare_exchange_strong(&tab.slot[h].key, &prev, key | (w ? 1u : 0u),
-                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (prev == 0) {
-                tab.slot[h].val = (int64_t)v;
-                const int e = __hip_atomic_fetch_add(tab.nlist, 1, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-                tab.list[e] = (int32_t)h;
-                got = cell_val_addr(tab, h);
-                break;
+            uint64_t cur = __hip_atomic_load(&tab.slot[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == 0) {
+                __hip_atomic_compare_exchange_strong(&tab.slot[h].key, &cur, want, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (cur == 0) {
+                    got = cell_val_addr(tab, h);
+                    won |= 1u << ord;
+                    break;
+                }
             }
-            if ((prev & ~(uint64_t)1) == key) {  // staged already
-                if (w && !(prev & 1))
+            if ((cur & ~(uint64_t)1) == key) {  // staged already
+                if (w && !(cur & 1))
                     __hip_atomic_fetch_or(&tab.slot[h].key, (uint64_t)1, __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 got = cell_val_addr(tab, h);
@@ -669,6 +716,24 @@ struct CellClaim {
         cs[ord] = got;
     }
 };
+// The won cells' values, four loads in flight at a time; the slot's key holds
+// the cell's global address and width.
+__device__ __forceinline__ void claim_values(const uint32_t* cs, uint32_t won) {
+    for (int r0 = 0; won >> r0; r0 += 4) {
+        int64_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if ((won >> (r0 + q)) & 1u) {
+                const uint64_t key = *(GTX_LDS const uint64_t*)(uintptr_t)(cs[r0 + q] - 8);
+                const uint64_t at = key & ~(uint64_t)3;
+                v[q] = (key & 2) ? *(GTX_GLOBAL const int64_t*)at : (int64_t)*(GTX_GLOBAL const int32_t*)at;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if ((won >> (r0 + q)) & 1u) *(GTX_LDS int64_t*)(uintptr_t)cs[r0 + q] = v[q];
+    }
+}
 
 // Serial side: the procedures' accessor over the staged cells.  The fetch
 // lanes resolved every cell ordinal of the transaction to the LDS address
@@ -768,7 +833,7 @@ __device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChun
     for (int r = 0; r < GTX_MAX_PARAMS; ++r) prm[r] = r < NP ? X.prm[r] : 0;
     RegAcc acc{X.ids, X.val};
     int64_t res[GTX_MAX_RESULTS];
-    const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+    const int32_t s = txn_exec_p<P>(acc, T, prm, 0, 0, 0, res);  // appends: k_part_gather
     if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
 #pragma unroll
     for (int r = 0; r < NR; ++r) c.res[k * c.rs + r] = res[r];
@@ -794,7 +859,7 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     for (int r = 0; r < NC; ++r) ids[r] = c.cs[k * c.css + r];
     LdsAcc acc{ids, seen};
     int64_t res[GTX_MAX_RESULTS];
-    const int32_t s = txn_exec_p<P>(acc, T, prm, c.ts[k], c.app0[k], c.app1[k], res);
+    const int32_t s = txn_exec_p<P>(acc, T, prm, 0, 0, 0, res);  // appends: k_part_gather
     if (s != GPUTX_COMMIT) c.st[k] = s;  // staged as COMMIT
 #pragma unroll
     for (int r = 0; r < NR; ++r) c.res[k * c.rs + r] = res[r];
@@ -1007,7 +1072,7 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
 
 __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
     return (size_t)8 * part_rs(a.res_rows) * cw + (size_t)8 * part_ps(a.prm_rows) * (cw + kChunkSpare) +
-           (size_t)8 * 4 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare) +
+           (size_t)8 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare) +
            (size_t)part_css(a.cells_max) * cw;
 }
 // Per staging wave: 64 group masks (8 bytes each), then a tag byte per slot.
@@ -1038,10 +1103,7 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     c.rs = part_rs(a.res_rows);
     c.res = reinterpret_cast<int64_t*>(base);
     c.prm = c.res + cw * c.rs;
-    c.ts = c.prm + (cw + kChunkSpare) * c.ps;
-    c.app0 = c.ts + cw;
-    c.app1 = c.app0 + cw;
-    c.idx = c.app1 + cw;
+    c.idx = c.prm + (cw + kChunkSpare) * c.ps;
     c.t = reinterpret_cast<int32_t*>(c.idx + cw);
     c.proc = c.t + cw;
     c.st = c.proc + cw;
@@ -1050,37 +1112,98 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     return c;
 }
 
-// One lane per transaction of the chunk starting at c0: load its signature
-// into the chunk buffer, write its appended rows (insert buffers, Section
-// 3.2) and stage its cells in the table.
-__device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
-    const int64_t j = c0 + lane;
-    if (j >= end) return;
-    const int32_t p = (int32_t)pos[j];
-    const int32_t t = a.ws.tty[p];
+// A staging lane's transaction as read a step before its cells are claimed,
+// from the partition-order records (k_part_gather): its partition-order
+// position j, type, input index and first kStagePrm parameters (wider
+// signatures read the rest when claimed).  Consecutive lanes read
+// consecutive records.  Timestamps and append rows serve only the appends,
+// which k_part_gather wrote.
+constexpr int kStagePrm = 8;
+struct StagedTxn {
+    int64_t i;
+    int32_t j, t;
+    int64_t prm[kStagePrm];
+};
+__device__ __forceinline__ void stage_load(const BulkArgs& a, int32_t j, StagedTxn& x) {
+    x.j = j;
+    x.t = a.ws.rec_t[j];
+    x.i = a.ws.rec_i[j];
+#pragma unroll
+    for (int k = 0; k < kStagePrm; ++k) x.prm[k] = k < a.prm_rows ? a.ws.rec_prm[(int64_t)k * a.n + j] : 0;
+}
+
+// One lane per transaction of a chunk (the lane's row): write its signature
+// into the chunk buffer and stage its cells in the table (its appended rows
+// were written by k_part_gather).  The cells are claimed first, then the won
+// cells' values are read together.
+// kUniform: every transaction of the wave has type tu, whose descriptor is
+// then read through the scalar cache.
+template <bool kUniform>
+__device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                               const StagedTxn& s, int lane, int32_t tu) {
+    const int32_t t = kUniform ? tu : s.t;
+    const DevType& T = a.types[t];
     TxnIn x;
-    load_txn(a, p, t, x);
+    x.t = t;
+    x.i = s.i;
+    x.ts = 0;
+    x.np = min(a.n_params, T.n_params);
+#pragma unroll
+    for (int k = 0; k < GTX_MAX_PARAMS; ++k)
+        x.prm[k] = k >= x.np ? 0 : k < kStagePrm ? s.prm[k] : a.ws.rec_prm[(int64_t)k * a.n + s.j];
+    for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
+    CellClaim claim{tab, c.cs + lane * c.css, 0u};
+    txn_cells(T, x.prm, claim);
+    x.app0 = 0;
+    x.app1 = 0;
+    claim_values(claim.cs, claim.won);
     const int rows = a.prm_rows;
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-        if (k < rows) c.prm[lane * c.ps + k] = k < x.np ? x.prm[k] : 0;
+        if (k < rows) c.prm[lane * c.ps + k] = x.prm[k];
 #pragma unroll
     for (int r = 0; r < GTX_MAX_RESULTS; ++r)
         if (r < a.res_rows) c.res[lane * c.rs + r] = 0;
-    c.ts[lane] = x.ts;
-    c.app0[lane] = x.app0;
-    c.app1[lane] = x.app1;
     c.idx[lane] = x.i;
     c.t[lane] = t;
-    c.proc[lane] = a.types[t].proc;
+    c.proc[lane] = T.proc;
     c.st[lane] = GPUTX_COMMIT;
-    for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
-    CellClaim claim{tab, c.cs + lane * c.css};
-    txn_cells(a.types[t], x.prm, claim);
-    AppendOnlyAcc ap;
-    int64_t unused[GTX_MAX_RESULTS];
-    (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+    return claim.won;
+}
+
+// The live lanes (c0 + lane < end) claim their transactions, read earlier
+// into x.  Needs the whole wave.
+__device__ __forceinline__ void part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                                const StagedTxn& x, int64_t c0, int64_t end, int lane) {
+    const bool live = c0 + lane < end;
+    const int32_t t0 = __builtin_amdgcn_readfirstlane(x.t);  // lane 0 is live if any lane is
+    uint32_t won = 0;
+    if (__ballot(live && x.t != t0) == 0) {
+        if (live) won = part_claim<true>(a, c, tab, x, lane, t0);
+    } else if (live) {
+        won = part_claim<false>(a, c, tab, x, lane, 0);
+    }
+    // list the won slots: one counter update for the whole wave
+    const int nw = __popc(won);
+    const int incl = wave_incl_sum_dpp(nw);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    if (total == 0) return;
+    int e0 = 0;
+    if (lane % 64 == 63) e0 = __hip_atomic_fetch_add(tab.nlist, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    int e = __builtin_amdgcn_readlane(e0, 63) + incl - nw;
+    const uint32_t* row = c.cs + lane * c.css;
+    const uint32_t base = lds_addr(tab.slot);
+    for (uint32_t m = won; m; m &= m - 1) tab.list[e++] = (int32_t)((row[__ffs(m) - 1] - base) >> 4);
+}
+
+// Read and claim the chunk starting at c0 in one go (no read-ahead).  Needs
+// the whole wave.
+__device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                           int64_t c0, int64_t end, int lane) {
+    StagedTxn x;
+    x.t = 0;
+    if (c0 + lane < end) stage_load(a, (int32_t)(c0 + lane), x);
+    part_claim_wave(a, c, tab, x, c0, end, lane);
 }
 
 // Staging side of the window form (lanes_window).  When the live lanes of
@@ -1132,9 +1255,29 @@ __device__ __forceinline__ void part_group(const PartChunk& c, const CellTab& ta
 // Fetch a chunk's transactions (part_fetch), then group each window's cells
 // for the window form (part_group).
 __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
-    part_fetch(a, c, tab, pos, c0, end, lane);
+                                           int64_t c0, int64_t end, int lane) {
+    part_fetch(a, c, tab, c0, end, lane);
     part_group(c, tab, c0, end, lane);
+}
+// The same for a chunk whose transactions were read a step ahead.
+__device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                                const StagedTxn& x, int64_t c0, int64_t end, int lane) {
+    part_claim_wave(a, c, tab, x, c0, end, lane);
+    part_group(c, tab, c0, end, lane);
+}
+
+// The serial wave writes the statuses and results of the cnt transactions it
+// just ran (it reads no global memory, so the stores never hold it up).
+__device__ __forceinline__ void part_writeout_all(const BulkArgs& a, const PartChunk& c, int cnt, int lane) {
+    for (int r = lane; r < cnt; r += 64) {
+        const int64_t i = c.idx[r];
+        a.status[i] = c.st[r];
+        int64_t* out = a.results + i * a.width;
+#pragma unroll
+        for (int q = 0; q < GTX_MAX_RESULTS; ++q)
+            if (q < a.width) out[q] = q < a.res_rows ? c.res[r * c.rs + q] : 0;
+        for (int q = GTX_MAX_RESULTS; q < a.width; ++q) out[q] = 0;
+    }
 }
 
 // The owning lanes write the chunk's statuses and results.
@@ -1233,14 +1376,13 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
 
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
-            part_stage(a, c, tab, pos, c0, end, lane);
+            part_stage(a, c, tab, c0, end, lane);
             __syncthreads();
             part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
@@ -1254,10 +1396,10 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Pipelined PART: one workgroup per long partition at a time.  Lane 0 of
-// wave 0 runs chunk k (CW transactions) serially while the CW / 64 staging
-// waves, one lane per transaction, write out chunk k-1 and stage chunk k+1 in
-// the other buffer.  The cell table persists across chunks (a cell chunk k+1
+// Pipelined PART: one workgroup per long partition at a time.  Wave 0 runs
+// chunk k (CW transactions) in timestamp order and writes out its outcomes
+// while the CW / 64 staging waves, one lane per transaction, stage chunk k+1
+// in the other buffer.  The cell table persists across chunks (a cell chunk k+1
 // shares with chunk k is found staged, with chunk k's writes applied by the
 // time chunk k+1 runs); it is flushed and emptied when a further chunk might
 // fill it past half, and at the end of each partition, at points where no
@@ -1287,7 +1429,6 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
     part_init_rows(buf(1), tab, tid, nthr);
     if (tid == 0) *tab.nlist = 0;
 
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
     __syncthreads();
@@ -1295,18 +1436,33 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        if (!serial) part_stage(a, buf(0), tab, pos, lo, end, sl);
+        // A staging lane reads its transaction of chunk k + 2 while it claims
+        // the cells of chunk k + 1.  xn: the next chunk to claim.
+        StagedTxn xn;
+        xn.t = 0;
+        if (!serial) {
+            const int64_t j0 = lo + sl, j1 = j0 + cw;
+            StagedTxn x0;
+            x0.t = 0;
+            if (j0 < end) stage_load(a, (int32_t)j0, x0);
+            if (j1 < end) stage_load(a, (int32_t)j1, xn);
+            part_stage_read(a, buf(0), tab, x0, lo, end, sl);
+        }
         __syncthreads();
         for (int64_t k = 0; k < nch; ++k) {
             const int64_t c0 = lo + cw * k;
+            StagedTxn xa = xn;
             if (serial) {
-                part_run_chunk(a, buf(k), tab, (int)min<int64_t>(cw, end - c0), lane, committed, aborted);
+                const int cnt = (int)min<int64_t>(cw, end - c0);
+                part_run_chunk(a, buf(k), tab, cnt, lane, committed, aborted);
+                part_writeout_all(a, buf(k), cnt, lane);
             } else {
-                if (k > 0) part_writeout(a, buf(k - 1), c0 - cw, end, sl);
                 bool flush = false;
                 if (k + 1 < nch) {
                     flush = *tab.nlist + cw * a.cells_max > cap / 2;
-                    if (!flush) part_stage(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
+                    const int64_t j2 = c0 + 2 * cw + sl;
+                    if (j2 < end) stage_load(a, (int32_t)j2, xa);
+                    if (!flush) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 }
                 if (sl == 0) flag[k & 1] = flush;
             }
@@ -1316,12 +1472,12 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
                 __syncthreads();
                 if (tid == 0) *tab.nlist = 0;
                 __syncthreads();
-                if (!serial) part_stage(a, buf(k + 1), tab, pos, c0 + cw, end, sl);
+                if (!serial) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 __syncthreads();
             }
+            xn = xa;
         }
-        // the last chunk's outcomes and every staged cell; the table is empty after
-        if (!serial) part_writeout(a, buf(nch - 1), lo + cw * (nch - 1), end, sl);
+        // every staged cell; the table is empty after
         part_flush(tab, tid, nthr);
         __syncthreads();
         if (tid == 0) *tab.nlist = 0;
@@ -1443,6 +1599,8 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         const bool wave = !pipe256 && !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
         b.long_part = (pipe256 || pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
+        hipLaunchKernelGGL(k_part_gather, dim3((unsigned)std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096)),
+                           dim3(GTX_BLOCK), 0, s, b);
         if (pipe256)
             hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 + 256), part_pipe_lds(a, 256), s, b);
         else if (pipe128)

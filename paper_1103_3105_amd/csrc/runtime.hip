@@ -395,6 +395,12 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.qv[0] = L.take<uint32_t>(n); w.qv[1] = L.take<uint32_t>(n);
     w.heads = L.take<int32_t>(n + 1);
     w.heads_tmp = L.take<int32_t>(std::max<int64_t>(1, (n + 2047) / 2048));
+    int prm_rows = 1;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i)
+        if (h->type_present[i]) prm_rows = std::max(prm_rows, proc_params(h->types[i].proc));
+    w.rec_i = L.take<int32_t>(n);
+    w.rec_t = L.take<int32_t>(n);
+    w.rec_prm = L.take<int64_t>(n * prm_rows);
     w.front[0] = L.take<int32_t>(n); w.front[1] = L.take<int32_t>(n);
     w.sort_hist = L.take<uint32_t>(8 * 256);
     size_t sw = std::max({sort_status_words(n, 8), sort_status_words(mcap, h->key_passes),
