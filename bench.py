@@ -111,10 +111,15 @@ def make_workload(args):
 
 
 def phase_bytes(workload: str, n: int, m: int, key_passes: int, committed: int):
-    """Algorithmic HBM bytes per phase of one bulk (what the method must move)."""
-    exec_per_txn = {"bank": 32 + 8 + 4 + 24 + 40 + 3 * 16,
-                    "order": 8 * 8 + 8 + 4 + 8 * 4 + 40 + 10 * 8,
-                    "sub": 16 + 8 + 4 + 14 * 4 + 64}[workload]
+    """Algorithmic HBM bytes per phase of one bulk (what the method must move).
+
+    Executing a transaction reads its parameters and timestamp, writes its
+    appended rows, reads and writes its cells, and writes its status and
+    results.  Under PART the gather pass moves the first three (signature in,
+    appended rows out) and the partition kernel the rest."""
+    sig_app = {"bank": 32 + 8 + 40, "order": 8 * 8 + 8 + 40, "sub": 16 + 8}[workload]
+    cells_out = {"bank": 4 + 24 + 3 * 16, "order": 4 + 8 * 4 + 10 * 8, "sub": 4 + 14 * 4 + 64}[workload]
+    exec_per_txn = sig_app + cells_out
     return {
         "order": 8 * n,
         "prepare": n * (32 + 4 + 4 + 8 + 8) + 2 * 2 * 8 * n,
@@ -122,7 +127,8 @@ def phase_bytes(workload: str, n: int, m: int, key_passes: int, committed: int):
         "op_sort": m * (4 + 16 * key_passes),
         "rank": m * 40,
         "features": n * 8,
-        "part": committed * exec_per_txn,
+        "part_gather": committed * sig_app,
+        "part": committed * cells_out,
         "tpl": committed * exec_per_txn,
         "kset": committed * exec_per_txn,
     }
@@ -411,7 +417,9 @@ def main():
     dom = max((k for k in phases if k in pb), key=lambda k: phases[k])
     dom_ms = phases[dom] / max(nb, 1)
     achieved = pb[dom] / (dom_ms / 1e3) / 1e9 if dom_ms > 0 else 0.0
-    kernel_of = {"part": "k_part_pipe<128>" if args.part_pipeline else "k_part_wave",
+    pipe_cw = 256 if args.workload == "bank" else 128  # the widest chunk whose LDS fits
+    kernel_of = {"part": f"k_part_pipe<{pipe_cw}>" if args.part_pipeline else "k_part_wave",
+                 "part_gather": "k_part_gather",
                  "tpl": "k_tpl", "kset": "k_kset", "rank": "k_rank_down",
                  "op_sort": "k_sort_pass", "prepare": "k_prepare", "emit": "k_emit"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",

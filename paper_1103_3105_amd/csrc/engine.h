@@ -106,7 +106,7 @@ constexpr int kRankTile = GTX_BLOCK * kRankItems;
 
 // Phase boundaries of one bulk; mark() records a timing event when enabled.
 enum Phase { PH_START, PH_ORDER, PH_PREPARE, PH_EMIT, PH_OPSORT, PH_RANK, PH_FEATURES,
-             PH_PARTSORT, PH_PART, PH_TPL, PH_KSET, PH_FINAL, PH_COUNT };
+             PH_PARTSORT, PH_PARTGATHER, PH_PART, PH_TPL, PH_KSET, PH_FINAL, PH_COUNT };
 struct PhaseMarks {
     hipEvent_t* ev = nullptr;  // PH_COUNT events of this bulk, or null
     void mark(int p, hipStream_t s) const {

@@ -1601,6 +1601,7 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
         hipLaunchKernelGGL(k_part_gather, dim3((unsigned)std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096)),
                            dim3(GTX_BLOCK), 0, s, b);
+        pm.mark(PH_PARTGATHER, s);
         if (pipe256)
             hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 + 256), part_pipe_lds(a, 256), s, b);
         else if (pipe128)
@@ -1612,6 +1613,8 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         const unsigned lanes = (unsigned)std::max<int64_t>(
             1, std::min<int64_t>((std::min<int64_t>(a.n, a.n_parts) + GTX_BLOCK - 1) / GTX_BLOCK, 4096));
         hipLaunchKernelGGL(k_part, dim3(lanes), dim3(GTX_BLOCK), 0, s, b);
+    } else {
+        pm.mark(PH_PARTGATHER, s);
     }
     pm.mark(PH_PART, s);
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_TPL || a.strategy == GPUTX_PART)

@@ -121,8 +121,8 @@ extern "C" int gputx_phase_timing(gputx_handle h, int enable) {
 }
 
 static const char* kPhaseNames[PH_COUNT - 1] = {"order", "prepare", "emit", "op_sort", "rank",
-                                                "features", "part_sort", "part", "tpl", "kset",
-                                                "finalize"};
+                                                "features", "part_sort", "part_gather", "part", "tpl",
+                                                "kset", "finalize"};
 
 extern "C" const char* gputx_phase_name(int i) {
     return (i >= 0 && i < PH_COUNT - 1) ? kPhaseNames[i] : nullptr;
