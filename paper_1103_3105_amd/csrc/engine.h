@@ -47,10 +47,9 @@ struct Ws {
     uint32_t* qv[2];     // [n] PART sort: serial position
     int32_t* heads;      // [n + 1] PART: first sorted position of each non-empty partition
     int32_t* heads_tmp;  // [head blocks] PART: per-block head counts, then offsets
-    // PART: each transaction PART runs, in partition order (k_part_gather)
-    int32_t* rec_i;      // [n] input index
-    int32_t* rec_t;      // [n] type
-    int64_t* rec_prm;    // [prm rows][n] parameters (zero past the type's own)
+    // PART: one record per serial position (k_part_gather): input index and
+    // type in the first word, then the parameters (zero past the type's own)
+    int64_t* rec;        // [n][rec_words]
     int32_t* front[2];   // [n] K-SET frontiers
     uint32_t* sort_hist; // [8][256]
     uint32_t* sort_status;
@@ -59,6 +58,10 @@ struct Ws {
     int32_t* tcnt_tmp;   // [kPrepBlocks][GPUTX_MAX_TYPES] per-block type counts
     RankAgg* rank_tmp;   // [2][rank tiles]
 };
+
+// Words of a PART record: the index/type word, then prm_rows parameters
+// (16-byte aligned records).
+inline int part_rec_words(int prm_rows) { return (1 + prm_rows + 1) & ~1; }
 
 struct BulkArgs {
     const int32_t* type;
@@ -88,6 +91,7 @@ struct BulkArgs {
     int32_t cell_bits;      // PART cell table: 1 << cell_bits slots
     int32_t cells_max;      // most cells one registered type's transaction lists
     int32_t prm_rows;       // PART LDS parameter rows: widest registered procedure
+    int32_t rec_words;      // PART record size in int64 words: 1 + prm_rows, rounded up to even
     int32_t pipe_bits;      // pipelined PART cell table: 1 << pipe_bits slots
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
     int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane

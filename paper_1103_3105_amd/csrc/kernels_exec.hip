@@ -576,27 +576,26 @@ __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int6
 
 // One lane per short partition (fewer than a.long_part transactions): its
 // transactions run one after another, in place.
-// Before PART runs: every transaction it runs, in partition order, read
-// from the bulk into records the PART kernels read contiguously, and its
-// appended rows written (they depend on the signature alone).  The whole
-// device takes part; each partition's reads are otherwise scattered over
-// the bulk.
+// Before PART runs: each transaction's record (input index, type and
+// parameters, one record per serial position) and its appended rows (they
+// depend on the signature alone).  Serial order keeps every read and every
+// appended row contiguous; the partition kernels then read one record per
+// transaction.  Under PART no transaction crosses partitions (Algorithm 1
+// falls back to TPL otherwise), so every valid transaction is PART's.
 __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     const GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART) return;
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
-    const int64_t total = a.ws.heads[st->n_heads];
-    for (int64_t j = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; j < total;
-         j += (int64_t)gridDim.x * GTX_BLOCK) {
-        const int32_t p = (int32_t)pos[j];
+    for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
+         p += (int64_t)gridDim.x * GTX_BLOCK) {
         const int32_t t = a.ws.tty[p];
+        if (t < 0) continue;
         TxnIn x;
         load_txn(a, p, t, x);
-        a.ws.rec_i[j] = (int32_t)x.i;
-        a.ws.rec_t[j] = t;
+        int64_t* r = a.ws.rec + p * a.rec_words;
+        r[0] = (int64_t)(((uint64_t)(uint32_t)t << 32) | (uint32_t)x.i);
 #pragma unroll
         for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-            if (k < a.prm_rows) a.ws.rec_prm[(int64_t)k * a.n + j] = x.prm[k];
+            if (k < a.prm_rows) r[1 + k] = x.prm[k];
         AppendOnlyAcc ap;
         int64_t unused[GTX_MAX_RESULTS];
         (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
@@ -1113,23 +1112,24 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
 }
 
 // A staging lane's transaction as read a step before its cells are claimed,
-// from the partition-order records (k_part_gather): its partition-order
-// position j, type, input index and first kStagePrm parameters (wider
-// signatures read the rest when claimed).  Consecutive lanes read
-// consecutive records.  Timestamps and append rows serve only the appends,
-// which k_part_gather wrote.
+// from its record (k_part_gather): serial position p, type, input index and
+// first kStagePrm parameters (wider signatures read the rest when claimed).
+// Timestamps and append rows serve only the appends, which k_part_gather
+// wrote.
 constexpr int kStagePrm = 8;
 struct StagedTxn {
     int64_t i;
-    int32_t j, t;
+    int32_t p, t;
     int64_t prm[kStagePrm];
 };
-__device__ __forceinline__ void stage_load(const BulkArgs& a, int32_t j, StagedTxn& x) {
-    x.j = j;
-    x.t = a.ws.rec_t[j];
-    x.i = a.ws.rec_i[j];
+__device__ __forceinline__ void stage_load(const BulkArgs& a, int32_t p, StagedTxn& x) {
+    const int64_t* r = a.ws.rec + (int64_t)p * a.rec_words;
+    const uint64_t w0 = (uint64_t)r[0];
+    x.p = p;
+    x.t = (int32_t)(w0 >> 32);
+    x.i = (int64_t)(uint32_t)w0;
 #pragma unroll
-    for (int k = 0; k < kStagePrm; ++k) x.prm[k] = k < a.prm_rows ? a.ws.rec_prm[(int64_t)k * a.n + j] : 0;
+    for (int k = 0; k < kStagePrm; ++k) x.prm[k] = k < a.prm_rows ? r[1 + k] : 0;
 }
 
 // One lane per transaction of a chunk (the lane's row): write its signature
@@ -1150,7 +1150,7 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
     x.np = min(a.n_params, T.n_params);
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-        x.prm[k] = k >= x.np ? 0 : k < kStagePrm ? s.prm[k] : a.ws.rec_prm[(int64_t)k * a.n + s.j];
+        x.prm[k] = k >= x.np ? 0 : k < kStagePrm ? s.prm[k] : a.ws.rec[(int64_t)s.p * a.rec_words + 1 + k];
     for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
     CellClaim claim{tab, c.cs + lane * c.css, 0u};
     txn_cells(T, x.prm, claim);
@@ -1199,10 +1199,10 @@ __device__ __forceinline__ void part_claim_wave(const BulkArgs& a, const PartChu
 // Read and claim the chunk starting at c0 in one go (no read-ahead).  Needs
 // the whole wave.
 __device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           int64_t c0, int64_t end, int lane) {
+                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
     StagedTxn x;
     x.t = 0;
-    if (c0 + lane < end) stage_load(a, (int32_t)(c0 + lane), x);
+    if (c0 + lane < end) stage_load(a, (int32_t)pos[c0 + lane], x);
     part_claim_wave(a, c, tab, x, c0, end, lane);
 }
 
@@ -1255,8 +1255,8 @@ __device__ __forceinline__ void part_group(const PartChunk& c, const CellTab& ta
 // Fetch a chunk's transactions (part_fetch), then group each window's cells
 // for the window form (part_group).
 __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           int64_t c0, int64_t end, int lane) {
-    part_fetch(a, c, tab, c0, end, lane);
+                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
+    part_fetch(a, c, tab, pos, c0, end, lane);
     part_group(c, tab, c0, end, lane);
 }
 // The same for a chunk whose transactions were read a step ahead.
@@ -1376,13 +1376,14 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
 
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
-            part_stage(a, c, tab, c0, end, lane);
+            part_stage(a, c, tab, pos, c0, end, lane);
             __syncthreads();
             part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
@@ -1429,6 +1430,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
     part_init_rows(buf(1), tab, tid, nthr);
     if (tid == 0) *tab.nlist = 0;
 
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     int64_t committed = 0, aborted = 0;
     __syncthreads();
@@ -1436,22 +1438,30 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        // A staging lane reads its transaction of chunk k + 2 while it claims
-        // the cells of chunk k + 1.  xn: the next chunk to claim.
+        // A staging lane reads its transaction's record for chunk k + 2 and
+        // the serial position of its transaction of chunk k + 3 while it
+        // claims the cells of chunk k + 1, so a step's global reads do not
+        // wait on one another.  xn: the next chunk to claim; pn: the position
+        // after it.
         StagedTxn xn;
         xn.t = 0;
+        int32_t pn = 0;
         if (!serial) {
-            const int64_t j0 = lo + sl, j1 = j0 + cw;
+            const int64_t j0 = lo + sl, j1 = j0 + cw, j2 = j1 + cw;
+            const int32_t p0 = j0 < end ? (int32_t)pos[j0] : 0;
+            const int32_t p1 = j1 < end ? (int32_t)pos[j1] : 0;
+            pn = j2 < end ? (int32_t)pos[j2] : 0;
             StagedTxn x0;
             x0.t = 0;
-            if (j0 < end) stage_load(a, (int32_t)j0, x0);
-            if (j1 < end) stage_load(a, (int32_t)j1, xn);
+            if (j0 < end) stage_load(a, p0, x0);
+            if (j1 < end) stage_load(a, p1, xn);
             part_stage_read(a, buf(0), tab, x0, lo, end, sl);
         }
         __syncthreads();
         for (int64_t k = 0; k < nch; ++k) {
             const int64_t c0 = lo + cw * k;
             StagedTxn xa = xn;
+            int32_t pa = 0;
             if (serial) {
                 const int cnt = (int)min<int64_t>(cw, end - c0);
                 part_run_chunk(a, buf(k), tab, cnt, lane, committed, aborted);
@@ -1460,8 +1470,9 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
                 bool flush = false;
                 if (k + 1 < nch) {
                     flush = *tab.nlist + cw * a.cells_max > cap / 2;
-                    const int64_t j2 = c0 + 2 * cw + sl;
-                    if (j2 < end) stage_load(a, (int32_t)j2, xa);
+                    const int64_t j2 = c0 + 2 * cw + sl, j3 = j2 + cw;
+                    if (j3 < end) pa = (int32_t)pos[j3];
+                    if (j2 < end) stage_load(a, pn, xa);
                     if (!flush) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 }
                 if (sl == 0) flag[k & 1] = flush;
@@ -1476,6 +1487,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
                 __syncthreads();
             }
             xn = xa;
+            pn = pa;
         }
         // every staged cell; the table is empty after
         part_flush(tab, tid, nthr);
@@ -1494,7 +1506,10 @@ __global__ void k_finalize(BulkArgs a) {
     gputx_bulk_stats* o = a.stats;
     const int err = st->error;
     if (!err) {
-        for (int k = 0; k < a.n_app; ++k) a.rowcount[k] += st->app_total[k];
+        // only the tables this bulk appends to: bulks on other streams of a
+        // batch may be updating the others' counts meanwhile
+        for (int k = 0; k < a.n_app; ++k)
+            if (st->app_total[k] != 0) a.rowcount[k] += st->app_total[k];
     }
     int64_t app = 0;
     for (int k = 0; k < a.n_app; ++k) app += st->app_total[k];

@@ -398,9 +398,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     int prm_rows = 1;
     for (int i = 0; i < GPUTX_MAX_TYPES; ++i)
         if (h->type_present[i]) prm_rows = std::max(prm_rows, proc_params(h->types[i].proc));
-    w.rec_i = L.take<int32_t>(n);
-    w.rec_t = L.take<int32_t>(n);
-    w.rec_prm = L.take<int64_t>(n * prm_rows);
+    w.rec = L.take<int64_t>(n * part_rec_words(prm_rows));
     w.front[0] = L.take<int32_t>(n); w.front[1] = L.take<int32_t>(n);
     w.sort_hist = L.take<uint32_t>(8 * 256);
     size_t sw = std::max({sort_status_words(n, 8), sort_status_words(mcap, h->key_passes),
@@ -488,6 +486,7 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
         a.prm_rows = std::max(a.prm_rows, proc_params(h->types[i].proc));
         a.res_rows = std::max(a.res_rows, proc_results(h->types[i].proc));
     }
+    a.rec_words = part_rec_words(a.prm_rows);
     a.cell_bits = 1;
     while ((1 << a.cell_bits) < 2 * 64 * a.cells_max) ++a.cell_bits;
     // the pipelined form keeps cells across chunks: room for several chunks
