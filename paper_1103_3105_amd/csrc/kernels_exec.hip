@@ -680,7 +680,7 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 // the procedure may write is marked written (bit 0), so it is stored back
 // when the table is flushed.  The first claimant of a cell (won, one bit per
 // ordinal) lists the slot and loads the cell's value afterwards
-// (part_claim_wave, claim_values): all of a transaction's claims go first,
+// (part_claim_wave, claim_values_issue): all of a transaction's claims go first,
 // so its loads are in flight together.
 struct CellClaim {
     CellTab tab;
@@ -716,22 +716,35 @@ struct CellClaim {
     }
 };
 // The won cells' values, four loads in flight at a time; the slot's key holds
-// the cell's global address and width.
-__device__ __forceinline__ void claim_values(const uint32_t* cs, uint32_t won) {
-    for (int r0 = 0; won >> r0; r0 += 4) {
+// the cell's global address and width.  claim_values_issue loads those of
+// ordinals 0-3 into registers (and handles any further ordinals itself);
+// claim_values_finish stores them, so other work can cover the loads.
+struct ValLoads {
+    int64_t v[4];
+};
+__device__ __forceinline__ int64_t cell_value_of(const uint32_t at_lds) {
+    const uint64_t key = *(GTX_LDS const uint64_t*)(uintptr_t)(at_lds - 8);
+    const uint64_t at = key & ~(uint64_t)3;
+    return (key & 2) ? *(GTX_GLOBAL const int64_t*)at : (int64_t)*(GTX_GLOBAL const int32_t*)at;
+}
+__device__ __forceinline__ void claim_values_issue(const uint32_t* cs, uint32_t won, ValLoads& L) {
+    for (int r0 = 4; won >> r0; r0 += 4) {
         int64_t v[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if ((won >> (r0 + q)) & 1u) {
-                const uint64_t key = *(GTX_LDS const uint64_t*)(uintptr_t)(cs[r0 + q] - 8);
-                const uint64_t at = key & ~(uint64_t)3;
-                v[q] = (key & 2) ? *(GTX_GLOBAL const int64_t*)at : (int64_t)*(GTX_GLOBAL const int32_t*)at;
-            }
-        }
+        for (int q = 0; q < 4; ++q)
+            if ((won >> (r0 + q)) & 1u) v[q] = cell_value_of(cs[r0 + q]);
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if ((won >> (r0 + q)) & 1u) *(GTX_LDS int64_t*)(uintptr_t)cs[r0 + q] = v[q];
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((won >> q) & 1u) L.v[q] = cell_value_of(cs[q]);
+}
+__device__ __forceinline__ void claim_values_finish(const uint32_t* cs, uint32_t won, const ValLoads& L) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if ((won >> q) & 1u) *(GTX_LDS int64_t*)(uintptr_t)cs[q] = L.v[q];
 }
 
 // Serial side: the procedures' accessor over the staged cells.  The fetch
@@ -1080,15 +1093,18 @@ size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
            (size_t)4 * (64 * a.cells_max + 4) + part_tstride(a.cell_bits);
 }
+// The pipelined form's table holds at most half of its slots: it
+// is flushed before a chunk could take it past that.
+__host__ __device__ inline int part_pipe_fill(int cap) { return cap / 2; }
 size_t part_pipe_lds(const BulkArgs& a, int cw) {
     return 2 * part_chunk_bytes(a, cw) + ((size_t)sizeof(CellSlot) << a.pipe_bits) + sizeof(CellSlot) +
-           (size_t)4 * ((size_t(1) << a.pipe_bits) / 2 + 4) + (size_t)(cw / 64) * part_tstride(a.pipe_bits);
+           (size_t)4 * (part_pipe_fill(1 << a.pipe_bits) + 4) + (size_t)(cw / 64) * part_tstride(a.pipe_bits);
 }
 // Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
 // limit (160 KB on gfx950), or the default 64 KB if raising it fails.
 static size_t g_part_lds_limit = 64 * 1024;
 // The pipelined form of width cw runs when its LDS fits and one chunk's cells
-// fit in half the table (the table is flushed at half-full).
+// fit in half the table (so that several chunks fit below the fill limit).
 static bool part_pipe_fits(const BulkArgs& a, int cw) {
     return a.part_pipeline && part_pipe_lds(a, cw) <= g_part_lds_limit &&
            (int64_t(1) << a.pipe_bits) >= int64_t(2) * cw * a.cells_max;
@@ -1156,7 +1172,6 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
     txn_cells(T, x.prm, claim);
     x.app0 = 0;
     x.app1 = 0;
-    claim_values(claim.cs, claim.won);
     const int rows = a.prm_rows;
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
@@ -1173,8 +1188,8 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
 
 // The live lanes (c0 + lane < end) claim their transactions, read earlier
 // into x.  Needs the whole wave.
-__device__ __forceinline__ void part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                                const StagedTxn& x, int64_t c0, int64_t end, int lane) {
+__device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                                    const StagedTxn& x, int64_t c0, int64_t end, int lane) {
     const bool live = c0 + lane < end;
     const int32_t t0 = __builtin_amdgcn_readfirstlane(x.t);  // lane 0 is live if any lane is
     uint32_t won = 0;
@@ -1187,23 +1202,14 @@ __device__ __forceinline__ void part_claim_wave(const BulkArgs& a, const PartChu
     const int nw = __popc(won);
     const int incl = wave_incl_sum_dpp(nw);
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    if (total == 0) return;
+    if (total == 0) return 0;
     int e0 = 0;
     if (lane % 64 == 63) e0 = __hip_atomic_fetch_add(tab.nlist, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     int e = __builtin_amdgcn_readlane(e0, 63) + incl - nw;
     const uint32_t* row = c.cs + lane * c.css;
     const uint32_t base = lds_addr(tab.slot);
     for (uint32_t m = won; m; m &= m - 1) tab.list[e++] = (int32_t)((row[__ffs(m) - 1] - base) >> 4);
-}
-
-// Read and claim the chunk starting at c0 in one go (no read-ahead).  Needs
-// the whole wave.
-__device__ __forceinline__ void part_fetch(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
-    StagedTxn x;
-    x.t = 0;
-    if (c0 + lane < end) stage_load(a, (int32_t)pos[c0 + lane], x);
-    part_claim_wave(a, c, tab, x, c0, end, lane);
+    return won;
 }
 
 // Staging side of the window form (lanes_window).  When the live lanes of
@@ -1252,18 +1258,25 @@ __device__ __forceinline__ void part_group(const PartChunk& c, const CellTab& ta
     }
 }
 
-// Fetch a chunk's transactions (part_fetch), then group each window's cells
-// for the window form (part_group).
-__device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
-    part_fetch(a, c, tab, pos, c0, end, lane);
-    part_group(c, tab, c0, end, lane);
-}
-// The same for a chunk whose transactions were read a step ahead.
+// Stage a chunk whose transactions were read already (x): claim the cells,
+// start loading the won ones, group each window's cells for the window form
+// (part_group) meanwhile, then store the loaded values.  Needs the whole wave.
 __device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                 const StagedTxn& x, int64_t c0, int64_t end, int lane) {
-    part_claim_wave(a, c, tab, x, c0, end, lane);
+    const uint32_t won = part_claim_wave(a, c, tab, x, c0, end, lane);
+    const uint32_t* row = c.cs + lane * c.css;
+    ValLoads vl;
+    claim_values_issue(row, won, vl);
     part_group(c, tab, c0, end, lane);
+    claim_values_finish(row, won, vl);
+}
+// Read and stage the chunk starting at c0 in one go (no read-ahead).
+__device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
+    StagedTxn x;
+    x.t = 0;
+    if (c0 + lane < end) stage_load(a, (int32_t)pos[c0 + lane], x);
+    part_stage_read(a, c, tab, x, c0, end, lane);
 }
 
 // The serial wave writes the statuses and results of the cnt transactions it
@@ -1403,8 +1416,8 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
 // in the other buffer.  The cell table persists across chunks (a cell chunk k+1
 // shares with chunk k is found staged, with chunk k's writes applied by the
 // time chunk k+1 runs); it is flushed and emptied when a further chunk might
-// fill it past half, and at the end of each partition, at points where no
-// wave probes it, so linear probing never sees a deleted slot.
+// fill it past part_pipe_fill, and at the end of each partition, at points
+// where no wave probes it, so linear probing never sees a deleted slot.
 template <int CW>
 __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
     constexpr int cw = CW;
@@ -1418,7 +1431,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
     const size_t cb = part_chunk_bytes(a, cw);
     auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a, cw); };
     const int cap = 1 << a.pipe_bits;
-    const CellTab tab = part_table_at(part_lds + 2 * cb, a.pipe_bits, cap / 2);
+    const CellTab tab = part_table_at(part_lds + 2 * cb, a.pipe_bits, part_pipe_fill(cap));
     GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk
     // one decision for the whole workgroup (another workgroup may fail the
     // bulk meanwhile; all waves must still meet at every barrier)
@@ -1469,7 +1482,7 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
             } else {
                 bool flush = false;
                 if (k + 1 < nch) {
-                    flush = *tab.nlist + cw * a.cells_max > cap / 2;
+                    flush = *tab.nlist + cw * a.cells_max > part_pipe_fill(cap);
                     const int64_t j2 = c0 + 2 * cw + sl, j3 = j2 + cw;
                     if (j3 < end) pa = (int32_t)pos[j3];
                     if (j2 < end) stage_load(a, pn, xa);
