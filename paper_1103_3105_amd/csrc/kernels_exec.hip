@@ -947,43 +947,59 @@ __device__ __forceinline__ void lanes_window(const PartChunk& c, int k0, int n) 
     constexpr bool kW = proc_cell_writes(P);
     const int s = lane_id();
     const bool live = s < n;
+    // Every ordinal's reads first and its writes last, so that no read waits
+    // behind a write it might alias (ordinals name different columns).
+    int k[NC];
+    bool head[NC], last[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        int k = k0 + s;  // < cw: every row read exists
-        bool head = true, last = true;
+        k[r] = k0 + s;  // < cw: every row read exists
+        head[r] = last[r] = true;
         if constexpr (kW) {
             const uint32_t g = c.grp[r * c.cw + k0 + s];
-            k = k0 + (int)(g & 63u);
-            head = g & 64u;
-            last = g & 128u;
+            k[r] = k0 + (int)(g & 63u);
+            head[r] = g & 64u;
+            last[r] = g & 128u;
         }
-        const uint32_t id = c.cs[k * c.css + r];
-        int64_t p[NP];
+    }
+    uint32_t id[NC];
+    int64_t p[NC][NP];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) p[q] = c.prm[k * c.ps + q];
-        const int64_t init = *(GTX_LDS const int64_t*)(uintptr_t)id;
-        int64_t old = init;
-        if constexpr (kW) {
+    for (int r = 0; r < NC; ++r) {
+        id[r] = c.cs[k[r] * c.css + r];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) p[r][q] = c.prm[k[r] * c.ps + q];
+    }
+    int64_t old[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) old[r] = *(GTX_LDS const int64_t*)(uintptr_t)id[r];
+    if constexpr (kW) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            const int64_t init = old[r];
             bool fa;
             int64_t fb;
-            cell_affine<P>(r, p, fa, fb);
+            cell_affine<P>(r, p[r], fa, fb);
             int a = fa;
             int64_t b = fb;
-            if (head) {
+            if (head[r]) {
                 b = a ? wrap_add(init, b) : b;
                 a = 0;
             }
             wave_affine_scan(a, b);
             const int64_t before = wave_shr1(b);
-            old = head ? init : before;
+            old[r] = head[r] ? init : before;
         }
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
         int64_t nv, res;
         bool w;
         int at;
-        cell_apply<P>(r, old, p, nv, w, at, res);
+        cell_apply<P>(r, old[r], p[r], nv, w, at, res);
         if (live) {
-            if (at >= 0) c.res[k * c.rs + at] = res;
-            if (w && last) *(GTX_LDS int64_t*)(uintptr_t)id = nv;
+            if (at >= 0) c.res[k[r] * c.rs + at] = res;
+            if (w && last[r]) *(GTX_LDS int64_t*)(uintptr_t)id[r] = nv;
         }
     }
 }
