@@ -657,7 +657,7 @@ struct CellTab {
     GTX_LDS CellSlot* slot;  // [1 << bits], then one sink slot outside the table
     GTX_LDS int32_t* list;   // claimed slots
     GTX_LDS int32_t* nlist;  // [4]: the count, then two flags of the pipelined form
-    GTX_LDS uint8_t* tag;    // [staging waves][tstride]: part_group's scratch per wave
+    GTX_LDS uint8_t* tag;    // [serial waves][tstride]: group_ordinal's scratch per wave
     int bits, tstride;
 };
 // LDS address of a slot's value (16-byte slots: bit 3 is set), and of the
@@ -924,82 +924,111 @@ __device__ __forceinline__ int64_t wave_shr1(int64_t v) {  // lane i gets lane i
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// The serial waves of a workgroup: this one's index and their number, and
+// its scratch for grouping (group_ordinal).
+struct SerialWave {
+    int ws, nsw;
+    GTX_LDS uint8_t* tag;  // [512 + tag bytes]: 64 group masks, then a tag byte per slot
+};
+
+// Sort a window's lanes (transactions k0 .. k0+n-1, lane j holding k0 + j)
+// into groups naming the same cell at ordinal r, stably: every lane stores
+// its lane number in the tag byte of its cell's slot, and the value it reads
+// back (one of the group's lanes, the same for the whole group) names the
+// group; each lane ORs its bit into that lane's group mask, then reads the
+// mask, and the groups are laid out in the order of those lanes.  For sorted
+// slot s, grp[r][k0 + s] holds the transaction's lane (bits 0-5), and whether
+// s starts (bit 6) or ends (bit 7) its group.  Lanes past n are groups of
+// their own.  Needs all 64 lanes of the wave.
+__device__ __forceinline__ void group_ordinal(const PartChunk& c, const CellTab& tab, GTX_LDS uint8_t* mine,
+                                              int r, int k0, int n) {
+    const int j = lane_id();
+    const bool live = j < n;
+    GTX_LDS uint64_t* gmask = (GTX_LDS uint64_t*)mine;
+    // volatile: the read must see whichever lane's store landed, not this lane's
+    volatile GTX_LDS uint8_t* tag = mine + 512;
+    const uint32_t h = (c.cs[(k0 + j) * c.css + r] - lds_addr(tab.slot)) >> 4;  // the sink is slot 1 << bits
+    gmask[j] = 0;
+    int rep = j;
+    if (live) {
+        tag[h] = (uint8_t)j;
+        rep = tag[h];
+    }
+    __hip_atomic_fetch_or(&gmask[rep], 1ull << j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const uint64_t eq = __hip_atomic_load(&gmask[rep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    const int rank = __popcll(eq & lanemask_lt());
+    const int size = __popcll(eq);
+    const int own = rep == j ? size : 0;
+    const int pos = __shfl(wave_incl_sum_dpp(own) - own, rep) + rank;
+    c.grp[r * c.cw + k0 + pos] = (uint8_t)(j | (rank == 0 ? 64 : 0) | (rank == size - 1 ? 128 : 0));
+}
+
 // Cellwise procedures (proc_cellwise) run a window of up to 64 transactions
-// at a time, one cell ordinal after the other (cells of different ordinals
-// are different columns, so ordinals do not interact).  A transaction's
+// at a time, one cell ordinal after the other; cells of different ordinals
+// are different columns, so ordinals do not interact and the serial waves
+// share them out (ordinal r goes to serial wave r mod nsw).  A transaction's
 // effect on its cell is the map v -> a ? v + b : b (cell_affine), and such
 // maps compose into maps of the same form, so the value a transaction sees
 // -- the maps of the earlier transactions on the same cell applied in order
-// to the staged value -- is a prefix composition.  The staging wave that
-// fetched the window sorted each ordinal's transactions into groups naming
-// the same cell, each group contiguous and in timestamp order (part_group);
-// lane s takes the transaction at sorted slot s.  The group's first map is
-// replaced by the constant it yields from the staged value, so one scan over
-// the wave gives every lane the value after its transaction without anything
-// crossing a group boundary, and the lane before it holds the value before.
-// The last lane of each group writes the cell.  The result equals running
-// the window's transactions one after another.  Read-only procedures see the
-// staged values and need no grouping.
+// to the staged value -- is a prefix composition.  group_ordinal sorts the
+// window's transactions into groups naming the same cell, each contiguous
+// and in timestamp order; lane s takes the transaction at sorted slot s.  The
+// group's first map is replaced by the constant it yields from the staged
+// value, so one scan over the wave gives every lane the value after its
+// transaction without anything crossing a group boundary, and the lane
+// before it holds the value before.  The last lane of each group writes the
+// cell.  The result equals running the window's transactions one after
+// another.  Read-only procedures see the staged values and need no grouping.
+// Each lane stores its transaction's result of ordinal r straight to the
+// results array (ordinal r yields result column r, or column 0 for
+// single-cell procedures).
 template <int P>
-__device__ __forceinline__ void lanes_window(const PartChunk& c, int k0, int n) {
+__device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                             const SerialWave& sw, int k0, int n) {
     constexpr int NP = proc_params(P);
     constexpr int NC = proc_cells(P);
     constexpr bool kW = proc_cell_writes(P);
     const int s = lane_id();
     const bool live = s < n;
-    // Every ordinal's reads first and its writes last, so that no read waits
-    // behind a write it might alias (ordinals name different columns).
-    int k[NC];
-    bool head[NC], last[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
-        k[r] = k0 + s;  // < cw: every row read exists
-        head[r] = last[r] = true;
+        if (r % sw.nsw != sw.ws) continue;
+        int k = k0 + s;  // < cw: every row read exists
+        bool head = true, last = true;
         if constexpr (kW) {
+            group_ordinal(c, tab, sw.tag, r, k0, n);
             const uint32_t g = c.grp[r * c.cw + k0 + s];
-            k[r] = k0 + (int)(g & 63u);
-            head[r] = g & 64u;
-            last[r] = g & 128u;
+            k = k0 + (int)(g & 63u);
+            head = g & 64u;
+            last = g & 128u;
         }
-    }
-    uint32_t id[NC];
-    int64_t p[NC][NP];
+        const uint32_t id = c.cs[k * c.css + r];
+        int64_t p[NP];
 #pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        id[r] = c.cs[k[r] * c.css + r];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) p[r][q] = c.prm[k[r] * c.ps + q];
-    }
-    int64_t old[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) old[r] = *(GTX_LDS const int64_t*)(uintptr_t)id[r];
-    if constexpr (kW) {
-#pragma unroll
-        for (int r = 0; r < NC; ++r) {
-            const int64_t init = old[r];
+        for (int q = 0; q < NP; ++q) p[q] = c.prm[k * c.ps + q];
+        const int64_t init = *(GTX_LDS const int64_t*)(uintptr_t)id;
+        int64_t old = init;
+        if constexpr (kW) {
             bool fa;
             int64_t fb;
-            cell_affine<P>(r, p[r], fa, fb);
+            cell_affine<P>(r, p, fa, fb);
             int a = fa;
             int64_t b = fb;
-            if (head[r]) {
+            if (head) {
                 b = a ? wrap_add(init, b) : b;
                 a = 0;
             }
             wave_affine_scan(a, b);
             const int64_t before = wave_shr1(b);
-            old[r] = head[r] ? init : before;
+            old = head ? init : before;
         }
-    }
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
         int64_t nv, res;
         bool w;
         int at;
-        cell_apply<P>(r, old[r], p[r], nv, w, at, res);
+        cell_apply<P>(r, old, p, nv, w, at, res);
         if (live) {
-            if (at >= 0) c.res[k[r] * c.rs + at] = res;
-            if (w && last[r]) *(GTX_LDS int64_t*)(uintptr_t)id[r] = nv;
+            if (at >= 0 && at < a.width) a.results[c.idx[k] * a.width + at] = res;
+            if (w && last) *(GTX_LDS int64_t*)(uintptr_t)id = nv;
         }
     }
 }
@@ -1016,19 +1045,27 @@ __device__ __forceinline__ void lanes_window(const PartChunk& c, int k0, int n) 
 // through the generic path, which checks that each ordinal it names was
 // staged, whenever a chunk mixes types.
 template <int P>
-__device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
-                                            const CellTab& tab, int cnt, int64_t& committed,
-                                            int64_t& aborted) {
+__device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
+                                            const CellTab& tab, const SerialWave& sw, int cnt,
+                                            int64_t& committed, int64_t& aborted) {
     constexpr int NP = proc_params(P);  // parameters the procedure can read
     constexpr int NR = proc_results(P); // results it can write (P == 0: up to res_rows)
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
     if constexpr (P != 0 && proc_cellwise(P) && proc_typed_cells(P) && NP <= 8) {
-        for (int k0 = 0; k0 < cnt; k0 += 64) lanes_window<P>(c, k0, min(64, cnt - k0));
-        if (lane_id() == 0) committed += cnt;  // every cellwise procedure commits
-        return;
+        for (int k0 = 0; k0 < cnt; k0 += 64) lanes_window<P>(a, c, tab, sw, k0, min(64, cnt - k0));
+        if (sw.ws == 0) {  // every cellwise procedure commits; the other result columns are zero
+            if (lane_id() == 0) committed += cnt;
+            constexpr int NR = proc_results(P);
+            for (int r = lane_id(); r < cnt; r += 64) {
+                const int64_t i = c.idx[r];
+                a.status[i] = GPUTX_COMMIT;
+                for (int q = NR; q < a.width; ++q) a.results[i * a.width + q] = 0;
+            }
+        }
+        return true;
     }
-    if (lane_id() != 0) return;
+    if (sw.ws != 0 || lane_id() != 0) return false;
     uint32_t seen = ~0u;
     if constexpr (ahead) {
         SerialRegs<NP, NC> A, B;  // transactions 0 and 1 (row 1 exists even if cnt == 1)
@@ -1095,6 +1132,7 @@ __device__ __forceinline__ void part_serial(const BulkArgs& a, const DevType& T,
         aborted += n_abort;
     }
     if (!(seen & 8u)) fail(a.ws.st, GPUTX_E_INTERNAL);
+    return false;
 }
 
 
@@ -1109,12 +1147,15 @@ size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
            (size_t)4 * (64 * a.cells_max + 4) + part_tstride(a.cell_bits);
 }
+// Serial waves of the pipelined form: cellwise procedures share their cell
+// ordinals among them (debit-credit and payment have three).
+constexpr int kPipeSerial = 3;
 // The pipelined form's table holds at most half of its slots: it
 // is flushed before a chunk could take it past that.
 __host__ __device__ inline int part_pipe_fill(int cap) { return cap / 2; }
 size_t part_pipe_lds(const BulkArgs& a, int cw) {
     return 2 * part_chunk_bytes(a, cw) + ((size_t)sizeof(CellSlot) << a.pipe_bits) + sizeof(CellSlot) +
-           (size_t)4 * (part_pipe_fill(1 << a.pipe_bits) + 4) + (size_t)(cw / 64) * part_tstride(a.pipe_bits);
+           (size_t)4 * (part_pipe_fill(1 << a.pipe_bits) + 4) + (size_t)kPipeSerial * part_tstride(a.pipe_bits);
 }
 // Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
 // limit (160 KB on gfx950), or the default 64 KB if raising it fails.
@@ -1228,62 +1269,14 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
     return won;
 }
 
-// Staging side of the window form (lanes_window).  When the live lanes of
-// the calling wave -- one window of the chunk -- all run one cellwise
-// procedure that writes cells, each cell ordinal's lanes are grouped by the
-// cell they name and sorted, stably, by group: every lane stores its lane
-// number in the wave's tag byte of its cell's slot, and the value it reads
-// back (one of the group's lanes, the same for the whole group) names the
-// group; each lane ORs its bit into that lane's group mask, then reads the
-// mask.  For sorted slot s the window's byte grp[r][s] holds the
-// transaction's lane (bits 0-5), and whether s starts (bit 6) or ends (bit 7)
-// its group.  Lanes past the chunk's transactions are groups of their own.
-// Needs all 64 lanes of the wave.
-__device__ __forceinline__ void part_group(const PartChunk& c, const CellTab& tab, int64_t c0, int64_t end,
-                                           int lane) {
-    const int j = lane & 63;
-    const int w0 = lane - j;
-    const bool live = c0 + lane < end;
-    if (__ballot(live) == 0) return;
-    const int proc = __builtin_amdgcn_readfirstlane(c.proc[w0]);  // the window's first lane is live
-    if (__ballot(live && c.proc[lane] != proc) != 0 || !proc_cellwise(proc) || !proc_typed_cells(proc) ||
-        !proc_cell_writes(proc))
-        return;
-    GTX_LDS uint8_t* mine = tab.tag + (lane >> 6) * tab.tstride;
-    GTX_LDS uint64_t* gmask = (GTX_LDS uint64_t*)mine;
-    // volatile: the read must see whichever lane's store landed, not this lane's
-    volatile GTX_LDS uint8_t* tag = mine + 512;
-    const uint64_t below = lanemask_lt();
-    const uint32_t base = lds_addr(tab.slot);
-    const int nc = proc_cells(proc);
-    for (int r = 0; r < nc; ++r) {
-        const uint32_t h = (c.cs[lane * c.css + r] - base) >> 4;  // slot; the sink is slot 1 << bits
-        gmask[j] = 0;
-        int rep = j;
-        if (live) {
-            tag[h] = (uint8_t)j;
-            rep = tag[h];
-        }
-        __hip_atomic_fetch_or(&gmask[rep], 1ull << j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const uint64_t eq = __hip_atomic_load(&gmask[rep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const int rank = __popcll(eq & below);
-        const int size = __popcll(eq);
-        const int own = rep == j ? size : 0;
-        const int pos = __shfl(wave_incl_sum_dpp(own) - own, rep) + rank;
-        c.grp[r * c.cw + w0 + pos] = (uint8_t)(j | (rank == 0 ? 64 : 0) | (rank == size - 1 ? 128 : 0));
-    }
-}
-
 // Stage a chunk whose transactions were read already (x): claim the cells,
-// start loading the won ones, group each window's cells for the window form
-// (part_group) meanwhile, then store the loaded values.  Needs the whole wave.
+// then load the won ones.  Needs the whole wave.
 __device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                 const StagedTxn& x, int64_t c0, int64_t end, int lane) {
     const uint32_t won = part_claim_wave(a, c, tab, x, c0, end, lane);
     const uint32_t* row = c.cs + lane * c.css;
     ValLoads vl;
     claim_values_issue(row, won, vl);
-    part_group(c, tab, c0, end, lane);
     claim_values_finish(row, won, vl);
 }
 // Read and stage the chunk starting at c0 in one go (no read-ahead).
@@ -1295,10 +1288,11 @@ __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c
     part_stage_read(a, c, tab, x, c0, end, lane);
 }
 
-// The serial wave writes the statuses and results of the cnt transactions it
-// just ran (it reads no global memory, so the stores never hold it up).
-__device__ __forceinline__ void part_writeout_all(const BulkArgs& a, const PartChunk& c, int cnt, int lane) {
-    for (int r = lane; r < cnt; r += 64) {
+// The serial waves write the statuses and results of the cnt transactions
+// they just ran, rows t0, t0 + nt, ... (they read no global memory, so the
+// stores never hold them up).
+__device__ __forceinline__ void part_writeout_all(const BulkArgs& a, const PartChunk& c, int cnt, int t0, int nt) {
+    for (int r = t0; r < cnt; r += nt) {
         const int64_t i = c.idx[r];
         a.status[i] = c.st[r];
         int64_t* out = a.results + i * a.width;
@@ -1339,10 +1333,13 @@ __device__ __forceinline__ void part_flush(const CellTab& tab, int tid, int nthr
     }
 }
 
-// Lane 0 of the calling wave runs the chunk, specialised on its procedure
-// when every transaction of the chunk has the same type.
-__device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                               int cnt, int lane, int64_t& committed, int64_t& aborted) {
+// The serial waves run the chunk, specialised on its procedure when every
+// transaction of the chunk has the same type.  Returns true when the
+// outcomes went straight to the status and results arrays (window form);
+// otherwise they are in the chunk's rows.
+__device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                               const SerialWave& sw, int cnt, int lane, int64_t& committed,
+                                               int64_t& aborted) {
     const int t0 = __builtin_amdgcn_readfirstlane(c.t[0]);
     bool differ = false;
     for (int e = lane; e < cnt; e += 64) differ = differ || c.t[e] != t0;
@@ -1351,8 +1348,7 @@ __device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChun
     switch (proc) {
 #define GTX_PART_CASE(P)                                                   \
     case P:                                                                \
-        part_serial<P>(a, a.types[t0], c, tab, cnt, committed, aborted);   \
-        break;
+        return part_serial<P>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
         GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
         GTX_PART_CASE(GPUTX_NEW_ORDER)
         GTX_PART_CASE(GPUTX_PAYMENT)
@@ -1365,7 +1361,7 @@ __device__ __forceinline__ void part_run_chunk(const BulkArgs& a, const PartChun
         GTX_PART_CASE(GPUTX_DEL_CF)
 #undef GTX_PART_CASE
     default:
-        part_serial<0>(a, a.types[t0], c, tab, cnt, committed, aborted);
+        return part_serial<0>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
     }
 }
 
@@ -1407,6 +1403,7 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
 
     const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
+    const SerialWave sw{0, 1, tab.tag};
     int64_t committed = 0, aborted = 0;
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
@@ -1414,9 +1411,9 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
             part_stage(a, c, tab, pos, c0, end, lane);
             __syncthreads();
-            part_run_chunk(a, c, tab, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+            const bool written = part_run_chunk(a, c, tab, sw, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
-            part_writeout(a, c, c0, end, lane);
+            if (!written) part_writeout(a, c, c0, end, lane);
             part_flush(tab, lane, 64);
             __syncthreads();
             if (lane == 0) *tab.nlist = 0;
@@ -1426,24 +1423,27 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     add_counts(st, committed, aborted);
 }
 
-// Pipelined PART: one workgroup per long partition at a time.  Wave 0 runs
-// chunk k (CW transactions) in timestamp order and writes out its outcomes
-// while the CW / 64 staging waves, one lane per transaction, stage chunk k+1
-// in the other buffer.  The cell table persists across chunks (a cell chunk k+1
+// Pipelined PART: one workgroup per long partition at a time.  The
+// kPipeSerial serial waves run chunk k (CW transactions) in timestamp order
+// (the window form shares the cell ordinals among them; otherwise lane 0 of
+// the first runs the chunk) and write out its outcomes, while the CW / 64
+// staging waves, one lane per transaction, stage chunk k+1 in the other
+// buffer.  The cell table persists across chunks (a cell chunk k+1
 // shares with chunk k is found staged, with chunk k's writes applied by the
 // time chunk k+1 runs); it is flushed and emptied when a further chunk might
 // fill it past part_pipe_fill, and at the end of each partition, at points
 // where no wave probes it, so linear probing never sees a deleted slot.
 template <int CW>
-__global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
+__global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a) {
     constexpr int cw = CW;
-    constexpr int nthr = 64 + cw;
+    constexpr int nser = 64 * kPipeSerial;
+    constexpr int nthr = nser + cw;
     GtxState* st = a.ws.st;
     extern __shared__ __attribute__((aligned(16))) unsigned char part_lds[];
     const int tid = threadIdx.x;
-    const bool serial = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+    const bool serial = __builtin_amdgcn_readfirstlane(tid) < nser;
     const int lane = tid & 63;
-    const int sl = tid - 64;  // staging lane: the transaction's column in the chunk
+    const int sl = tid - nser;  // staging lane: the transaction's column in the chunk
     const size_t cb = part_chunk_bytes(a, cw);
     auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a, cw); };
     const int cap = 1 << a.pipe_bits;
@@ -1461,6 +1461,8 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
 
     const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
+    const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const SerialWave sw{ws, kPipeSerial, tab.tag + (serial ? ws : 0) * tab.tstride};
     int64_t committed = 0, aborted = 0;
     __syncthreads();
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
@@ -1493,8 +1495,8 @@ __global__ __launch_bounds__(64 + CW) void k_part_pipe(BulkArgs a) {
             int32_t pa = 0;
             if (serial) {
                 const int cnt = (int)min<int64_t>(cw, end - c0);
-                part_run_chunk(a, buf(k), tab, cnt, lane, committed, aborted);
-                part_writeout_all(a, buf(k), cnt, lane);
+                if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted) && ws == 0)
+                    part_writeout_all(a, buf(k), cnt, lane, 64);
             } else {
                 bool flush = false;
                 if (k + 1 < nch) {
@@ -1647,11 +1649,11 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
                            dim3(GTX_BLOCK), 0, s, b);
         pm.mark(PH_PARTGATHER, s);
         if (pipe256)
-            hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 + 256), part_pipe_lds(a, 256), s, b);
+            hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 * kPipeSerial + 256), part_pipe_lds(a, 256), s, b);
         else if (pipe128)
-            hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 + 128), part_pipe_lds(a, 128), s, b);
+            hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 * kPipeSerial + 128), part_pipe_lds(a, 128), s, b);
         else if (pipe64)
-            hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 + 64), part_pipe_lds(a, 64), s, b);
+            hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 * kPipeSerial + 64), part_pipe_lds(a, 64), s, b);
         else if (wave)
             hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
         const unsigned lanes = (unsigned)std::max<int64_t>(
