@@ -138,7 +138,7 @@ def oracle_baseline(w, bulk, width, budget_s=12.0):
     """The serial oracle on this host, on the same bulk from the same tables."""
     import oracle
     reps, elapsed, committed = 0, 0.0, 0
-    while elapsed < budget_s and reps < 50:
+    while elapsed < budget_s and reps < 500:
         tabs = w.copy_tables()
         t0 = time.perf_counter()
         rc, st, _ = oracle.run_serial(tabs, w.types, bulk.type, bulk.params, bulk.ts, width)
