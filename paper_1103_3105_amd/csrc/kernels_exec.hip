@@ -623,10 +623,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part(BulkArgs a) {
 }
 
 // Signatures of one PART chunk of cw transactions staged in LDS.  Parameters,
-// cell addresses and results are stored one row per transaction (rows of a
-// 16-byte multiple), so the serial lane reads a transaction's cell addresses
-// with one LDS load; the parameter and address arrays have kChunkSpare spare
-// rows so reading up to three transactions ahead needs no bound.
+// cell addresses and results are stored one row per transaction (odd
+// strides, part_ps/css/rs); the parameter and address arrays have
+// kChunkSpare spare rows so reading up to three transactions ahead needs no
+// bound.
 constexpr int kChunkSpare = 4;
 struct PartChunk {
     int64_t* res;   // [cw][rs] results
@@ -639,9 +639,11 @@ struct PartChunk {
     uint8_t* grp;   // [css][cw] per ordinal and window: sorted slot -> transaction (part_group)
     int cw, ps, css, rs;
 };
-__host__ __device__ inline int part_ps(int prm_rows) { return (prm_rows + 1) & ~1; }
-__host__ __device__ inline int part_css(int cells) { return (cells + 3) & ~3; }
-__host__ __device__ inline int part_rs(int res_rows) { return (res_rows + 1) & ~1; }
+// Odd row strides (in elements): the staging lanes write one row each, and
+// an odd stride spreads consecutive lanes over the LDS banks.
+__host__ __device__ inline int part_ps(int prm_rows) { return prm_rows | 1; }
+__host__ __device__ inline int part_css(int cells) { return cells | 1; }
+__host__ __device__ inline int part_rs(int res_rows) { return res_rows | 1; }
 
 // The chunk's table cells, staged in LDS: an open-addressing hash table keyed
 // by cell address (bit 1: 64-bit cell, bit 0: written; key 0 = empty slot),
@@ -830,12 +832,8 @@ __device__ __forceinline__ void serial_fwd_step(const DevType& T, const PartChun
                                                 SerialRegs<NP, NC>& Z, int64_t& committed,
                                                 int64_t& aborted) {
     (void)cnt;  // rows past the chunk hold table addresses (part_init_rows)
-    {
-        const uint4 id4 = *reinterpret_cast<const uint4*>(c.cs + (k + 2) * c.css);
-        const uint32_t idv[4] = {id4.x, id4.y, id4.z, id4.w};
 #pragma unroll
-        for (int r = 0; r < NC; ++r) Z.ids[r] = idv[r];
-    }
+    for (int r = 0; r < NC; ++r) Z.ids[r] = c.cs[(k + 2) * c.css + r];
 #pragma unroll
     for (int r = 0; r < NP; ++r) Z.prm[r] = c.prm[(k + 2) * c.ps + r];
 #pragma unroll
