@@ -196,6 +196,35 @@ def test_part_cellwise_one_procedure(proc, pipeline):
 
 
 @pytest.mark.parametrize("pipeline", [0, 1])
+@pytest.mark.parametrize("hot", [False, True])
+def test_part_chunk_and_window_edges(pipeline, hot):
+    """Partitions of 255, 256, 257, 511, 513 and 769 debit-credits: around
+    the 256-transaction chunks and 64-transaction windows.  hot: every
+    transaction of a partition names the same account, teller and branch, so
+    every window is one group per ordinal (the scan's longest groups)."""
+    counts = [255, 256, 257, 511, 513, 769]
+    nb, tpb, apt = len(counts), 3, 4
+    rng = np.random.default_rng(68)
+    n = sum(counts)
+    tabs = wl.bank_tables(rng, nb, nb * tpb, nb * tpb * apt, history_capacity=n)
+    branch = np.repeat(np.arange(nb), counts)
+    rng.shuffle(branch)
+    if hot:
+        teller = branch * tpb
+        acct = teller * apt
+    else:
+        teller = branch * tpb + rng.integers(0, tpb, n)
+        acct = teller * apt + rng.integers(0, apt, n)
+    delta = rng.integers(-99_999, 100_000, n)
+    bulk = wl.Bulk(np.zeros(n, np.int32), np.stack([acct, teller, branch, delta]).astype(np.int64),
+                   np.arange(n, dtype=np.int64))
+    _say("part edges", pipeline, hot)
+    s, g, o = run_both(tabs, wl.bank_types(), bulk, 3, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2, s.as_dict()
+    assert_parity(s, g, o, bulk)
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
 def test_part_mixed_type_ids(pipeline):
     """Debit-credit registered under two type ids: chunks are not of one type,
     so PART runs them through its generic serial path (which checks that every
