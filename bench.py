@@ -82,6 +82,33 @@ def random_gather_ceiling(device, stream, table_rows: int = 1 << 29, gathers: in
     return gathers * 8 / (ms / 1e3) / 1e9
 
 
+def random_atomic_ceiling(device, stream, table_rows: int = 1 << 26, updates: int = 1 << 26,
+                          reps: int = 3) -> float:
+    """Device atomic adds per second at uniform random rows of a 256 MiB int32
+    table (a plain library scatter-add): the ceiling the lock executor's
+    counter increments are measured against."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(1105)
+    tbl = torch.zeros(table_rows, dtype=torch.int32, device=device)
+    idx = torch.randint(0, table_rows, (updates,), dtype=torch.int64, device=device, generator=g)
+    one = torch.ones(updates, dtype=torch.int32, device=device)
+    tbl.index_add_(0, idx, one)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        tbl.index_add_(0, idx, one)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    total = int(tbl.sum().item())
+    del tbl, idx, one
+    if total != updates * (reps + 1):  # every add landed
+        raise RuntimeError(f"atomic ceiling check: {total} != {updates * (reps + 1)}")
+    return updates / (ms / 1e3)
+
+
 def make_workload(args):
     from paper_1103_3105_amd import workloads as wl
     # append capacity for every bulk this run executes (timed, PCIe, strategy comparison)
@@ -293,6 +320,9 @@ def bench_grid(args):
                 s = gputx.stats_from(stats)
                 ms = a.elapsed_time(b)
                 row[strat] = dict(ms=round(ms, 3), txn_per_s=round(s.committed / (ms / 1e3)))
+                if strat == "TPL":  # one device atomic add per operation (its lock group's counter)
+                    row[strat]["atomics"] = int(s.n_ops)
+                    row[strat]["atomics_per_s"] = round(s.n_ops / (ms / 1e3))
                 row["depth"], row["w0"] = int(s.depth), int(s.w0)
             log(f"[bench] grid n={n} theta={theta}: " + ", ".join(
                 f"{k}={row[k]['ms']:.2f}ms" for k in ("TPL", "PART", "KSET")))
@@ -504,6 +534,16 @@ def main():
     torch.cuda.empty_cache()
     if "grid" in sections:
         out["strategy_grid"] = bench_grid(args)
+        # the lock executor's counter increments against a random-atomic ceiling
+        ceil = random_atomic_ceiling(torch.device("cuda", 0), torch.cuda.current_stream())
+        log(f"[bench] random 4-byte atomic-add ceiling: {ceil / 1e9:.2f} G/s")
+        at = [r for r in out["strategy_grid"] if r["n"] == args.n and r["theta"] == args.theta]
+        if at:
+            t = at[0]["TPL"]
+            out["atomics"] = {"kernel": "k_tpl", "workload": f"same bank bulk under TPL (n={args.n}, "
+                              f"theta={args.theta})", "per_bulk": t["atomics"], "ms": t["ms"],
+                              "per_s": t["atomics_per_s"], "random_atomic_ceiling_per_s": round(ceil),
+                              "frac_of_random_atomic": round(t["atomics_per_s"] / ceil, 6)}
     if "batch" in sections:
         out["batched_vs_plain"] = bench_batch(args)
     if "serve" in sections:
