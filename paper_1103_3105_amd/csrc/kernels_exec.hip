@@ -1207,12 +1207,14 @@ __device__ __forceinline__ void stage_load(const BulkArgs& a, int32_t p, StagedT
 // into the chunk buffer and stage its cells in the table (its appended rows
 // were written by k_part_gather).  The cells are claimed first, then the won
 // cells' values are read together.
-// kUniform: every transaction of the wave has type tu, whose descriptor is
-// then read through the scalar cache.
-template <bool kUniform>
+// P != 0: every transaction of the wave has type tu, of procedure P; its
+// descriptor is then read through the scalar cache, and only P's parameters
+// and cell ordinals are handled.
+template <int P>
 __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                const StagedTxn& s, int lane, int32_t tu) {
-    const int32_t t = kUniform ? tu : s.t;
+    constexpr int NP = P != 0 ? proc_params(P) : GTX_MAX_PARAMS;
+    const int32_t t = P != 0 ? tu : s.t;
     const DevType& T = a.types[t];
     TxnIn x;
     x.t = t;
@@ -1221,13 +1223,15 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
     x.np = min(a.n_params, T.n_params);
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-        x.prm[k] = k >= x.np ? 0 : k < kStagePrm ? s.prm[k] : a.ws.rec[(int64_t)s.p * a.rec_words + 1 + k];
-    for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
+        x.prm[k] = (k >= NP || k >= x.np) ? 0
+                 : k < kStagePrm ? s.prm[k] : a.ws.rec[(int64_t)s.p * a.rec_words + 1 + k];
+    const int ncs = P != 0 ? proc_cells(P) : c.css;  // ordinals the serial side can read
+    for (int r = 0; r < ncs; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
     CellClaim claim{tab, c.cs + lane * c.css, 0u};
-    txn_cells(T, x.prm, claim);
+    txn_cells<P>(T, x.prm, claim);
     x.app0 = 0;
     x.app1 = 0;
-    const int rows = a.prm_rows;
+    const int rows = P != 0 ? NP : a.prm_rows;  // P's serial code reads only its own
 #pragma unroll
     for (int k = 0; k < GTX_MAX_PARAMS; ++k)
         if (k < rows) c.prm[lane * c.ps + k] = x.prm[k];
@@ -1249,9 +1253,29 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
     const int32_t t0 = __builtin_amdgcn_readfirstlane(x.t);  // lane 0 is live if any lane is
     uint32_t won = 0;
     if (__ballot(live && x.t != t0) == 0) {
-        if (live) won = part_claim<true>(a, c, tab, x, lane, t0);
+        if (live) {
+            switch (a.types[t0].proc) {
+#define GTX_CLAIM_CASE(P)                                     \
+    case P:                                                   \
+        won = part_claim<P>(a, c, tab, x, lane, t0);          \
+        break;
+                GTX_CLAIM_CASE(GPUTX_DEBIT_CREDIT)
+                GTX_CLAIM_CASE(GPUTX_NEW_ORDER)
+                GTX_CLAIM_CASE(GPUTX_PAYMENT)
+                GTX_CLAIM_CASE(GPUTX_ORDER_STATUS)
+                GTX_CLAIM_CASE(GPUTX_GET_SUB)
+                GTX_CLAIM_CASE(GPUTX_GET_CF)
+                GTX_CLAIM_CASE(GPUTX_UPD_SUB_FIELD)
+                GTX_CLAIM_CASE(GPUTX_UPD_LOC)
+                GTX_CLAIM_CASE(GPUTX_INS_CF)
+                GTX_CLAIM_CASE(GPUTX_DEL_CF)
+#undef GTX_CLAIM_CASE
+            default:
+                won = part_claim<0>(a, c, tab, x, lane, 0);
+            }
+        }
     } else if (live) {
-        won = part_claim<false>(a, c, tab, x, lane, 0);
+        won = part_claim<0>(a, c, tab, x, lane, 0);
     }
     // list the won slots: one counter update for the whole wave
     const int nw = __popc(won);

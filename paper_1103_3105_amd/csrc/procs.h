@@ -176,9 +176,10 @@ __device__ __forceinline__ GTX_GLOBAL V* colp(const DevType& T, int role, int c)
 // The set depends only on the parameters, and every cell lies in a row of
 // the transaction's basic operations, so under PART (no cross-partition
 // transaction) no two partitions share a cell.
-template <class F>
+// P != 0: the caller knows the procedure is P.
+template <int P = 0, class F>
 __device__ __forceinline__ void txn_cells(const DevType& T, const int64_t* p, F& f) {
-    switch (T.proc) {
+    switch (P != 0 ? P : T.proc) {
     case GPUTX_DEBIT_CREDIT:
         f.cell(0, colp<int64_t>(T, 0, 0) + p[0], true);
         f.cell(1, colp<int64_t>(T, 1, 0) + p[1], true);
