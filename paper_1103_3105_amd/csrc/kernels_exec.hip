@@ -781,7 +781,7 @@ struct LdsAcc {
     template <class V>
     __device__ __forceinline__ void st(int ord, GTX_GLOBAL V* p, V v) { ref(ord, p).set(v); }
     template <class V>
-    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by the owning lanes
+    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by k_part_gather
 };
 
 // Serial accessor over registers: the running transaction's cell values were
@@ -809,7 +809,7 @@ struct RegAcc {
     template <class V>
     __device__ __forceinline__ void st(int ord, GTX_GLOBAL V* p, V v) { ref(ord, p).set(v); }
     template <class V>
-    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by the owning lanes
+    __device__ __forceinline__ void app(GTX_GLOBAL V*, V) {}  // written by k_part_gather
 };
 
 // Cell addresses, parameters and cell values of one transaction, in registers.
@@ -1031,11 +1031,13 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
     }
 }
 
-// Lane 0 runs the chunk's cnt transactions in order against the staged
-// cells.  Statuses and results go to LDS; the owning lanes write them out
-// after the chunk.  P != 0: all run procedure P with descriptor T; P == 0:
-// mixed types.  The LDS parameter rows past a transaction's own are zero, so
-// they are read without a bound.
+// The chunk's cnt transactions run in order against the staged cells: as
+// windows (cellwise procedures, all serial waves; outcomes go straight to
+// the status and results arrays, and part_serial returns true), or on lane 0
+// of the first serial wave (statuses and results go to the chunk's LDS rows,
+// which the caller writes out).  P != 0: all run procedure P with descriptor
+// T; P == 0: mixed types.  The LDS parameter rows past a transaction's own
+// are zero, so they are read without a bound.
 //
 // Narrow procedures whose cell ordinals cannot alias across transactions
 // (proc_typed_cells) run as a forwarding pipeline (serial_fwd_step), which
@@ -1139,7 +1141,7 @@ __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
            (size_t)8 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare) +
            (size_t)part_css(a.cells_max) * cw;
 }
-// Per staging wave: 64 group masks (8 bytes each), then a tag byte per slot.
+// Per serial wave: 64 group masks (8 bytes each), then a tag byte per slot.
 __host__ __device__ inline int part_tstride(int bits) { return 512 + (1 << bits) + 16; }
 size_t part_wave_lds(const BulkArgs& a) {
     return part_chunk_bytes(a, 64) + ((size_t)sizeof(CellSlot) << a.cell_bits) + sizeof(CellSlot) +
@@ -1387,9 +1389,9 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
     }
 }
 
-// Every row of a chunk's address array starts at the sink slot, so the
-// serial lane's read-ahead past the chunk's last transaction always finds an
-// address inside the table.
+// Every row of a chunk's address array starts at the sink slot, so reads
+// ahead past the chunk's last transaction always find an address inside the
+// table.
 __device__ __forceinline__ void part_init_rows(const PartChunk& c, const CellTab& tab, int tid, int nthreads) {
     for (int e = tid; e < (c.cw + kChunkSpare) * c.css; e += nthreads) c.cs[e] = cell_sink_addr(tab);
 }
@@ -1405,12 +1407,12 @@ __device__ __forceinline__ CellTab part_table_at(unsigned char* base, int bits, 
     return tab;
 }
 
-// One wave per long partition, still one serial thread of control (Section
-// 5.2).  For each chunk of 64 of the partition's transactions the lanes load
-// the signatures into LDS, write their appended rows and stage every cell the
-// chunk may use in the LDS cell table; lane 0 then runs the 64 in order
-// against the table; finally the owning lanes write statuses, results and
-// the cells that were written.  Workgroups take long partitions in turn.
+// One wave per long partition (Section 5.2).  For each chunk of 64 of the
+// partition's transactions the lanes read the records into LDS and stage
+// every cell the chunk may use in the LDS cell table; the wave then runs the
+// 64 in order against the table (part_run_chunk); finally the lanes write
+// statuses and results if the chunk's form left them in LDS, and the cells
+// that were written.  Workgroups take long partitions in turn.
 __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_PART || (int)blockIdx.x >= st->n_heads) return;
