@@ -683,13 +683,20 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 // when the table is flushed.  The first claimant of a cell (won, one bit per
 // ordinal) lists the slot and loads the cell's value afterwards
 // (part_claim_wave, claim_values_issue): all of a transaction's claims go first,
-// so its loads are in flight together.
+// so its loads are in flight together.  With NV > 0 (procedures of at most NV
+// cells, their ordinals known at compile time) each cell's value is loaded
+// before its claim instead, into a register, and the won ones are stored
+// after the last claim (store_won): the loads then overlap the claims.
+template <int NV>
 struct CellClaim {
     CellTab tab;
     uint32_t* cs;  // the transaction's row of cell addresses
     uint32_t won;
+    int64_t v[NV > 0 ? NV : 1];
+    uint32_t at[NV > 0 ? NV : 1];
     template <class V>
     __device__ __forceinline__ void cell(int ord, GTX_GLOBAL V* p, bool w) {
+        if constexpr (NV > 0) v[ord] = (int64_t)*p;  // kept only if this lane wins the cell
         const uint64_t key = cell_key(p);
         const uint64_t want = key | (w ? 1u : 0u);
         const uint32_t mask = (1u << tab.bits) - 1;
@@ -703,6 +710,7 @@ struct CellClaim {
                 if (cur == 0) {
                     got = cell_val_addr(tab, h);
                     won |= 1u << ord;
+                    if constexpr (NV > 0) at[ord] = got;
                     break;
                 }
             }
@@ -715,6 +723,11 @@ struct CellClaim {
             }
         }
         cs[ord] = got;
+    }
+    __device__ __forceinline__ void store_won() const {
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if ((won >> r) & 1u) *(GTX_LDS int64_t*)(uintptr_t)at[r] = v[r];
     }
 };
 // The won cells' values, four loads in flight at a time; the slot's key holds
@@ -1214,7 +1227,9 @@ __device__ __forceinline__ void stage_load(const BulkArgs& a, int32_t p, StagedT
 // and cell ordinals are handled.
 template <int P>
 __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                               const StagedTxn& s, int lane, int32_t tu) {
+                                               const StagedTxn& s, int lane, int32_t tu, uint32_t& pending) {
+    // values loaded during the claims for procedures of a few cells
+    constexpr int NV = (P != 0 && proc_cells(P) <= 4) ? proc_cells(P) : 0;
     constexpr int NP = P != 0 ? proc_params(P) : GTX_MAX_PARAMS;
     const int32_t t = P != 0 ? tu : s.t;
     const DevType& T = a.types[t];
@@ -1229,8 +1244,13 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
                  : k < kStagePrm ? s.prm[k] : a.ws.rec[(int64_t)s.p * a.rec_words + 1 + k];
     const int ncs = P != 0 ? proc_cells(P) : c.css;  // ordinals the serial side can read
     for (int r = 0; r < ncs; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
-    CellClaim claim{tab, c.cs + lane * c.css, 0u};
+    CellClaim<NV> claim;
+    claim.tab = tab;
+    claim.cs = c.cs + lane * c.css;
+    claim.won = 0;
     txn_cells<P>(T, x.prm, claim);
+    if constexpr (NV > 0) claim.store_won();
+    pending = NV > 0 ? 0u : claim.won;
     x.app0 = 0;
     x.app1 = 0;
     const int rows = P != 0 ? NP : a.prm_rows;  // P's serial code reads only its own
@@ -1248,18 +1268,19 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
 }
 
 // The live lanes (c0 + lane < end) claim their transactions, read earlier
-// into x.  Needs the whole wave.
+// into x, and the wave lists the slots it won.  Returns the lane's won cells
+// whose values are still to be loaded.  Needs the whole wave.
 __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                     const StagedTxn& x, int64_t c0, int64_t end, int lane) {
     const bool live = c0 + lane < end;
     const int32_t t0 = __builtin_amdgcn_readfirstlane(x.t);  // lane 0 is live if any lane is
-    uint32_t won = 0;
+    uint32_t won = 0, pending = 0;
     if (__ballot(live && x.t != t0) == 0) {
         if (live) {
             switch (a.types[t0].proc) {
 #define GTX_CLAIM_CASE(P)                                     \
     case P:                                                   \
-        won = part_claim<P>(a, c, tab, x, lane, t0);          \
+        won = part_claim<P>(a, c, tab, x, lane, t0, pending); \
         break;
                 GTX_CLAIM_CASE(GPUTX_DEBIT_CREDIT)
                 GTX_CLAIM_CASE(GPUTX_NEW_ORDER)
@@ -1273,35 +1294,35 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
                 GTX_CLAIM_CASE(GPUTX_DEL_CF)
 #undef GTX_CLAIM_CASE
             default:
-                won = part_claim<0>(a, c, tab, x, lane, 0);
+                won = part_claim<0>(a, c, tab, x, lane, 0, pending);
             }
         }
     } else if (live) {
-        won = part_claim<0>(a, c, tab, x, lane, 0);
+        won = part_claim<0>(a, c, tab, x, lane, 0, pending);
     }
     // list the won slots: one counter update for the whole wave
     const int nw = __popc(won);
     const int incl = wave_incl_sum_dpp(nw);
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    if (total == 0) return 0;
+    if (total == 0) return pending;
     int e0 = 0;
     if (lane % 64 == 63) e0 = __hip_atomic_fetch_add(tab.nlist, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     int e = __builtin_amdgcn_readlane(e0, 63) + incl - nw;
     const uint32_t* row = c.cs + lane * c.css;
     const uint32_t base = lds_addr(tab.slot);
     for (uint32_t m = won; m; m &= m - 1) tab.list[e++] = (int32_t)((row[__ffs(m) - 1] - base) >> 4);
-    return won;
+    return pending;
 }
 
 // Stage a chunk whose transactions were read already (x): claim the cells,
 // then load the won ones.  Needs the whole wave.
 __device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                 const StagedTxn& x, int64_t c0, int64_t end, int lane) {
-    const uint32_t won = part_claim_wave(a, c, tab, x, c0, end, lane);
+    const uint32_t pending = part_claim_wave(a, c, tab, x, c0, end, lane);
     const uint32_t* row = c.cs + lane * c.css;
     ValLoads vl;
-    claim_values_issue(row, won, vl);
-    claim_values_finish(row, won, vl);
+    claim_values_issue(row, pending, vl);
+    claim_values_finish(row, pending, vl);
 }
 // Read and stage the chunk starting at c0 in one go (no read-ahead).
 __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
