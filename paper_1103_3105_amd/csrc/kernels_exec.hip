@@ -636,7 +636,6 @@ struct PartChunk {
     int32_t* proc;  // [cw] procedure
     int32_t* st;    // [cw] status
     uint32_t* cs;   // [cw + kChunkSpare][css] LDS address of each of the transaction's staged cells
-    uint8_t* grp;   // [css][cw] per ordinal and window: sorted slot -> transaction (part_group)
     int cw, ps, css, rs;
 };
 // Odd row strides (in elements): the staging lanes write one row each, and
@@ -942,23 +941,23 @@ struct SerialWave {
     GTX_LDS uint8_t* tag;  // [512 + tag bytes]: 64 group masks, then a tag byte per slot
 };
 
-// Sort a window's lanes (transactions k0 .. k0+n-1, lane j holding k0 + j)
-// into groups naming the same cell at ordinal r, stably: every lane stores
-// its lane number in the tag byte of its cell's slot, and the value it reads
-// back (one of the group's lanes, the same for the whole group) names the
-// group; each lane ORs its bit into that lane's group mask, then reads the
-// mask, and the groups are laid out in the order of those lanes.  For sorted
-// slot s, grp[r][k0 + s] holds the transaction's lane (bits 0-5), and whether
-// s starts (bit 6) or ends (bit 7) its group.  Lanes past n are groups of
-// their own.  Needs all 64 lanes of the wave.
-__device__ __forceinline__ void group_ordinal(const PartChunk& c, const CellTab& tab, GTX_LDS uint8_t* mine,
-                                              int r, int k0, int n) {
+// Sort a window's lanes (transactions k0 .. k0+n-1, lane j holding k0 + j,
+// naming the cell at LDS address id) into groups naming the same cell,
+// stably: every lane stores its lane number in the tag byte of its cell's
+// slot, and the value it reads back (one of the group's lanes, the same for
+// the whole group) names the group; each lane ORs its bit into that lane's
+// group mask, then reads the mask, and the groups are laid out in the order
+// of those lanes.  Returns the lane's sorted slot, and whether it starts or
+// ends its group.  Lanes past n are groups of their own.  Needs all 64
+// lanes of the wave.
+__device__ __forceinline__ int group_ordinal(const CellTab& tab, GTX_LDS uint8_t* mine, uint32_t id, int n,
+                                             bool& head, bool& last) {
     const int j = lane_id();
     const bool live = j < n;
     GTX_LDS uint64_t* gmask = (GTX_LDS uint64_t*)mine;
     // volatile: the read must see whichever lane's store landed, not this lane's
     volatile GTX_LDS uint8_t* tag = mine + 512;
-    const uint32_t h = (c.cs[(k0 + j) * c.css + r] - lds_addr(tab.slot)) >> 4;  // the sink is slot 1 << bits
+    const uint32_t h = (id - lds_addr(tab.slot)) >> 4;  // the sink is slot 1 << bits
     gmask[j] = 0;
     int rep = j;
     if (live) {
@@ -970,8 +969,17 @@ __device__ __forceinline__ void group_ordinal(const PartChunk& c, const CellTab&
     const int rank = __popcll(eq & lanemask_lt());
     const int size = __popcll(eq);
     const int own = rep == j ? size : 0;
-    const int pos = __shfl(wave_incl_sum_dpp(own) - own, rep) + rank;
-    c.grp[r * c.cw + k0 + pos] = (uint8_t)(j | (rank == 0 ? 64 : 0) | (rank == size - 1 ? 128 : 0));
+    head = rank == 0;
+    last = rank == size - 1;
+    return __shfl(wave_incl_sum_dpp(own) - own, rep) + rank;
+}
+// Lane to (push): the value lands in lane `to` (a permutation of the wave).
+__device__ __forceinline__ uint32_t push32(int to, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_ds_permute(to * 4, (int)v);
+}
+__device__ __forceinline__ int64_t push64(int to, int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)push32(to, (uint32_t)(u >> 32)) << 32) | push32(to, (uint32_t)u));
 }
 
 // Cellwise procedures (proc_cellwise) run a window of up to 64 transactions
@@ -1004,22 +1012,28 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
 #pragma unroll
     for (int r = 0; r < NC; ++r) {
         if (r % sw.nsw != sw.ws) continue;
-        int k = k0 + s;  // < cw: every row read exists
-        bool head = true, last = true;
-        if constexpr (kW) {
-            group_ordinal(c, tab, sw.tag, r, k0, n);
-            const uint32_t g = c.grp[r * c.cw + k0 + s];
-            k = k0 + (int)(g & 63u);
-            head = g & 64u;
-            last = g & 128u;
-        }
-        const uint32_t id = c.cs[k * c.css + r];
+        // this lane's transaction in window order
+        const int kj = k0 + s;  // < cw: every row read exists
+        uint32_t id = c.cs[kj * c.css + r];
         int64_t p[NP];
 #pragma unroll
-        for (int q = 0; q < NP; ++q) p[q] = c.prm[k * c.ps + q];
-        const int64_t init = *(GTX_LDS const int64_t*)(uintptr_t)id;
+        for (int q = 0; q < NP; ++q) p[q] = c.prm[kj * c.ps + q];
+        int64_t init = *(GTX_LDS const int64_t*)(uintptr_t)id;
+        int64_t idx = c.idx[kj];
         int64_t old = init;
+        bool last = true;
         if constexpr (kW) {
+            // take the transaction at this lane's sorted slot instead
+            bool hd, ls;
+            const int to = group_ordinal(tab, sw.tag, id, n, hd, ls);
+            const uint32_t fl = push32(to, (hd ? 1u : 0u) | (ls ? 2u : 0u));
+            id = push32(to, id);
+#pragma unroll
+            for (int q = 0; q < NP; ++q) p[q] = push64(to, p[q]);
+            init = push64(to, init);
+            idx = push64(to, idx);
+            const bool head = fl & 1u;
+            last = fl & 2u;
             bool fa;
             int64_t fb;
             cell_affine<P>(r, p, fa, fb);
@@ -1037,8 +1051,8 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
         bool w;
         int at;
         cell_apply<P>(r, old, p, nv, w, at, res);
-        if (live) {
-            if (at >= 0 && at < a.width) a.results[c.idx[k] * a.width + at] = res;
+        if (live) {  // sorted slots below n hold the live transactions
+            if (at >= 0 && at < a.width) a.results[idx * a.width + at] = res;
             if (w && last) *(GTX_LDS int64_t*)(uintptr_t)id = nv;
         }
     }
@@ -1151,8 +1165,7 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
 
 __host__ __device__ inline size_t part_chunk_bytes(const BulkArgs& a, int cw) {
     return (size_t)8 * part_rs(a.res_rows) * cw + (size_t)8 * part_ps(a.prm_rows) * (cw + kChunkSpare) +
-           (size_t)8 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare) +
-           (size_t)part_css(a.cells_max) * cw;
+           (size_t)8 * cw + (size_t)4 * 3 * cw + (size_t)4 * part_css(a.cells_max) * (cw + kChunkSpare);
 }
 // Per serial wave: 64 group masks (8 bytes each), then a tag byte per slot.
 __host__ __device__ inline int part_tstride(int bits) { return 512 + (1 << bits) + 16; }
@@ -1193,7 +1206,6 @@ __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const Bu
     c.proc = c.t + cw;
     c.st = c.proc + cw;
     c.cs = reinterpret_cast<uint32_t*>(c.st + cw);
-    c.grp = reinterpret_cast<uint8_t*>(c.cs + (cw + kChunkSpare) * c.css);
     return c;
 }
 
