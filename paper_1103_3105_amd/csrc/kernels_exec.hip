@@ -633,7 +633,7 @@ struct PartChunk {
     int64_t* prm;   // [cw + kChunkSpare][ps] parameters
     int64_t* idx;   // [cw] input index (status / results slot)
     int32_t* t;     // [cw] type
-    int32_t* proc;  // [cw] procedure
+    int32_t* proc;  // [cw] procedure (bits 0-15) and cell class (bits 16-31)
     int32_t* st;    // [cw] status
     uint32_t* cs;   // [cw + kChunkSpare][css] LDS address of each of the transaction's staged cells
     int cw, ps, css, rs;
@@ -1092,7 +1092,10 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         }
         return true;
     }
-    if (sw.ws != 0 || lane_id() != 0) return false;
+    // lane 0 of one serial wave per cell class: classes never share a cell
+    if (lane_id() != 0) return false;
+    if constexpr (P != 0)
+        if (T.cell_class % sw.nsw != sw.ws) return false;
     uint32_t seen = ~0u;
     if constexpr (ahead) {
         SerialRegs<NP, NC> A, B;  // transactions 0 and 1 (row 1 exists even if cnt == 1)
@@ -1131,9 +1134,11 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         // which reads only that procedure's parameters and cells
         int n_commit = 0, n_abort = 0;
         for (int k = 0; k < cnt; ++k) {
+            const int32_t pc = c.proc[k];
+            if ((pc >> 16) % sw.nsw != sw.ws) continue;
             const DevType& Tk = a.types[c.t[k]];
             int32_t s = GPUTX_INVALID;
-            switch (c.proc[k]) {
+            switch (pc & 0xffff) {
 #define GTX_ONE(Q)                                                    \
     case Q:                                                           \
         s = serial_one<Q>(Tk, c, k, &seen);                           \
@@ -1274,7 +1279,7 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
         if (r < a.res_rows) c.res[lane * c.rs + r] = 0;
     c.idx[lane] = x.i;
     c.t[lane] = t;
-    c.proc[lane] = T.proc;
+    c.proc[lane] = T.proc | (T.cell_class << 16);
     c.st[lane] = GPUTX_COMMIT;
     return claim.won;
 }
@@ -1345,11 +1350,13 @@ __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c
     part_stage_read(a, c, tab, x, c0, end, lane);
 }
 
-// The serial waves write the statuses and results of the cnt transactions
-// they just ran, rows t0, t0 + nt, ... (they read no global memory, so the
-// stores never hold them up).
-__device__ __forceinline__ void part_writeout_all(const BulkArgs& a, const PartChunk& c, int cnt, int t0, int nt) {
-    for (int r = t0; r < cnt; r += nt) {
+// A serial wave writes the statuses and results of the chunk's transactions
+// it ran: those of its cell classes (it reads no global memory, so the stores
+// never hold it up).
+__device__ __forceinline__ void part_writeout_own(const BulkArgs& a, const PartChunk& c, int cnt, int lane,
+                                                  const SerialWave& sw) {
+    for (int r = lane; r < cnt; r += 64) {
+        if ((c.proc[r] >> 16) % sw.nsw != sw.ws) continue;
         const int64_t i = c.idx[r];
         a.status[i] = c.st[r];
         int64_t* out = a.results + i * a.width;
@@ -1552,8 +1559,8 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
             int32_t pa = 0;
             if (serial) {
                 const int cnt = (int)min<int64_t>(cw, end - c0);
-                if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted) && ws == 0)
-                    part_writeout_all(a, buf(k), cnt, lane, 64);
+                if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted))
+                    part_writeout_own(a, buf(k), cnt, lane, sw);
             } else {
                 bool flush = false;
                 if (k + 1 < nch) {

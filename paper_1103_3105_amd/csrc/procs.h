@@ -19,7 +19,8 @@ struct DevType {
     int32_t n_results;
     int32_t root_key;
     int32_t app_idx[2];  // append-table index of the procedure's appends (-1: none)
-    int32_t pad[2];
+    int32_t cell_class;  // types of different classes never name the same cell
+    int32_t pad;
     int64_t dims[4];     // procedure dimensions (see type registration)
     int64_t rows[GTX_ROLES];        // rows of each bound (non-append) table
     int64_t root_div[GTX_ROLES];    // rows per root key
@@ -223,6 +224,13 @@ __device__ __forceinline__ void txn_cells(const DevType& T, const int64_t* p, F&
     }
 }
 
+// Roles (bound tables) whose rows txn_cells names for procedure P.
+__host__ __device__ constexpr uint32_t proc_cell_roles(int proc) {
+    return (proc == GPUTX_DEBIT_CREDIT || proc == GPUTX_PAYMENT) ? 0x7u
+         : proc == GPUTX_NEW_ORDER ? 0x8u : proc == GPUTX_ORDER_STATUS ? 0x4u
+         : (proc == GPUTX_GET_SUB || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 0x1u
+         : (proc == GPUTX_GET_CF || proc == GPUTX_INS_CF || proc == GPUTX_DEL_CF) ? 0x2u : 0xffu;
+}
 // Most cells txn_cells lists for one transaction of procedure P (0: any).
 __host__ __device__ constexpr int proc_cells(int proc) {
     return proc == GPUTX_NEW_ORDER ? 15 : proc == GPUTX_GET_SUB ? 14

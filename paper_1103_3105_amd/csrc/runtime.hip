@@ -356,6 +356,46 @@ extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, in
         mo = std::max(mo, ps.ops);
     }
     h->max_ops = mo;
+    // Cell classes: types whose procedures name rows of a common table are
+    // joined, so types of different classes never name the same cell (PART
+    // may run them side by side).
+    int cls[GPUTX_MAX_TYPES];
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) cls[i] = i;
+    auto find = [&](int x) {
+        while (cls[x] != x) x = cls[x] = cls[cls[x]];
+        return x;
+    };
+    auto tables_of = [&](int i, int64_t* ids) {
+        const uint32_t roles = proc_cell_roles(h->types[i].proc);
+        int k = 0;
+        for (int r = 0; r < GTX_ROLES; ++r)
+            if ((roles >> r) & 1u) ids[k++] = h->types[i].table_ids[r];
+        return k;
+    };
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
+        if (!h->type_present[i]) continue;
+        int64_t ti[GTX_ROLES];
+        const int ni = tables_of(i, ti);
+        for (int j = 0; j < i; ++j) {
+            if (!h->type_present[j]) continue;
+            int64_t tj[GTX_ROLES];
+            const int nj = tables_of(j, tj);
+            bool shared = false;
+            for (int x = 0; x < ni && !shared; ++x)
+                for (int y = 0; y < nj && !shared; ++y) shared = ti[x] == tj[y];
+            if (shared) cls[find(i)] = find(j);
+        }
+    }
+    int label[GPUTX_MAX_TYPES], nlabel = 0;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) label[i] = -1;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
+        if (!h->type_present[i]) continue;
+        const int root = find(i);
+        if (label[root] < 0) label[root] = nlabel++;
+        const int32_t c = label[root];
+        HIP_OK(h, hipMemcpy((char*)(h->d_types + i) + offsetof(DevType, cell_class), &c, sizeof c,
+                            hipMemcpyHostToDevice));
+    }
     return GPUTX_OK;
 }
 
