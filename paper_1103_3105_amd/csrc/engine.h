@@ -54,6 +54,11 @@ struct Ws {
     uint32_t* sort_hist; // [8][256]
     uint32_t* sort_status;
     uint32_t* sort_ctrl; // [16]
+    // the partition sort's own histogram, look-back words and tile counters,
+    // so that it can run beside the item-key sort
+    uint32_t* psort_hist;   // [8][256]
+    uint32_t* psort_status;
+    uint32_t* psort_ctrl;   // [16]
     int32_t* scan_tmp;   // [(1 + GTX_MAX_APPEND)][scan blocks]
     int32_t* tcnt_tmp;   // [kPrepBlocks][GPUTX_MAX_TYPES] per-block type counts
     RankAgg* rank_tmp;   // [2][rank tiles]
@@ -96,7 +101,7 @@ struct BulkArgs {
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
     int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane
     int32_t res_rows;       // PART LDS result rows: most results of a registered procedure
-    int32_t pad_;
+    int32_t part_early;     // 1: PART's sort and records run before the choice, beside the ranking
     Ws ws;
 };
 
@@ -118,10 +123,24 @@ struct PhaseMarks {
     }
 };
 
-// bulk generation (kernels_front.hip)
-void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
+// A second stream for work that may overlap the ranking: the fork event is
+// recorded on the bulk's stream, the join event on this one.
+struct SideLane {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// bulk generation (kernels_front.hip); with a side lane and a.part_early set,
+// PART's partition sort and records run on it from the emission on, and the
+// bulk's stream waits for them after the features
+hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm,
+                        const SideLane* side = nullptr);
 // execution (kernels_exec.hip)
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
+// PART's stable sort of transactions by partition and the partition heads
+// (kernels_exec.hip), gated on the choice; with a.part_early set they run
+// ungated and the records (k_part_gather) follow them on the same stream
+void launch_part_sort(const BulkArgs& a, hipStream_t s);
 // zero-transaction bulk: reset state and publish statistics
 void launch_empty(const BulkArgs& a, hipStream_t s);
 // workgroups of the persistent executors that fit on one compute unit

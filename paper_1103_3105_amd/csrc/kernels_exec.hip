@@ -509,7 +509,7 @@ __device__ __forceinline__ bool part_head(const uint32_t* key, int64_t i, uint32
 
 __global__ __launch_bounds__(GTX_BLOCK) void k_heads_up(BulkArgs a) {
     const GtxState* st = a.ws.st;
-    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    if (!(a.part_early || st->run_part) || ld_relaxed(&st->error) != 0) return;
     __shared__ int lds[GTX_WAVES + 1];
     const uint32_t* key = a.ws.qk[a.part_passes & 1];
     const int64_t i0 = (int64_t)blockIdx.x * kHeadTile + (int64_t)threadIdx.x * kHeadItems;
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_heads_up(BulkArgs a) {
 
 __global__ __launch_bounds__(GTX_BLOCK) void k_heads_mid(BulkArgs a, int nb) {
     GtxState* st = a.ws.st;
-    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    if (!(a.part_early || st->run_part) || ld_relaxed(&st->error) != 0) return;
     __shared__ int lds[GTX_WAVES + 1];
     int carry = 0;
     for (int b0 = 0; b0 < nb; b0 += GTX_BLOCK) {
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_heads_mid(BulkArgs a, int nb) {
 
 __global__ __launch_bounds__(GTX_BLOCK) void k_heads_down(BulkArgs a) {
     const GtxState* st = a.ws.st;
-    if (!st->run_part || ld_relaxed(&st->error) != 0) return;
+    if (!(a.part_early || st->run_part) || ld_relaxed(&st->error) != 0) return;
     __shared__ int lds[GTX_WAVES + 1];
     const uint32_t* key = a.ws.qk[a.part_passes & 1];
     const uint32_t sentinel = (uint32_t)a.n_parts;
@@ -584,7 +584,9 @@ __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int6
 // falls back to TPL otherwise), so every valid transaction is PART's.
 __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     const GtxState* st = a.ws.st;
-    if (failed(st) || st->chosen != GPUTX_PART) return;
+    // ahead of the choice too: the records are workspace, and the appended
+    // rows (a function of the signatures alone) are the ones any executor writes
+    if (failed(st) || !(a.part_early || st->chosen == GPUTX_PART)) return;
     for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * GTX_BLOCK) {
         const int32_t t = a.ws.tty[p];
@@ -1676,27 +1678,34 @@ int exec_resident_blocks_per_cu() {
     return cached;
 }
 
+static void launch_part_gather(const BulkArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_part_gather, dim3((unsigned)std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096)),
+                       dim3(GTX_BLOCK), 0, s, a);
+}
+
+void launch_part_sort(const BulkArgs& a, hipStream_t s) {
+    SortPlan sp{};
+    sp.key_bytes = 4;
+    sp.keys[0] = a.ws.qk[0]; sp.keys[1] = a.ws.qk[1];
+    sp.vals[0] = a.ws.qv[0]; sp.vals[1] = a.ws.qv[1];
+    sp.hist = a.ws.psort_hist; sp.status = a.ws.psort_status; sp.ctrl = a.ws.psort_ctrl;
+    sp.cap = a.n; sp.count_dev = nullptr; sp.npass = a.part_passes;
+    sp.gate = a.part_early ? nullptr : &a.ws.st->run_part;
+    sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
+    sort_pairs(sp, s);
+    const unsigned nbh = (unsigned)std::max<int64_t>(1, (a.n + kHeadTile - 1) / kHeadTile);
+    hipLaunchKernelGGL(k_heads_up, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_heads_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, (int)nbh);
+    hipLaunchKernelGGL(k_heads_down, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+    if (a.part_early) launch_part_gather(a, s);
+}
+
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     hipLaunchKernelGGL(k_exec_gate, dim3(1), dim3(64), 0, s, a);
     // PART: group transactions by partition (stable, so timestamp order is
     // kept inside each partition); only when PART was chosen
     const bool part = a.strategy == GPUTX_AUTO || a.strategy == GPUTX_PART;
-    if (part) {
-        SortPlan sp{};
-        sp.key_bytes = 4;
-        sp.keys[0] = a.ws.qk[0]; sp.keys[1] = a.ws.qk[1];
-        sp.vals[0] = a.ws.qv[0]; sp.vals[1] = a.ws.qv[1];
-        sp.hist = a.ws.sort_hist; sp.status = a.ws.sort_status; sp.ctrl = a.ws.sort_ctrl;
-        sp.cap = a.n; sp.count_dev = nullptr; sp.npass = a.part_passes;
-        sp.gate = &a.ws.st->run_part; sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
-        sort_pairs(sp, s);
-    }
-    if (part) {
-        const unsigned nbh = (unsigned)std::max<int64_t>(1, (a.n + kHeadTile - 1) / kHeadTile);
-        hipLaunchKernelGGL(k_heads_up, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_heads_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, (int)nbh);
-        hipLaunchKernelGGL(k_heads_down, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
-    }
+    if (part && !a.part_early) launch_part_sort(a, s);
     pm.mark(PH_PARTSORT, s);
     if (part) {
         // long partitions: a workgroup each with the LDS cell table (chunks of
@@ -1709,8 +1718,7 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         const bool wave = !pipe256 && !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
         b.long_part = (pipe256 || pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
         const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
-        hipLaunchKernelGGL(k_part_gather, dim3((unsigned)std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096)),
-                           dim3(GTX_BLOCK), 0, s, b);
+        if (!a.part_early) launch_part_gather(a, s);
         pm.mark(PH_PARTGATHER, s);
         if (pipe256)
             hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 * kPipeSerial + 256), part_pipe_lds(a, 256), s, b);

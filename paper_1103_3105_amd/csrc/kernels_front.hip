@@ -541,7 +541,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_features(BulkArgs a) {
 // ---- host side ------------------------------------------------------------
 static unsigned blocks_for(int64_t n, int64_t per) { return (unsigned)std::max<int64_t>(1, (n + per - 1) / per); }
 
-void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
+hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, const SideLane* side) {
     pm.mark(PH_START, s);
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(GTX_BLOCK), 0, s, a.ws.st);
     hipLaunchKernelGGL(k_order_check, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
@@ -566,6 +566,19 @@ void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     pm.mark(PH_PREPARE, s);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_EMIT, s);
+    // PART's partition ids are known once the operations are emitted: with a
+    // side lane, its sort, heads and records run beside the item-key sort and
+    // the ranking
+    const bool early = side && a.part_early;
+    hipError_t e = hipSuccess;
+    if (early) {
+        e = hipEventRecord(side->fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
+        if (e != hipSuccess) return e;
+        launch_part_sort(a, side->s);
+        e = hipEventRecord(side->join, side->s);
+        if (e != hipSuccess) return e;
+    }
     {
         SortPlan sp{};
         sp.key_bytes = 4;
@@ -584,6 +597,8 @@ void launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     pm.mark(PH_RANK, s);
     hipLaunchKernelGGL(k_features, dim3(std::min<unsigned>(1024, blocks_for(a.n, GTX_BLOCK))), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_FEATURES, s);
+    if (early) e = hipStreamWaitEvent(s, side->join, 0);
+    return e;
 }
 
 }  // namespace gtx

@@ -34,6 +34,8 @@ struct gputx_ctx {
     bool timing = false;
     hipEvent_t* ev = nullptr;  // kRing * PH_COUNT
     int ring_used = 0;
+    // second stream of the one-bulk form (PART's partition sort beside the ranking)
+    gtx::SideLane side{};
 };
 
 

@@ -79,11 +79,17 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     if (e == hipSuccess) e = hipMemset(h->d_types, 0, sizeof(DevType) * GPUTX_MAX_TYPES);
     if (e == hipSuccess) e = hipMemset(h->d_rowcount, 0, sizeof(int64_t) * GTX_MAX_APPEND);
     if (e == hipSuccess) e = hipMemset(h->d_capacity, 0, sizeof(int64_t) * GTX_MAX_APPEND);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming);
     if (e != hipSuccess) {
         int rc = gtx_set_err(nullptr, GPUTX_E_HIP, "device setup failed: %s", hipGetErrorString(e));
         if (h->d_types) (void)hipFree(h->d_types);
         if (h->d_rowcount) (void)hipFree(h->d_rowcount);
         if (h->d_capacity) (void)hipFree(h->d_capacity);
+        if (h->side.join) (void)hipEventDestroy(h->side.join);
+        if (h->side.fork) (void)hipEventDestroy(h->side.fork);
+        if (h->side.s) (void)hipStreamDestroy(h->side.s);
         delete h;
         return rc;
     }
@@ -100,6 +106,10 @@ extern "C" int gputx_destroy(gputx_handle h) {
     (void)hipFree(h->d_types);
     (void)hipFree(h->d_rowcount);
     (void)hipFree(h->d_capacity);
+    (void)hipStreamSynchronize(h->side.s);
+    (void)hipEventDestroy(h->side.join);
+    (void)hipEventDestroy(h->side.fork);
+    (void)hipStreamDestroy(h->side.s);
     if (h->ev) {
         for (int i = 0; i < gputx_ctx::kRing * PH_COUNT; ++i) (void)hipEventDestroy(h->ev[i]);
         delete[] h->ev;
@@ -441,10 +451,12 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.rec = L.take<int64_t>(n * part_rec_words(prm_rows));
     w.front[0] = L.take<int32_t>(n); w.front[1] = L.take<int32_t>(n);
     w.sort_hist = L.take<uint32_t>(8 * 256);
-    size_t sw = std::max({sort_status_words(n, 8), sort_status_words(mcap, h->key_passes),
-                          sort_status_words(n, h->part_passes)});
+    size_t sw = std::max(sort_status_words(n, 8), sort_status_words(mcap, h->key_passes));
     w.sort_status = L.take<uint32_t>((int64_t)sw);
     w.sort_ctrl = L.take<uint32_t>(16);
+    w.psort_hist = L.take<uint32_t>(8 * 256);
+    w.psort_status = L.take<uint32_t>((int64_t)sort_status_words(n, h->part_passes));
+    w.psort_ctrl = L.take<uint32_t>(16);
     const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
     w.scan_tmp = L.take<int32_t>(nb * (1 + GTX_MAX_APPEND));
     w.tcnt_tmp = L.take<int32_t>(kPrepBlocks * GPUTX_MAX_TYPES);
@@ -567,7 +579,11 @@ extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strat
     if (b->n == 0) {
         launch_empty(a, s);
     } else {
-        launch_front(a, s, pm);
+        // PART's partition sort does not depend on the choice: when PART may
+        // run, it overlaps the ranking on the context's second stream
+        a.part_early = (strategy == GPUTX_AUTO || strategy == GPUTX_PART) ? 1 : 0;
+        hipError_t fe = launch_front(a, s, pm, &h->side);
+        if (fe != hipSuccess) return gtx_set_err(h, GPUTX_E_HIP, "stream fork failed: %s", hipGetErrorString(fe));
         launch_exec(a, s, pm);
     }
     hipError_t e = hipGetLastError();
@@ -647,7 +663,7 @@ extern "C" int gputx_batch_create(gputx_handle h, const gputx_batch_item* items,
                 launch_empty(args[k], es[l]);
                 continue;
             }
-            launch_front(args[k], fs[l], none);
+            (void)launch_front(args[k], fs[l], none);
             hipEvent_t ready = mkev();
             e = hipEventRecord(ready, fs[l]);
             if (e == hipSuccess) e = hipStreamWaitEvent(es[l], ready, 0);

@@ -159,7 +159,7 @@ extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_se
             hipGraph_t gf = nullptr, ge = nullptr;
             hipGraphExec_t xf = nullptr, xe = nullptr;
             SERVE_OK(hipStreamBeginCapture(s.fs, hipStreamCaptureModeThreadLocal));
-            launch_front(a, s.fs, none);
+            (void)launch_front(a, s.fs, none);
             SERVE_OK(hipStreamEndCapture(s.fs, &gf));
             s.graphs.push_back(gf);
             SERVE_OK(hipGraphInstantiate(&xf, gf, nullptr, nullptr, 0));
