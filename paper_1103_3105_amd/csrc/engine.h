@@ -40,7 +40,8 @@ struct Ws {
     int32_t* op_txn;     // [mcap] serial position of each operation
     uint32_t* pk[2];     // [mcap] operation sort: item key
     uint32_t* pv[2];     // [mcap] operation sort: op index << 1 | write
-    OpInfo* op_info;     // [mcap]
+    int32_t* op_rank;    // [mcap] the paper's rank of each operation
+    OpInfo* op_info;     // [mcap] written only when TPL or K-SET runs
     int32_t* srt_txn;    // [mcap] serial position of each sorted op
     int32_t* grp_cnt;    // [mcap] per-group completion counters
     uint32_t* qk[2];     // [n] PART sort: partition id
@@ -135,6 +136,9 @@ struct SideLane {
 // bulk's stream waits for them after the features
 hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm,
                         const SideLane* side = nullptr);
+// the lock and k-set executors' per-operation records (kernels_front.hip),
+// gated on the choice
+void launch_rank_full(const BulkArgs& a, hipStream_t s);
 // execution (kernels_exec.hip)
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 // PART's stable sort of transactions by partition and the partition heads

@@ -224,7 +224,23 @@ __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* 
     }
 }
 
-// Only when K-SET runs: the transaction of each operation in item-sorted
+// Only when K-SET runs: each transaction's in-degree, the in-edges its
+// operations contribute (Section 4.2's dependency graph) ...
+__global__ __launch_bounds__(GTX_BLOCK) void k_kset_indeg(BulkArgs a) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
+    for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
+         p += (int64_t)gridDim.x * GTX_BLOCK) {
+        int in = 0;
+        if (a.ws.tty[p] >= 0) {
+            const int64_t o1 = p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : st->m;
+            for (int64_t o = a.ws.cnt[p]; o < o1; ++o) in += a.ws.op_info[o].in;
+        }
+        a.ws.indeg[p] = in;
+    }
+}
+
+// ... the transaction of each operation in item-sorted
 // order (the read runs K-SET releases) ...
 __global__ __launch_bounds__(GTX_BLOCK) void k_kset_sorted_txn(BulkArgs a) {
     const GtxState* st = a.ws.st;
@@ -1735,10 +1751,12 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
         pm.mark(PH_PARTGATHER, s);
     }
     pm.mark(PH_PART, s);
+    launch_rank_full(a, s);  // wait targets, groups, successors: TPL or K-SET chosen
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_TPL || a.strategy == GPUTX_PART)
         hipLaunchKernelGGL(k_tpl, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_TPL, s);
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_KSET) {
+        hipLaunchKernelGGL(k_kset_indeg, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset_sorted_txn, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset_succ, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);

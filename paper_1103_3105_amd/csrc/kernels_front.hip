@@ -383,9 +383,16 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_mid(BulkArgs a, int nb_cap) 
     }
 }
 
+// Downsweep of the ranking scan.  The front end (kFull = false) keeps only
+// each operation's rank, all that the features need; the lock and k-set
+// executors' wait targets, groups and successor ranges (kFull = true) are
+// written by a second downsweep over the same sorted pairs and carries, only
+// when one of those executors was chosen.
+template <bool kFull>
 __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap) {
     const GtxState* st = a.ws.st;
     if (bulk_failed(st)) return;
+    if (kFull && st->chosen != GPUTX_TPL && st->chosen != GPUTX_KSET) return;
     __shared__ RankAgg lds[GTX_WAVES];
     const int32_t m = (int32_t)st->m;
     const int64_t base = (int64_t)blockIdx.x * kRankTile;
@@ -462,6 +469,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
             }
             in_c = Aex > gs ? 1 : 0;
         }
+        if (!kFull) {
+            a.ws.op_rank[o] = rank;
+            continue;
+        }
         OpInfo inf;
         inf.grp = g;
         inf.tgt = tgt;
@@ -484,21 +495,16 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_features(BulkArgs a) {
     __shared__ int red[2][GTX_WAVES];
     int zero = 0, dmax = 0;
     for (int64_t p = gid(); p < a.n; p += (int64_t)gridDim.x * GTX_BLOCK) {
-        int mr = 0, in = 0;
+        int mr = 0;
         if (a.ws.tty[p] >= 0) {
             // Section 4.2 steps 4-5: a transaction's k-set rank is the maximum
             // rank of its operations (reduced over its contiguous op range)
             const int64_t o1 = p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : st->m;
-            for (int64_t o = a.ws.cnt[p]; o < o1; ++o) {
-                const OpInfo inf = a.ws.op_info[o];
-                mr = max(mr, inf.rank);
-                in += inf.in;
-            }
+            for (int64_t o = a.ws.cnt[p]; o < o1; ++o) mr = max(mr, a.ws.op_rank[o]);
             zero += mr == 0;
             dmax = max(dmax, mr);
         }
         a.ws.maxrank[p] = mr;
-        a.ws.indeg[p] = in;
     }
     int z = wave_sum(zero);
     int d = wave_max(dmax);
@@ -593,12 +599,17 @@ hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, 
     const int nbr = (int)blocks_for(a.mcap, kRankTile);
     hipLaunchKernelGGL(k_rank_up, dim3(nbr), dim3(GTX_BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_rank_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, nbr);
-    hipLaunchKernelGGL(k_rank_down, dim3(nbr), dim3(GTX_BLOCK), 0, s, a, nbr);
+    hipLaunchKernelGGL(k_rank_down<false>, dim3(nbr), dim3(GTX_BLOCK), 0, s, a, nbr);
     pm.mark(PH_RANK, s);
     hipLaunchKernelGGL(k_features, dim3(std::min<unsigned>(1024, blocks_for(a.n, GTX_BLOCK))), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_FEATURES, s);
     if (early) e = hipStreamWaitEvent(s, side->join, 0);
     return e;
+}
+
+void launch_rank_full(const BulkArgs& a, hipStream_t s) {
+    const int nbr = (int)blocks_for(a.mcap, kRankTile);
+    hipLaunchKernelGGL(k_rank_down<true>, dim3(nbr), dim3(GTX_BLOCK), 0, s, a, nbr);
 }
 
 }  // namespace gtx

@@ -438,6 +438,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.op_txn = L.take<int32_t>(mcap);
     w.pk[0] = L.take<uint32_t>(mcap); w.pk[1] = L.take<uint32_t>(mcap);
     w.pv[0] = L.take<uint32_t>(mcap); w.pv[1] = L.take<uint32_t>(mcap);
+    w.op_rank = L.take<int32_t>(mcap);
     w.op_info = L.take<OpInfo>(mcap);
     w.srt_txn = L.take<int32_t>(mcap);
     w.grp_cnt = L.take<int32_t>(mcap);
