@@ -9,9 +9,9 @@
 // One pass per digit, one kernel per pass (reduce-free "onesweep" design):
 //  * a histogram kernel counts every pass's digits once up front and turns
 //    them into global exclusive digit offsets (last-block pattern);
-//  * each pass kernel takes a tile of 4096 keys (dynamic tile id, so every
-//    earlier tile is already running), ranks keys within each wave64 by an
-//    8-ballot match on the digit, combines the 4 waves through LDS, publishes
+//  * each pass kernel takes a tile of 8192 32-bit or 4096 64-bit keys (dynamic
+//    tile id, so every earlier tile is already running), ranks keys within each
+//    wave64 by an 8-ballot match on the digit, combines the waves through LDS, publishes
 //    its per-digit count and resolves its global offset by decoupled
 //    look-back over earlier tiles (flag and count share one 32-bit word, so
 //    no fence is needed), then scatters through LDS so that each digit's run
@@ -21,7 +21,13 @@
 namespace gtx {
 
 constexpr int kItems = 16;
-constexpr int kTile = GTX_BLOCK * kItems;
+// Workgroup of a pass: 8 waves for 32-bit keys (8192-key tiles, so half as
+// many tiles walk the look-back chain), 4 for 64-bit keys (LDS for 4096).
+template <class K>
+constexpr int sort_block() { return sizeof(K) == 4 ? 512 : 256; }
+template <class K>
+constexpr int sort_tile() { return sort_block<K>() * kItems; }
+constexpr int kTileMin = 256 * kItems;  // sizes the look-back words for either key width
 constexpr uint32_t kAgg = 1u << 30;
 constexpr uint32_t kPrefix = 2u << 30;
 constexpr uint32_t kCountMask = (1u << 30) - 1u;
@@ -90,8 +96,22 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_hist(const K* keys, const in
     }
 }
 
+// Exclusive sum over the threads of a B-thread workgroup.
+template <int B>
+__device__ __forceinline__ int sort_block_excl_sum(int v, int* lds /* >= B / 64 */) {
+    int inc = wave_incl_sum(v);
+    if (lane_id() == 63) lds[wave_id()] = inc;
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int w = 0; w < B / 64; ++w)
+        if (w < wave_id()) base += lds[w];
+    __syncthreads();
+    return base + inc - v;
+}
+
 template <class K>
-__global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ kin,
+__global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const int64_t* count_dev, int64_t count_cap,
@@ -99,18 +119,21 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
                                                          uint32_t* status, int64_t max_tiles,
                                                          uint32_t* ctrl, const int32_t* gate,
                                                          GtxState* st, uint64_t spin_ticks) {
+    constexpr int B = sort_block<K>();
+    constexpr int kW = B / 64;
+    constexpr int kTile = sort_tile<K>();
     if (sort_gated(gate, st)) return;
     __shared__ uint32_t tile_s;
-    __shared__ uint32_t wcnt[GTX_WAVES][256];
+    __shared__ uint32_t wcnt[kW][256];
     __shared__ uint32_t dstart[256];
     __shared__ int64_t gbase[256];
     __shared__ K skeys[kTile];
     __shared__ uint32_t svals[kTile];
-    __shared__ int scratch[GTX_WAVES + 1];
+    __shared__ int scratch[kW + 1];
 
     const int64_t count = count_dev ? *count_dev : count_cap;
     if (threadIdx.x == 0) tile_s = atomicAdd(&ctrl[pass], 1u);
-    for (int i = threadIdx.x; i < GTX_WAVES * 256; i += GTX_BLOCK) (&wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kW * 256; i += B) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const int64_t tile = tile_s;
     const int64_t base = tile * kTile;
@@ -138,22 +161,27 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
     }
     __syncthreads();
 
-    // per digit: exclusive offsets over waves, block total, block-local start
+    // per digit (threads 0..255): exclusive offsets over waves, block total,
+    // block-local start
     const int d = threadIdx.x;
+    const bool digit = d < 256;
     uint32_t tot = 0;
+    if (digit) {
 #pragma unroll
-    for (int ww = 0; ww < GTX_WAVES; ++ww) {
-        uint32_t c = wcnt[ww][d];
-        wcnt[ww][d] = tot;
-        tot += c;
+        for (int ww = 0; ww < kW; ++ww) {
+            uint32_t c = wcnt[ww][d];
+            wcnt[ww][d] = tot;
+            tot += c;
+        }
     }
-    int total_unused;
-    dstart[d] = (uint32_t)block_excl_sum((int)tot, &total_unused, scratch);
+    const int ds = sort_block_excl_sum<B>(digit ? (int)tot : 0, scratch);
+    if (digit) dstart[d] = (uint32_t)ds;
 
     // decoupled look-back for digit d
     uint32_t* my = status + ((int64_t)pass * max_tiles + tile) * 256 + d;
     uint32_t excl = 0;
-    if (tile == 0) {
+    if (!digit) {
+    } else if (tile == 0) {
         st_relaxed(my, kPrefix | tot);
     } else {
         st_relaxed(my, kAgg | tot);
@@ -199,7 +227,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
         }
         st_relaxed(my, kPrefix | (excl + tot));
     }
-    gbase[d] = (int64_t)hist[pass * 256 + d] + excl - dstart[d];
+    if (digit) gbase[d] = (int64_t)hist[pass * 256 + d] + excl - dstart[d];
     __syncthreads();
 
 #pragma unroll
@@ -214,7 +242,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
     }
     __syncthreads();
     int64_t n_here = count - base < kTile ? count - base : kTile;
-    for (int i = threadIdx.x; i < n_here; i += GTX_BLOCK) {
+    for (int i = threadIdx.x; i < n_here; i += B) {
         K kk = skeys[i];
         int64_t out = gbase[digit_of(kk, pass)] + i;
         kout[out] = kk;
@@ -222,13 +250,13 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_pass(const K* __restrict__ k
     }
 }
 
-int64_t sort_tiles(int64_t cap) { return (cap + kTile - 1) / kTile; }
+int64_t sort_tiles(int64_t cap) { return (cap + kTileMin - 1) / kTileMin; }
 
 size_t sort_status_words(int64_t cap, int npass) { return (size_t)sort_tiles(cap) * 256 * npass; }
 
 template <class K>
 static void sort_impl(const SortPlan& p, hipStream_t s) {
-    int64_t tiles = sort_tiles(p.cap);
+    const int64_t tiles = (p.cap + sort_tile<K>() - 1) / sort_tile<K>();
     if (tiles == 0 || p.npass == 0) return;
     int64_t n_status = tiles * 256 * p.npass;
     int init_blocks = (int)std::min<int64_t>(1024, (n_status + GTX_BLOCK * 16 - 1) / (GTX_BLOCK * 16));
@@ -241,7 +269,7 @@ static void sort_impl(const SortPlan& p, hipStream_t s) {
                        (const K*)p.keys[0], p.count_dev, p.cap, p.npass, p.hist, p.ctrl, p.gate, p.st);
     for (int pass = 0; pass < p.npass; ++pass) {
         int src = pass & 1;
-        hipLaunchKernelGGL(k_sort_pass<K>, dim3((unsigned)tiles), dim3(GTX_BLOCK), 0, s,
+        hipLaunchKernelGGL(k_sort_pass<K>, dim3((unsigned)tiles), dim3(sort_block<K>()), 0, s,
                            (const K*)p.keys[src], (const uint32_t*)p.vals[src], (K*)p.keys[src ^ 1],
                            p.vals[src ^ 1], p.count_dev, p.cap, pass, p.hist, p.status, tiles,
                            p.ctrl, p.gate, p.st, p.spin_ticks);
