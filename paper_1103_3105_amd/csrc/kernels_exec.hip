@@ -603,6 +603,11 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     // ahead of the choice too: the records are workspace, and the appended
     // rows (a function of the signatures alone) are the ones any executor writes
     if (failed(st) || !(a.part_early || st->chosen == GPUTX_PART)) return;
+    // Ahead of the choice it may also run before the execution gate's capacity
+    // check: a bulk whose appends overflow a table writes nothing (the gate
+    // then fails it).
+    for (int k = 0; k < a.n_app; ++k)
+        if (st->app_total[k] > 0 && a.rowcount[k] + st->app_total[k] > a.capacity[k]) return;
     for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * GTX_BLOCK) {
         const int32_t t = a.ws.tty[p];

@@ -289,6 +289,23 @@ def test_unsorted_flagged_sorted_is_error():
     assert ok
 
 
+def test_append_capacity_error_writes_nothing_past_capacity():
+    """An overflowing bulk leaves even the rows past the declared capacity
+    untouched, under every strategy (the columns here are longer than the
+    capacity the table declares, so a stray append would land in them)."""
+    from paper_1103_3105_amd import gputx
+    tabs, types, bulk = util.small_bank(30, 3000)
+    tabs["history"] = wl.Table("history", ["i64"] * 5, [np.zeros(4096, np.int64) for _ in range(5)],
+                               0, 100, append=True)
+    for strategy in STRATS:
+        s, g, o = run_both(tabs, types, bulk, 3, strategy)
+        assert s.error == gputx.E_CAPACITY and o[0] == oracle.E_CAPACITY, strategy
+        for c in g[0]["history"].cols:
+            assert not c.any(), strategy
+        ok, msg = util.tables_equal(tabs, g[0])
+        assert ok, (strategy, msg)
+
+
 def test_append_capacity_error():
     from paper_1103_3105_amd import gputx
     tabs, types, bulk = util.small_bank(29, 3000)
