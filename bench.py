@@ -152,12 +152,12 @@ def phase_bytes(workload: str, n: int, m: int, key_passes: int, committed: int):
         "prepare": n * (32 + 4 + 4 + 8 + 8) + 2 * 2 * 8 * n,
         "emit": n * (32 + 8 + 8) + m * 12,
         "op_sort": m * (4 + 16 * key_passes),
-        "rank": m * 40,
-        "features": n * 8,
+        "rank": m * 12,
+        "features": n * 12 + m * 4,
         "part_gather": committed * sig_app,
         "part": committed * cells_out,
-        "tpl": committed * exec_per_txn,
-        "kset": committed * exec_per_txn,
+        "tpl": committed * exec_per_txn + m * 40,
+        "kset": committed * exec_per_txn + m * 40,
     }
 
 
