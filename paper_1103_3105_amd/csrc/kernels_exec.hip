@@ -11,8 +11,9 @@
 //              target, the transaction runs, every counter is incremented.
 //              Workgroups claim 256-transaction windows in timestamp order
 //              and group each window by type.
-//   k_part_gather PART: every transaction in partition order into records
-//              the partition kernels read contiguously; the appended rows.
+//   k_part_gather PART: every transaction's record (input index, type,
+//              parameters) at its serial position, and its appended rows; in
+//              the one-bulk call it runs ahead of the choice on a second stream.
 //   k_part_pipe PART (Section 5.2), few long partitions: one workgroup per
 //              partition; staging waves put each chunk's cells in an LDS
 //              table while the serial wave runs the previous chunk against

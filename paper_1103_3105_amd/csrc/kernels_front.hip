@@ -8,12 +8,16 @@
 //   scan (3)       exclusive scans of the counts; append capacity check
 //   k_emit         basic operations (item key, op index << 1 | write) in
 //                  serial order; cross-partition count c; PART partition keys
+//   [side stream]  one-bulk calls where PART may run: PART's partition sort,
+//                  heads and records from here on, beside the next three steps
 //   [op sort]      stable radix sort on the item key: Section 4.2 step 1
-//   rank (3)       steps 2-3: group boundaries and per-op rank, plus lock
-//                  targets, successor ranges and in-degrees (three-phase
-//                  segmented scan over the sorted operations)
-//   k_features     steps 4-5 without a second sort: per-transaction max rank by
-//                  atomic max; w0, depth; Algorithm 1 picks the strategy
+//   rank (3)       steps 2-3: group boundaries and per-op rank (three-phase
+//                  segmented scan over the sorted operations); lock targets,
+//                  successor ranges and in-edges come from a second downsweep
+//                  launched with the executors, only when TPL or K-SET runs
+//   k_features     steps 4-5 without a second sort: per-transaction max rank
+//                  over its contiguous op range; w0, depth; Algorithm 1 picks
+//                  the strategy
 #include "engine.h"
 
 namespace gtx {
