@@ -1761,7 +1761,9 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_TPL || a.strategy == GPUTX_PART)
         hipLaunchKernelGGL(k_tpl, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
     pm.mark(PH_TPL, s);
-    if (a.strategy == GPUTX_AUTO || a.strategy == GPUTX_KSET) {
+    // Algorithm 1 picks K-SET only when the 0-set holds at least w0_bar
+    // transactions, which a bulk of fewer cannot reach
+    if (a.strategy == GPUTX_KSET || (a.strategy == GPUTX_AUTO && a.n >= a.w0_bar)) {
         hipLaunchKernelGGL(k_kset_indeg, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset_sorted_txn, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset_succ, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
