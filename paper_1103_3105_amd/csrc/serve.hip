@@ -164,12 +164,16 @@ extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_se
             s.graphs.push_back(gf);
             SERVE_OK(hipGraphInstantiate(&xf, gf, nullptr, nullptr, 0));
             s.front.push_back(xf);
+            // upload now, so that the first bulk of this size class on this
+            // slot does not pay for it in the middle of the trace
+            SERVE_OK(hipGraphUpload(xf, s.fs));
             SERVE_OK(hipStreamBeginCapture(es, hipStreamCaptureModeThreadLocal));
             launch_exec(a, es, none);
             SERVE_OK(hipStreamEndCapture(es, &ge));
             s.graphs.push_back(ge);
             SERVE_OK(hipGraphInstantiate(&xe, ge, nullptr, nullptr, 0));
             s.exec.push_back(xe);
+            SERVE_OK(hipGraphUpload(xe, es));
         }
     }
     SERVE_OK(hipDeviceSynchronize());
