@@ -182,6 +182,7 @@ def bench_batch(args):
     launch) vs plain (one execute + wait per bulk), with Algorithm 1's
     thresholds calibrated on a sample of the bulks first."""
     import torch
+    import oracle
     from paper_1103_3105_amd import autotune, batching, gputx
     log("[bench] generating the 512-bulk batch workload")
     bw = batching.config4(n_bulks=args.bulks)
@@ -208,7 +209,7 @@ def bench_batch(args):
     t0 = time.perf_counter()
     lat = batching.run_plain(eng, jobs, outs)
     plain_s = time.perf_counter() - t0
-    want = batching.oracle_replay(bw, o_tabs)
+    want = oracle.run_sequence(o_tabs, bw.types, batching.sequence(bw))
     parity = all(np.array_equal(outs[k]["status"].cpu().numpy()[:b.n], want[k][0]) and
                  np.array_equal(outs[k]["results"].cpu().numpy()[:b.n], want[k][1])
                  for k, (db, b) in enumerate(bw.jobs))

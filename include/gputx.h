@@ -130,7 +130,12 @@ typedef struct {
     int32_t spin_limit_ms; /* watchdog on every device wait; expiry -> GPUTX_E_DEADLOCK  */
     int32_t grid_blocks;   /* persistent grid size (0: one workgroup per compute unit)  */
     int32_t part_pipeline; /* PART with a staging wave beside the serial one (1, default) */
-    int32_t reserved;      /* 0                                                          */
+    int32_t part_scan;     /* 1 (default): PART runs procedures whose effect on each cell
+                              is a map of that cell alone (debit-credit, payment, order
+                              status, the subscriber reads and field updates) 64 at a
+                              time as a scan of those maps per cell, reported as
+                              "PART-scan" (stats.part_scan); 0: every partition runs its
+                              transactions one after another (Section 5.2 as written)  */
 } gputx_options;
 
 /* One relation.  Columns are device arrays of capacity rows, caller-owned,
@@ -187,7 +192,10 @@ typedef struct {
     int64_t aborted;
     int64_t invalid;
     int64_t appended;   /* rows appended to append-only tables (batched update)   */
-    int64_t reserved[7];
+    int64_t part_scan;  /* PART ran: partition chunks executed in the scan form
+                           (gputx_options.part_scan); 0 = Section 5.2's
+                           one-after-another run throughout                      */
+    int64_t reserved[6];
 } gputx_bulk_stats;
 
 /* Fill *opt with defaults. */

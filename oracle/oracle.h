@@ -51,6 +51,28 @@ int orc_execute(int64_t n, const int32_t* type, const int64_t* params, int32_t n
                 const int64_t* ts, const int32_t* proc_of_type, int32_t n_types,
                 orc_table* tables, int32_t* status, int64_t* results, int32_t width);
 
+/*
+ * The paper's CPU counterpart (Section 6.3): an H-Store-style partitioned
+ * executor.  Each transaction is routed by its partition (part[i] >= 0: all
+ * its rows lie in that partition; -1: it spans several).  Worker w of
+ * n_threads owns the partitions p with p % n_threads == w and runs their
+ * transactions one after another in timestamp order; a transaction that
+ * spans partitions runs alone, after every earlier transaction and before
+ * any later one (all workers wait at a barrier on each side).  Appended rows
+ * take the slots a timestamp-order scan of the append counts gives them, so
+ * the result equals orc_execute's exactly.  Same arguments and return codes
+ * as orc_execute.
+ */
+int orc_execute_partitioned(int64_t n, const int32_t* type, const int64_t* params, int32_t n_params,
+                            const int64_t* ts, const int32_t* proc_of_type, int32_t n_types,
+                            orc_table* tables, const int64_t* part, int32_t n_threads,
+                            int32_t* status, int64_t* results, int32_t width);
+
+/* Pieces of the serial executor the partitioned one reuses (serial.c). */
+int orc_is_valid(int proc, const int64_t* p, const orc_table* R);
+void orc_appends_of(int proc, const int64_t* p, int64_t* h, int64_t* o, int64_t* ol);
+int32_t orc_run_one(int proc, const int64_t* p, int64_t ts, orc_table* R, int64_t* res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -313,6 +313,13 @@ def choose_strategy(w0: int, d: int, c: int, w0_bar: int, c_bar: int, d_bar: int
     return "TPL"
 
 
+def strategy_run(chosen: str, c: int) -> str:
+    """The executor that runs once a strategy is chosen or requested: PART
+    needs every transaction inside one partition, and Section 5.2 hands
+    bulks with cross-partition transactions to TPL."""
+    return "TPL" if chosen == "PART" and c > 0 else chosen
+
+
 # ---------------------------------------------------------------------------
 # serial twin (any order)
 

@@ -60,14 +60,14 @@ static int order_dims(const orc_table* R, orc_odims* d) {
 }
 
 /* Number of rows a valid transaction appends to history / orders / order_line. */
-static void appends_of(int proc, const int64_t* p, int64_t* h, int64_t* o, int64_t* ol) {
+void orc_appends_of(int proc, const int64_t* p, int64_t* h, int64_t* o, int64_t* ol) {
     *h = *o = *ol = 0;
     if (proc == ORC_DEBIT_CREDIT) *h = 1;
     if (proc == ORC_NEW_ORDER) { *o = 1; *ol = p[3]; }
 }
 
 /* Parameter validity (INVALID otherwise). */
-static int is_valid(int proc, const int64_t* p, const orc_table* R) {
+int orc_is_valid(int proc, const int64_t* p, const orc_table* R) {
     orc_odims od = {0, 0, 0, 0};
     switch (proc) {
     case ORC_DEBIT_CREDIT:
@@ -106,7 +106,7 @@ static int is_valid(int proc, const int64_t* p, const orc_table* R) {
 }
 
 /* Run one valid transaction; returns its status, writes its results. */
-static int32_t run_one(int proc, const int64_t* p, int64_t ts, orc_table* R, int64_t* res) {
+int32_t orc_run_one(int proc, const int64_t* p, int64_t ts, orc_table* R, int64_t* res) {
     orc_odims od = {0, 0, 0, 0};
     switch (proc) {
     case ORC_DEBIT_CREDIT: {
@@ -250,10 +250,10 @@ int orc_execute(int64_t n, const int32_t* type, const int64_t* params, int32_t n
         int proc = (t >= 0 && t < n_types) ? proc_of_type[t] : 0;
         memset(p, 0, sizeof(int64_t) * 64);
         for (int32_t k = 0; k < n_params; ++k) p[k] = params[(int64_t)k * n + i];
-        ok[i] = (unsigned char)(proc > 0 && is_valid(proc, p, tables));
+        ok[i] = (unsigned char)(proc > 0 && orc_is_valid(proc, p, tables));
         if (ok[i]) {
             int64_t h, o, ol;
-            appends_of(proc, p, &h, &o, &ol);
+            orc_appends_of(proc, p, &h, &o, &ol);
             need_h += h; need_o += o; need_ol += ol;
         }
     }
@@ -274,7 +274,7 @@ int orc_execute(int64_t n, const int32_t* type, const int64_t* params, int32_t n
         for (int32_t k = 0; k < n_params; ++k) p[k] = params[(int64_t)k * n + i];
         int64_t tmp[64];
         memset(tmp, 0, sizeof(tmp));
-        status[i] = run_one(proc, p, ts[i], tables, tmp);
+        status[i] = orc_run_one(proc, p, ts[i], tables, tmp);
         for (int32_t w = 0; w < width && w < 64; ++w) res[w] = tmp[w];
     }
     free(order); free(p); free(ok);

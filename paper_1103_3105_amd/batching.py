@@ -57,18 +57,9 @@ def config4(n_bulks: int = 512, lo: int = 256, hi: int = 262_144, repeats: int =
                          f"batch-{n_bulks}x[{lo},{hi}]")
 
 
-def oracle_replay(bw: BatchWorkload, tables: Dict[str, wl.Table], times: int = 1):
-    """Serial oracle over the job sequence (``times`` passes); returns the
-    per-job (status, results) of the last pass."""
-    import oracle
-    out = []
-    for _ in range(times):
-        out = []
-        for db, b in bw.jobs:
-            rc, st, res = oracle.run_serial(tables, bw.types, b.type, b.params, b.ts, WIDTH[db])
-            assert rc == 0, rc
-            out.append((st, res))
-    return out
+def sequence(bw: BatchWorkload):
+    """(bulk, result width) of every job in submission order."""
+    return [(b, WIDTH[db]) for db, b in bw.jobs]
 
 
 def device_jobs(eng, bw: BatchWorkload, strategy: int) -> List[dict]:

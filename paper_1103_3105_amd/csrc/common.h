@@ -38,6 +38,7 @@ struct GtxState {
     int64_t narrow_prog;  // K-SET: waves finished in narrow mode (watchdog progress)
     int32_t n_heads;      // PART: non-empty partitions
     int32_t pad;
+    int64_t scan_chunks;  // PART: chunks run in the scan form
 };
 
 namespace gtx {

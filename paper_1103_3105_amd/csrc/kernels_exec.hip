@@ -1104,9 +1104,13 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
     constexpr int NC = proc_cells(P);   // cells it can name
     constexpr bool ahead = P != 0 && NP <= 8 && NC <= 4 && proc_typed_cells(P);
     if constexpr (P != 0 && proc_cellwise(P) && proc_typed_cells(P) && NP <= 8) {
+      if (a.part_scan) {
         for (int k0 = 0; k0 < cnt; k0 += 64) lanes_window<P>(a, c, tab, sw, k0, min(64, cnt - k0));
         if (sw.ws == 0) {  // every cellwise procedure commits; the other result columns are zero
-            if (lane_id() == 0) committed += cnt;
+            if (lane_id() == 0) {
+                committed += cnt;
+                atomicAdd((unsigned long long*)&a.ws.st->scan_chunks, 1ull);
+            }
             constexpr int NR = proc_results(P);
             for (int r = lane_id(); r < cnt; r += 64) {
                 const int64_t i = c.idx[r];
@@ -1115,6 +1119,7 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
             }
         }
         return true;
+      }
     }
     // lane 0 of one serial wave per cell class: classes never share a cell
     if (lane_id() != 0) return false;
@@ -1643,7 +1648,8 @@ __global__ void k_finalize(BulkArgs a) {
     o->aborted = st->aborted;
     o->invalid = st->invalid;
     o->appended = err ? 0 : app;
-    for (int k = 0; k < 7; ++k) o->reserved[k] = 0;
+    o->part_scan = st->scan_chunks;
+    for (int k = 0; k < 6; ++k) o->reserved[k] = 0;
 }
 
 // ---------------------------------------------------------------------------

@@ -56,7 +56,7 @@ extern "C" int gputx_default_options(gputx_options* o) {
     o->spin_limit_ms = 5000;
     o->grid_blocks = 0;
     o->part_pipeline = 1;
-    o->reserved = 0;
+    o->part_scan = 1;
     return GPUTX_OK;
 }
 
@@ -526,6 +526,7 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     a.d_bar = h->opt.d_bar;
     a.kset_narrow = h->opt.kset_narrow;
     a.part_pipeline = h->opt.part_pipeline;
+    a.part_scan = h->opt.part_scan;
     a.grid_blocks = grid_blocks;
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
     // PART cell table: at most half full when every lane of a chunk stages

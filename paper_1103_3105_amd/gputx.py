@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
     _fields_ = [("w0_bar", c_int64), ("c_bar", c_int64), ("d_bar", c_int64),
                 ("part_size", c_int64), ("group_by_type", c_int32), ("kset_narrow", c_int32),
                 ("spin_limit_ms", c_int32), ("grid_blocks", c_int32), ("part_pipeline", c_int32),
-                ("reserved", c_int32)]
+                ("part_scan", c_int32)]
 
 
 class TableDesc(ctypes.Structure):
@@ -62,12 +62,20 @@ class BulkStats(ctypes.Structure):
     _fields_ = [("error", c_int32), ("chosen", c_int32), ("n_ops", c_int64), ("w0", c_int64),
                 ("depth", c_int64), ("cross", c_int64), ("waves", c_int64),
                 ("committed", c_int64), ("aborted", c_int64), ("invalid", c_int64),
-                ("appended", c_int64), ("reserved", c_int64 * 7)]
+                ("appended", c_int64), ("part_scan", c_int64),
+                ("reserved", c_int64 * 6)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in ("error", "chosen", "n_ops", "w0", "depth", "cross",
                                               "waves", "committed", "aborted", "invalid",
-                                              "appended")}
+                                              "appended", "part_scan")}
+
+    @property
+    def label(self) -> str:
+        """Name of the executor that ran: PART's per-cell map scan form is
+        reported as PART-scan, apart from Section 5.2's sequential form."""
+        name = STRATEGY_NAME.get(self.chosen, str(self.chosen))
+        return "PART-scan" if name == "PART" and self.part_scan > 0 else name
 
 
 STATS_BYTES = ctypes.sizeof(BulkStats)

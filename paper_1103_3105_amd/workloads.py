@@ -173,13 +173,25 @@ def bank_tables(rng: np.random.Generator, n_branch: int, n_teller: int, n_accoun
 
 
 def bank_bulk(rng: np.random.Generator, n: int, n_branch: int, n_teller: int, n_account: int,
-              theta: float, ts0: int = 0) -> Bulk:
+              theta: float, ts0: int = 0, remote_frac: float = 0.0) -> Bulk:
     """n debit-credits: acct Zipf(theta), teller and branch of that account,
-    delta uniform in [-99999, 99999], ts = ts0 .. ts0+n-1."""
+    delta uniform in [-99999, 99999], ts = ts0 .. ts0+n-1.
+
+    With ``remote_frac`` > 0 (and more than one branch), that fraction of the
+    transactions goes through a teller drawn uniformly from another branch
+    (TPC-B's remote account holders): their account and their teller/branch
+    rows then lie under different partition roots."""
     apt = n_account // n_teller
     tpb = n_teller // n_branch
     acct = zipf_ids(rng, n_account, theta, n)
     teller = acct // apt
+    if remote_frac > 0 and n_branch > 1:
+        remote = rng.random(n) < remote_frac
+        k = int(remote.sum())
+        home = teller[remote] // tpb
+        other = (home + rng.integers(1, n_branch, k)) % n_branch
+        teller = teller.copy()
+        teller[remote] = other * tpb + rng.integers(0, tpb, k)
     branch = teller // tpb
     delta = rng.integers(-99_999, 100_000, n, dtype=np.int64)
     params = np.stack([acct, teller, branch, delta]).astype(np.int64)

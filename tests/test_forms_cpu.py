@@ -30,7 +30,7 @@ def test_batch_oracle_replay_is_per_database_serial_order():
     bw = batching.config4(n_bulks=12, lo=32, hi=512, repeats=1, bank_branches=2,
                           accounts_per_branch=100, n_wh=1, items_per_w=200, c_per_d=10)
     t1 = util.copy_tables(bw.tables)
-    got = batching.oracle_replay(bw, t1)
+    got = oracle.run_sequence(t1, bw.types, batching.sequence(bw))
     # the same as one serial run per database over the concatenated bulks
     t2 = util.copy_tables(bw.tables)
     for db, width in (("bank", 3), ("order", 16)):

@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from paper_1103_3105_amd import batching
 from tests import util
 
@@ -49,7 +50,7 @@ def test_batch_graph_replays_match_oracle(strategy):
             torch.cuda.synchronize()
             # eager work between replays
             _ = (jobs[0]["dev"]["params"] * 1).sum().item()
-            want = batching.oracle_replay(bw, o_tabs, times=1)
+            want = oracle.run_sequence(o_tabs, bw.types, batching.sequence(bw), times=1)
             for k, (db, b) in enumerate(bw.jobs):
                 s = batch.stats(k)
                 assert s.error == 0, (r, k, s.as_dict())
@@ -79,7 +80,7 @@ def test_plain_form_matches_batched():
         lat = batching.run_plain(eng, jobs, outs)
         assert lat.shape[0] == len(jobs)
         o_tabs = util.copy_tables(bw.tables)
-        want = batching.oracle_replay(bw, o_tabs)
+        want = oracle.run_sequence(o_tabs, bw.types, batching.sequence(bw))
         for k, (db, b) in enumerate(bw.jobs):
             assert np.array_equal(outs[k]["status"].cpu().numpy()[:b.n], want[k][0])
             assert np.array_equal(outs[k]["results"].cpu().numpy()[:b.n], want[k][1])

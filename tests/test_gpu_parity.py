@@ -121,9 +121,10 @@ def test_subscriber_with_aborts(strategy):
     check_features(s, tabs, types, bulk, part_size=16)
 
 
+@pytest.mark.parametrize("scan", [1, 0])
 @pytest.mark.parametrize("pipeline", [0, 1])
 @pytest.mark.parametrize("workload", ["bank", "order", "sub"])
-def test_part_forms(workload, pipeline):
+def test_part_forms(workload, pipeline, scan):
     """Both PART kernels: one wave per partition, and the pipelined pair of
     waves whose LDS cell table persists across chunks (the order and
     subscriber bulks fill it within a few chunks, so it is flushed often)."""
@@ -137,10 +138,17 @@ def test_part_forms(workload, pipeline):
     else:
         tabs, types, bulk = util.small_sub(63, 20_000, n_sub=2000, theta=0.8)
         width, ps = 14, 16
-    _say("part form", workload, pipeline)
-    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline)
+    _say("part form", workload, pipeline, scan)
+    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline,
+                       part_scan=scan)
     assert s.chosen == 2, s.as_dict()
     assert_parity(s, g, o, bulk)
+    # the scan form runs only when enabled, and then for the bank's chunks
+    # (one cellwise procedure throughout)
+    if not scan:
+        assert s.part_scan == 0
+    elif workload == "bank":
+        assert s.part_scan > 0
 
 
 @pytest.mark.parametrize("pipeline", [0, 1])
@@ -166,10 +174,11 @@ def test_part_partition_lengths(pipeline):
     assert_parity(s, g, o, bulk)
 
 
+@pytest.mark.parametrize("scan", [1, 0])
 @pytest.mark.parametrize("pipeline", [0, 1])
 @pytest.mark.parametrize("proc", ["PAYMENT", "ORDER_STATUS", "GET_SUB", "GET_CF",
                                   "UPD_SUB_FIELD", "UPD_LOC"])
-def test_part_cellwise_one_procedure(proc, pipeline):
+def test_part_cellwise_one_procedure(proc, pipeline, scan):
     """Bulks of one cellwise procedure, so PART runs every chunk through the
     window form (a scan over each cell's maps).  Hot keys put many
     transactions on the same cells within a window: warehouse and district
@@ -189,15 +198,19 @@ def test_part_cellwise_one_procedure(proc, pipeline):
         tabs = wl.sub_tables(rng, 300, occupancy=0.5)
         bulk = wl.sub_bulk(rng, n, 300, 0.99, mix=mix)
         types, width, ps = wl.sub_types(), 14, 16
-    _say("part cellwise", proc, pipeline)
-    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline)
+    _say("part cellwise", proc, pipeline, scan)
+    s, g, o = run_both(tabs, types, bulk, width, "PART", part_size=ps, part_pipeline=pipeline,
+                       part_scan=scan)
     assert s.chosen == 2, s.as_dict()
     assert_parity(s, g, o, bulk)
+    if not scan:
+        assert s.part_scan == 0
 
 
+@pytest.mark.parametrize("scan", [1, 0])
 @pytest.mark.parametrize("pipeline", [0, 1])
 @pytest.mark.parametrize("hot", [False, True])
-def test_part_chunk_and_window_edges(pipeline, hot):
+def test_part_chunk_and_window_edges(pipeline, hot, scan):
     """Partitions of 255, 256, 257, 511, 513 and 769 debit-credits: around
     the 256-transaction chunks and 64-transaction windows.  hot: every
     transaction of a partition names the same account, teller and branch, so
@@ -218,8 +231,9 @@ def test_part_chunk_and_window_edges(pipeline, hot):
     delta = rng.integers(-99_999, 100_000, n)
     bulk = wl.Bulk(np.zeros(n, np.int32), np.stack([acct, teller, branch, delta]).astype(np.int64),
                    np.arange(n, dtype=np.int64))
-    _say("part edges", pipeline, hot)
-    s, g, o = run_both(tabs, wl.bank_types(), bulk, 3, "PART", part_pipeline=pipeline)
+    _say("part edges", pipeline, hot, scan)
+    s, g, o = run_both(tabs, wl.bank_types(), bulk, 3, "PART", part_pipeline=pipeline,
+                       part_scan=scan)
     assert s.chosen == 2, s.as_dict()
     assert_parity(s, g, o, bulk)
 
@@ -315,3 +329,69 @@ def test_append_capacity_error():
     assert s.error == gputx.E_CAPACITY and o[0] == oracle.E_CAPACITY
     ok, _ = util.tables_equal(tabs, g[0])
     assert ok
+
+
+# ---------------------------------------------------------------------------
+# cross-partition transactions and Algorithm 1's branches
+
+def _remote_bank(seed, n=20_000, remote_frac=0.05, theta=0.8):
+    rng = np.random.default_rng(seed)
+    tabs = wl.bank_tables(rng, 8, 80, 24_000, history_capacity=n)
+    bulk = wl.bank_bulk(rng, n, 8, 80, 24_000, theta, remote_frac=remote_frac)
+    return tabs, wl.bank_types(), bulk
+
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_cross_partition_bulk(strategy):
+    """A bank bulk where about 5% of debit-credits use a teller of another
+    branch (c > 0).  PART, requested or picked by Algorithm 1, hands the
+    bulk to TPL (Section 5.2); every strategy stays bit-exact, appended
+    history rows included."""
+    tabs, types, bulk = _remote_bank(31)
+    _say("cross-partition bank", strategy)
+    s, g, o = run_both(tabs, types, bulk, 3, strategy, ts_sorted=True)
+    assert_parity(s, g, o, bulk)
+    check_features(s, tabs, types, bulk)
+    assert s.cross > 0
+    want = {"TPL": 1, "PART": 1, "KSET": 3, "AUTO": 1}[strategy]
+    assert s.chosen == want, s.as_dict()
+
+
+def test_cross_partition_hand_built_bulk():
+    """The six-transaction hand-counted case of the oracle pins (c = 2)."""
+    rng = np.random.default_rng(77)
+    tabs = wl.bank_tables(rng, 2, 4, 12, history_capacity=8)
+    p = np.array([[0, 7, 1, 11, 5, 6], [0, 3, 2, 1, 1, 2], [0, 1, 1, 0, 0, 1],
+                  [10, -20, 30, -40, 50, -60]], dtype=np.int64)
+    bulk = wl.Bulk(np.zeros(6, np.int32), p, np.arange(6, dtype=np.int64))
+    for strategy in ("PART", "AUTO"):
+        s, g, o = run_both(tabs, wl.bank_types(), bulk, 3, strategy, ts_sorted=True)
+        assert_parity(s, g, o, bulk)
+        assert (s.cross, s.w0, s.chosen) == (2, 2, 1), s.as_dict()
+
+
+@pytest.mark.parametrize("remote", [0.0, 0.05])
+@pytest.mark.parametrize("bars", [
+    dict(w0_bar=1, c_bar=0, d_bar=1 << 30),            # K-SET: w0 >= w0_bar
+    dict(w0_bar=1 << 40, c_bar=1 << 40, d_bar=1 << 30),  # PART: c <= c_bar
+    dict(w0_bar=1 << 40, c_bar=-1, d_bar=1),           # PART: d >= d_bar
+    dict(w0_bar=1 << 40, c_bar=-1, d_bar=1 << 30),     # TPL
+])
+def test_algorithm1_choice_matches_reference(bars, remote):
+    """Algorithm 1 on the device takes the branch the reference rule takes
+    for the bulk's own (w0, d, c), followed by Section 5.2's PART -> TPL
+    hand-off when c > 0; the chosen executor is bit-exact."""
+    tabs, types, bulk = _remote_bank(32, n=6000, remote_frac=remote)
+    s, g, o = run_both(tabs, types, bulk, 3, "AUTO", ts_sorted=True, **bars)
+    assert_parity(s, g, o, bulk)
+    per = ref.bulk_ops(types, bulk.type, bulk.params, bulk.ts, util.sizes_of(tabs),
+                       util.roots_of(tabs))
+    w0, d, c = ref.features([x for _, _, x in per], util.roots_of(tabs), 1)
+    pick = ref.choose_strategy(w0, d, c, bars["w0_bar"], bars["c_bar"], bars["d_bar"])
+    want = ref.strategy_run(pick, c)
+    assert gputx_name(s.chosen) == want, (s.as_dict(), pick, want)
+
+
+def gputx_name(code):
+    from paper_1103_3105_amd import gputx
+    return gputx.STRATEGY_NAME[code]

@@ -142,6 +142,77 @@ def test_alg1_truth_table():
         assert ref.choose_strategy(w0, d, c, w0_bar=100, c_bar=0, d_bar=10) == want
 
 
+def _cross_bank():
+    """Hand-built bank: 2 branches x 2 tellers x 3 accounts, 6 debit-credits
+    of which two go through a teller of the other branch (hand-counted)."""
+    rng = np.random.default_rng(77)
+    tabs = wl.bank_tables(rng, 2, 4, 12, history_capacity=8)
+    #            acct  teller branch    account's branch   teller's branch
+    rows = [(0, 0, 0),    # 0          0                  local
+            (7, 3, 1),    # 1          1                  local
+            (1, 2, 1),    # 0          1                  cross
+            (11, 1, 0),   # 1          0                  cross
+            (5, 1, 0),    # 0          0                  local
+            (6, 2, 1)]    # 1          1                  local
+    p = np.array([[a for a, _, _ in rows], [t for _, t, _ in rows], [b for _, _, b in rows],
+                  [10, -20, 30, -40, 50, -60]], dtype=np.int64)
+    bulk = wl.Bulk(np.zeros(6, np.int32), p, np.arange(6, dtype=np.int64))
+    return tabs, wl.bank_types(), bulk
+
+
+def test_cross_partition_count_hand_counted():
+    """Appendix D's c: transactions whose items lie under more than one
+    partition root.  Two of the six cross branches; with both branches in
+    one partition none does."""
+    tabs, types, bulk = _cross_bank()
+    per = ref.bulk_ops(types, bulk.type, bulk.params, bulk.ts, util.sizes_of(tabs),
+                       util.roots_of(tabs))
+    txn_ops = [o for _, _, o in per]
+    roots = util.roots_of(tabs)
+    assert [len(ref.partitions_of(o, roots, 1)) for o in txn_ops] == [1, 1, 2, 2, 1, 1]
+    w0, d, c = ref.features(txn_ops, roots, 1)
+    assert c == 2
+    assert ref.features(txn_ops, roots, 2)[2] == 0
+    # hand-counted w0: only t0 and t1 have no earlier conflicting txn (t2
+    # meets t1 on branch 1, t3 meets t0 on branch 0, t4 meets t3 on teller 1,
+    # t5 meets t2 on teller 2)
+    assert w0 == 2
+    # root-key locking: every op becomes its partition root; the cross txns
+    # then name two roots
+    per_r = ref.bulk_ops(wl.bank_types(root_key=True), bulk.type, bulk.params, bulk.ts,
+                         util.sizes_of(tabs), roots)
+    assert [len(o) for _, _, o in per_r] == [1, 1, 2, 2, 1, 1]
+    # serial semantics still hold: final balances are initial + per-row sums
+    t, st, _ = _run(tabs, types, bulk, 3)
+    assert (st == 0).all()
+    for role, col in (("account", 0), ("teller", 1), ("branch", 2)):
+        want = tabs[role].cols[0].copy()
+        np.add.at(want, bulk.params[col], bulk.params[3])
+        assert np.array_equal(t[role].cols[0], want), role
+
+
+def test_cross_partition_bulks_run_under_tpl():
+    """Section 5.2: PART with a cross-partition transaction hands the bulk to
+    TPL; Algorithm 1's own choice is unchanged otherwise."""
+    assert ref.strategy_run("PART", 1) == "TPL"
+    assert ref.strategy_run("PART", 0) == "PART"
+    assert ref.strategy_run("KSET", 5) == "KSET"
+    assert ref.strategy_run("TPL", 5) == "TPL"
+    # Algorithm 1 with c > c_bar but d >= d_bar picks PART, which then runs as TPL
+    assert ref.strategy_run(ref.choose_strategy(3, 50, 2, 100, 0, 10), 2) == "TPL"
+
+
+def test_remote_generator_counts():
+    """The generator's remote fraction yields cross-partition transactions at
+    about that rate, and every remote teller lies in another branch."""
+    rng = np.random.default_rng(5)
+    b = wl.bank_bulk(rng, 20000, 8, 80, 8000, 0.0, remote_frac=0.15)
+    acct_branch = b.params[0] // 1000
+    cross = acct_branch != b.params[2]
+    assert abs(cross.mean() - 0.15) < 0.02
+    assert np.array_equal(b.params[2], b.params[1] // 10)
+
+
 # ---------------------------------------------------------------------------
 # serial semantics: closed forms and invariants
 
