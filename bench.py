@@ -6,9 +6,19 @@ uniform account keys, executed with ``gputx_execute_bulk`` (strategy chosen
 by Algorithm 1 unless ``--strategy`` is given).  A step is one bulk through
 the whole path: timestamp check, validation and scans, basic-operation
 emission, the item-key radix sort, the ranking scan, features and strategy
-choice, the executor and the batched append.  The bulk's arrays are already
-resident in HBM when the timed region starts; the PCIe-inclusive rate (bulk
-H2D + status/results D2H) is reported separately.
+choice, the executor and the batched append.
+
+``value`` is timed with the bulk's arrays already resident in HBM when the
+timed region starts and the results left in HBM.  ``pcie_inclusive_value``
+adds every bulk's host-to-device copy of its signatures and the
+device-to-host copy of its statuses and results (pinned host buffers, three
+streams, copies of one bulk overlapping the execution of another).
+
+Further sections (``--sections``): the strategy grid of the scaled bank
+(every cell checked against the oracle), the tiny bank and the order-entry
+bulk under every strategy (checked too), the measured ceilings (lock
+hand-off latency, contended and random atomics, random gathers at cache- and
+HBM-resident sizes), the batched form and the served form.
 
 Prints one JSON line (see the ``out`` dict at the bottom).
 """
@@ -58,61 +68,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def random_gather_ceiling(device, stream, table_rows: int = 1 << 29, gathers: int = 1 << 26,
-                          reps: int = 3) -> float:
-    """GB/s of gathered bytes for 8-byte loads at uniform random rows of a
-    4 GiB int64 table (a plain library gather): the random-access ceiling the
-    executors' scattered row accesses are measured against."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(1103)
-    tbl = torch.zeros(table_rows, dtype=torch.int64, device=device)
-    idx = torch.randint(0, table_rows, (gathers,), dtype=torch.int64, device=device, generator=g)
-    out = torch.empty(gathers, dtype=torch.int64, device=device)
-    torch.index_select(tbl, 0, idx, out=out)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
-        torch.index_select(tbl, 0, idx, out=out)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del tbl, idx, out
-    return gathers * 8 / (ms / 1e3) / 1e9
+def ceilings(device: int, log=print) -> dict:
+    """Measured ceilings on this device (the library's probes): lock
+    hand-off latency, atomic adds on 1, 64 and 640 addresses and at uniform
+    random addresses, 8-byte random gathers from a 64 MiB table (held by the
+    256 MB Infinity Cache) and from a 4 GiB table."""
+    from paper_1103_3105_amd import gputx
+    out = {}
+    out["handoff_ns_cross_xcd"] = round(gputx.gputx_probe_handoff(device, 20000, False), 1)
+    out["handoff_ns_same_xcd"] = round(gputx.gputx_probe_handoff(device, 20000, True), 1)
+    for k in (1, 64, 640):
+        out[f"atomic_add_per_s_{k}_addr"] = round(gputx.gputx_probe_atomic_add(device, k, 1 << 24))
+    out["atomic_add_per_s_random_2^26_addr"] = round(gputx.gputx_probe_atomic_add(device, 1 << 26, 1 << 26))
+    out["gather_gbs_64MiB"] = round(gputx.gputx_probe_gather(device, 64 << 20, 1 << 26), 1)
+    out["gather_gbs_4GiB"] = round(gputx.gputx_probe_gather(device, 4 << 30, 1 << 26), 1)
+    log("[bench] ceilings: " + ", ".join(f"{k}={v}" for k, v in out.items()))
+    return out
 
 
-def random_atomic_ceiling(device, stream, table_rows: int = 1 << 26, updates: int = 1 << 26,
-                          reps: int = 3) -> float:
-    """Device atomic adds per second at uniform random rows of a 256 MiB int32
-    table (a plain library scatter-add): the ceiling the lock executor's
-    counter increments are measured against."""
-    import torch
-    g = torch.Generator(device=device)
-    g.manual_seed(1105)
-    tbl = torch.zeros(table_rows, dtype=torch.int32, device=device)
-    idx = torch.randint(0, table_rows, (updates,), dtype=torch.int64, device=device, generator=g)
-    one = torch.ones(updates, dtype=torch.int32, device=device)
-    tbl.index_add_(0, idx, one)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    for _ in range(reps):
-        tbl.index_add_(0, idx, one)
-    b.record(stream)
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    total = int(tbl.sum().item())
-    del tbl, idx, one
-    if total != updates * (reps + 1):  # every add landed
-        raise RuntimeError(f"atomic ceiling check: {total} != {updates * (reps + 1)}")
-    return updates / (ms / 1e3)
+def host_cpu() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
 def make_workload(args):
     from paper_1103_3105_amd import workloads as wl
     # append capacity for every bulk this run executes (timed, PCIe, strategy comparison)
-    steps_total = args.warmup + 2 * args.steps + 24
+    steps_total = max(args.warmup, args.steps, 4) + 4   # appends are truncated between phases
     if args.workload == "bank":
         w = wl.config2(n=args.n, theta=args.theta, history_capacity=args.n * steps_total)
         name = (f"debit-credit bank: 64 branches, 640 tellers, 6.4M accounts; one bulk of "
@@ -174,7 +164,202 @@ def oracle_baseline(w, bulk, width, budget_s=12.0):
         committed += int((st == 0).sum())
         reps += 1
     return {"value": committed / elapsed, "unit": "txn/s", "cores": 1, "kind": "oracle",
-            "sample": f"{reps} serial runs of the same {bulk.n}-txn bulk ({elapsed:.1f} s)"}
+            "sample": f"{reps} serial runs of the same {bulk.n}-txn bulk ({elapsed:.1f} s)",
+            "host": host_cpu()}
+
+
+def partitioned_baseline(w, bulk, width, part_size, budget_s=6.0):
+    """The paper's CPU counterpart (Section 6.3): H-Store-style workers, one
+    per group of partitions, on the host's cores (at most 16), routing
+    included in the time; its first run is checked against the serial
+    oracle."""
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    ref_tabs = w.copy_tables()
+    rc, o_st, o_res = oracle.run_serial(ref_tabs, w.types, bulk.type, bulk.params, bulk.ts, width)
+    assert rc == 0
+    reps, elapsed, committed, parity = 0, 0.0, 0, None
+    while elapsed < budget_s and reps < 500:
+        tabs = w.copy_tables()
+        t0 = time.perf_counter()
+        part = oracle.partition_ids(tabs, w.types, bulk.type, bulk.params, part_size)
+        rc, st, res = oracle.run_partitioned(tabs, w.types, bulk.type, bulk.params, bulk.ts, width,
+                                             part, threads)
+        elapsed += time.perf_counter() - t0
+        assert rc == 0
+        if parity is None:
+            parity = bool(np.array_equal(st, o_st) and np.array_equal(res, o_res) and all(
+                np.array_equal(a[:tabs[k].n_rows], b[:tabs[k].n_rows])
+                for k in tabs for a, b in zip(tabs[k].cols, ref_tabs[k].cols)))
+        committed += int((st == 0).sum())
+        reps += 1
+    return {"value": committed / elapsed, "unit": "txn/s", "cores": threads,
+            "kind": "partitioned CPU counterpart (H-Store style, Section 6.3)",
+            "sample": f"{reps} runs of the same {bulk.n}-txn bulk ({elapsed:.1f} s)",
+            "parity_vs_oracle": parity, "host": host_cpu()}
+
+
+class DeviceSnapshot:
+    """A device copy of an engine's non-append tables, restored (with the
+    append tables emptied) between runs that must start from the same
+    database."""
+
+    def __init__(self, eng):
+        self.eng = eng
+        self.cols = {k: [c.clone() for c in v] for k, v in eng.cols.items()
+                     if not eng.append_tables[k]}
+
+    def restore(self):
+        for k, cols in self.cols.items():
+            for d, s in zip(self.eng.cols[k], cols):
+                d.copy_(s)
+        self.eng.truncate_appends()
+
+
+def device_parity(eng, want, status, results, n) -> bool:
+    """Statuses, results, every non-append table and the appended rows of
+    one bulk run from the snapshot's tables, against the oracle's."""
+    o_tabs, o_st, o_res = want
+    ok = (np.array_equal(status[:n].cpu().numpy(), o_st) and
+          np.array_equal(results[:n].cpu().numpy(), o_res))
+    for name, t in o_tabs.items():
+        if not ok:
+            break
+        host = eng.table_host(name)
+        rows = t.n_rows
+        if t.append:
+            ok = eng.row_count(name) == rows
+        ok = ok and all(np.array_equal(h[:rows], c[:rows]) for h, c in zip(host, t.cols))
+    return bool(ok)
+
+
+def run_strategies(w, bulk, width, strategies, part_size=1, engine_opts=None, label=""):
+    """Every requested strategy on the same bulk from the same tables: one
+    untimed run, then one timed run whose outputs and tables are compared
+    with the oracle.  Returns one dict per strategy."""
+    import torch
+    import oracle
+    from paper_1103_3105_amd import gputx
+    o_tabs = w.copy_tables()
+    rc, o_st, o_res = oracle.run_serial(o_tabs, w.types, bulk.type, bulk.params, bulk.ts, width)
+    assert rc == 0
+    want = (o_tabs, o_st, o_res)
+    eng = gputx.Engine(w.tables, w.types, part_size=part_size, **(engine_opts or {}))
+    out = {}
+    try:
+        snap = DeviceSnapshot(eng)
+        dev = eng.bulk_to_device(bulk)
+        st = torch.empty(max(bulk.n, 1), dtype=torch.int32, device=eng.device)
+        res = torch.empty((max(bulk.n, 1), width), dtype=torch.int64, device=eng.device)
+        stats = torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device)
+        for name, strat, opts in strategies:
+            if opts:
+                eng.set_options(**opts)
+            snap.restore()
+            eng.execute(dev, gputx.STRATEGY[strat], width, ts_sorted=True, status=st, results=res, stats=stats)
+            torch.cuda.synchronize()
+            snap.restore()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            eng.execute(dev, gputx.STRATEGY[strat], width, ts_sorted=True, status=st, results=res, stats=stats)
+            b.record()
+            torch.cuda.synchronize()
+            s = gputx.stats_from(stats)
+            ms = a.elapsed_time(b)
+            par = s.error == 0 and device_parity(eng, want, st, res, bulk.n)
+            out[name] = dict(ms=round(ms, 3), txn_per_s=round(s.committed / (ms / 1e3)), ran=s.label,
+                             error=int(s.error), parity=bool(par), depth=int(s.depth), w0=int(s.w0),
+                             waves=int(s.waves), n_ops=int(s.n_ops))
+            if opts:   # back to the defaults for the next strategy
+                eng.set_options(**{k: getattr(gputx.gputx_default_options(), k) for k in opts})
+        log(f"[bench] {label}: " + ", ".join(f"{k}={v['ms']:.3f}ms({v['ran']}, parity={v['parity']})"
+                                            for k, v in out.items()))
+    finally:
+        eng.close()
+    return out
+
+
+# the executors compared on one bulk: PART in both forms (Section 5.2's
+# one-after-another run, and the per-cell map scan where it applies)
+STRATEGY_SET = [("TPL", "TPL", None), ("PART", "PART", {"part_scan": 0}),
+                ("PART-scan", "PART", {"part_scan": 1}), ("KSET", "KSET", None),
+                ("AUTO", "AUTO", None)]
+
+
+def bench_grid(args):
+    """TPL, PART, PART-scan and K-SET on the same scaled-bank bulks
+    (n x theta), each cell checked against the oracle."""
+    from paper_1103_3105_amd import workloads as wl
+    rows = []
+    for theta in (0.0, 0.8, 0.99):
+        for n in args.grid_n:
+            w = wl.config2(n=n, theta=theta, history_capacity=n)
+            r = run_strategies(w, w.bulks[0], 3, STRATEGY_SET[:4], label=f"grid n={n} theta={theta}")
+            rows.append(dict(n=n, theta=theta, **r))
+    return rows
+
+
+def bench_configs(args):
+    """The tiny bank (one 4096-transaction chain) and the order-entry bulk
+    (16 warehouses, 2^18 transactions) under every strategy, checked."""
+    from paper_1103_3105_amd import workloads as wl
+    out = {}
+    w1 = wl.config1()
+    out["tiny_bank_4096"] = dict(workload="1 branch, 10 tellers, 1000 accounts; 4096 debit-credits",
+                                 **run_strategies(w1, w1.bulks[0], 3, STRATEGY_SET, label="tiny bank"))
+    w3 = wl.config3(n=args.order_n)
+    out["order_entry"] = dict(workload=f"16 warehouses x 10 districts x 3000 customers, 100k items; "
+                                       f"{args.order_n} txns, mix 45/43/12",
+                              **run_strategies(w3, w3.bulks[0], 16, STRATEGY_SET, label="order entry"))
+    return out
+
+
+def pcie_inclusive(eng, dev, status, results, width, step, reps):
+    """Transactions per second with every bulk's signatures copied in from
+    pinned host memory and its statuses and results copied back: one stream
+    per direction beside the execution stream, two buffer sets, so the
+    copies of one bulk overlap the execution of another."""
+    import torch
+    from paper_1103_3105_amd import gputx
+    n = dev["type"].shape[0]
+    comp = torch.cuda.current_stream()
+    h2d, d2h = torch.cuda.Stream(), torch.cuda.Stream()
+    pin = [{k: v.cpu().pin_memory() for k, v in dev.items()} for _ in range(2)]
+    devs = [dev, {k: torch.empty_like(v) for k, v in dev.items()}]
+    outs = [(status, results), (torch.empty_like(status), torch.empty_like(results))]
+    host = [(torch.empty(status.shape, dtype=status.dtype).pin_memory(),
+             torch.empty(results.shape, dtype=results.dtype).pin_memory()) for _ in range(2)]
+    ev = lambda: torch.cuda.Event()
+    in_ready, exec_done, out_done = [ev(), ev()], [ev(), ev()], [ev(), ev()]
+    stats = torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device)
+    committed = 0
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(comp)
+    for k in range(reps):
+        b = k & 1
+        with torch.cuda.stream(h2d):
+            if k >= 2:
+                h2d.wait_event(exec_done[b])     # the bulk that used these inputs has run
+            for key in devs[b]:
+                devs[b][key].copy_(pin[b][key], non_blocking=True)
+            in_ready[b].record(h2d)
+        comp.wait_event(in_ready[b])
+        if k >= 2:
+            comp.wait_event(out_done[b])         # its outputs have been copied out
+        step(devs[b], outs[b][0], outs[b][1], stats)
+        exec_done[b].record(comp)
+        with torch.cuda.stream(d2h):
+            d2h.wait_event(exec_done[b])
+            host[b][0].copy_(outs[b][0], non_blocking=True)
+            host[b][1].copy_(outs[b][1], non_blocking=True)
+            out_done[b].record(d2h)
+    comp.wait_stream(d2h)
+    t1.record(comp)
+    torch.cuda.synchronize()
+    committed = gputx.stats_from(stats).committed * reps
+    return committed / (t0.elapsed_time(t1) / 1e3), host[(reps - 1) & 1]
 
 
 def bench_batch(args):
@@ -297,41 +482,6 @@ def bench_serve(args):
                             for k, v in tuned.items() if k != "samples"})
 
 
-def bench_grid(args):
-    """TPL, PART and K-SET on the same scaled-bank bulks (n x theta)."""
-    import torch
-    from paper_1103_3105_amd import gputx, workloads as wl
-    out = []
-    for theta in (0.0, 0.8, 0.99):
-        for n in args.grid_n:
-            w = wl.config2(n=n, theta=theta, history_capacity=n)
-            eng = gputx.Engine(w.tables, w.types)
-            dev = eng.bulk_to_device(w.bulks[0])
-            row = dict(n=n, theta=theta)
-            for strat in ("TPL", "PART", "KSET"):
-                eng.truncate_appends()
-                st, res, stats = eng.execute(dev, gputx.STRATEGY[strat], 3, ts_sorted=True)
-                torch.cuda.synchronize()
-                eng.truncate_appends()
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                eng.execute(dev, gputx.STRATEGY[strat], 3, ts_sorted=True, status=st, results=res, stats=stats)
-                b.record()
-                torch.cuda.synchronize()
-                s = gputx.stats_from(stats)
-                ms = a.elapsed_time(b)
-                row[strat] = dict(ms=round(ms, 3), txn_per_s=round(s.committed / (ms / 1e3)))
-                if strat == "TPL":  # one device atomic add per operation (its lock group's counter)
-                    row[strat]["atomics"] = int(s.n_ops)
-                    row[strat]["atomics_per_s"] = round(s.n_ops / (ms / 1e3))
-                row["depth"], row["w0"] = int(s.depth), int(s.w0)
-            log(f"[bench] grid n={n} theta={theta}: " + ", ".join(
-                f"{k}={row[k]['ms']:.2f}ms" for k in ("TPL", "PART", "KSET")))
-            out.append(row)
-            eng.close()
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,16 +492,20 @@ def main():
     ap.add_argument("--n-sub", type=int, default=10_000_000)
     ap.add_argument("--theta", type=float, default=0.0)
     ap.add_argument("--strategy", default="AUTO", choices=["AUTO", "TPL", "PART", "KSET"])
-    ap.add_argument("--compare", action="store_true", help="also time every strategy")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--part-scan", type=int, default=1, choices=[0, 1],
+                    help="PART's per-cell map scan for cellwise procedures (1) or Section 5.2's "
+                         "one-after-another run throughout (0)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
     ap.add_argument("--part-pipeline", type=int, default=1, choices=[0, 1],
                     help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
-    ap.add_argument("--sections", default="grid,batch,serve",
-                    help="extra sections after the headline bulk: grid,batch,serve (or none)")
+    ap.add_argument("--sections", default="grid,configs,ceilings,batch,serve",
+                    help="extra sections after the headline bulk: grid,configs,ceilings,batch,serve "
+                         "(or none)")
     ap.add_argument("--grid-n", type=lambda v: [int(x) for x in v.split(",")],
                     default=[1 << 16, 1 << 18, 1 << 20])
+    ap.add_argument("--order-n", type=int, default=1 << 18)
     ap.add_argument("--serve-points", type=lambda v: [(float(p.split(':')[0]), float(p.split(':')[1]))
                                                       for p in v.split(",")],
                     default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 200.0)],
@@ -376,8 +530,9 @@ def main():
     log(f"[bench] generating {args.workload} n={args.n}")
     w, wname, width = make_workload(args)
     bulk = w.bulks[0]
-    eng = gputx.Engine(w.tables, w.types, part_size=(128 if args.workload == "sub" else 1),
-                       part_pipeline=args.part_pipeline)
+    part_size = 128 if args.workload == "sub" else 1
+    eng = gputx.Engine(w.tables, w.types, part_size=part_size, part_pipeline=args.part_pipeline,
+                       part_scan=args.part_scan)
     dev = eng.bulk_to_device(bulk)
     n = bulk.n
     status = torch.empty(n, dtype=torch.int32, device=eng.device)
@@ -385,34 +540,24 @@ def main():
     stats = torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device)
     stream = torch.cuda.current_stream()
 
-    def step(strategy):
-        eng.execute(dev, gputx.STRATEGY[strategy], width, ts_sorted=True, status=status,
-                    results=results, stats=stats, stream=stream)
+    def step(strategy, d=dev, st=status, res=results, sts=stats):
+        eng.execute(d, gputx.STRATEGY[strategy], width, ts_sorted=True, status=st, results=res,
+                    stats=sts, stream=stream)
 
-    # parity on the first warm-up bulk (outside timing)
+    # parity on the first bulk (outside timing)
     log("[bench] parity check vs oracle on the first bulk")
     step(args.strategy)
     torch.cuda.synchronize()
     s0 = gputx.stats_from(stats)
     o_tabs = w.copy_tables()
     rc, o_st, o_res = oracle.run_serial(o_tabs, w.types, bulk.type, bulk.params, bulk.ts, width)
-    parity = (rc == 0 and s0.error == 0 and np.array_equal(status.cpu().numpy(), o_st)
-              and np.array_equal(results.cpu().numpy(), o_res))
-    for name, t in o_tabs.items():
-        if t.append:
-            continue
-        host = eng.table_host(name)
-        parity = parity and all(np.array_equal(h, c) for h, c in zip(host, t.cols))
-    log(f"[bench] parity={parity} stats={s0.as_dict()}")
+    parity = rc == 0 and s0.error == 0 and device_parity(eng, (o_tabs, o_st, o_res), status, results, n)
+    log(f"[bench] parity={parity} ran={s0.label} stats={s0.as_dict()}")
 
+    eng.truncate_appends()
     for _ in range(max(args.warmup - 1, 0)):
         step(args.strategy)
     torch.cuda.synchronize()
-
-    # random-access ceiling (outside timing): 8-byte gathers at uniform random
-    # rows of a 4 GiB table, far larger than the caches
-    gather_gbs = random_gather_ceiling(eng.device, stream)
-    log(f"[bench] random 8-byte gather ceiling: {gather_gbs:.1f} GB/s of gathered bytes")
 
     # a plain copy of known size (outside timing): PMC byte counters of the
     # profiled runs are scaled by what they read for it
@@ -422,6 +567,7 @@ def main():
     torch.cuda.synchronize()
     del calib_src, calib_dst
 
+    eng.truncate_appends()
     gputx.gputx_phase_timing(eng.h, True)
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
@@ -440,7 +586,7 @@ def main():
     committed = s.committed
     value = committed * args.steps / (total_ms / 1e3)
     log(f"[bench] {args.steps} steps {total_ms:.2f} ms (wall {wall*1e3:.1f} ms) "
-        f"strategy={gputx.STRATEGY_NAME[s.chosen]} waves={s.waves} depth={s.depth} w0={s.w0}")
+        f"ran={s.label} waves={s.waves} depth={s.depth} w0={s.w0}")
     log("[bench] phases (ms/bulk): " + ", ".join(f"{k}={v / max(nb, 1):.3f}" for k, v in phases.items()))
 
     # roofline of the dominant phase (kernel group)
@@ -455,53 +601,47 @@ def main():
                  "op_sort": "k_sort_pass", "prepare": "k_prepare", "emit": "k_emit"}
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 6),
-                "traffic": measured_traffic(kernel_of.get(dom, dom)), "kernel": dom,
-                "bytes_per_launch": pb[dom], "ms_per_launch": round(dom_ms, 4),
-                "random_gather_ceiling": round(gather_gbs, 1),
-                "frac_of_random_gather": round(achieved / gather_gbs, 6) if gather_gbs > 0 else None}
+                "traffic": measured_traffic(kernel_of.get(dom, dom)), "kernel": kernel_of.get(dom, dom),
+                "phase": dom, "bytes_per_launch": pb[dom], "ms_per_launch": round(dom_ms, 4)}
 
-    # PCIe-inclusive rate: bulk H2D + status/results D2H around each bulk
-    pin = {k: torch.empty_like(v, device="cpu").pin_memory() for k, v in dev.items()}
-    for k in pin:
-        pin[k].copy_(dev[k])
-    st_h = torch.empty_like(status, device="cpu").pin_memory()
-    res_h = torch.empty_like(results, device="cpu").pin_memory()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    reps = max(2, args.steps // 2)
-    for _ in range(reps):
-        for k in dev:
-            dev[k].copy_(pin[k], non_blocking=True)
-        step(args.strategy)
-        st_h.copy_(status, non_blocking=True)
-        res_h.copy_(results, non_blocking=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    pcie_value = committed * reps / (e0.elapsed_time(e1) / 1e3)
+    # transfer-inclusive rate: every bulk's signatures in, statuses and results out
+    eng.truncate_appends()
+    reps = max(4, args.steps)
+    pcie_value, (h_st, h_res) = pcie_inclusive(
+        eng, dev, status, results, width,
+        lambda d, st, res, sts: step(args.strategy, d, st, res, sts), reps)
+    log(f"[bench] PCIe-inclusive (pipelined copies): {pcie_value / 1e6:.1f}M txn/s")
 
-    extra = {}
-    if args.compare:
-        for strat in ("TPL", "PART", "KSET"):
-            step(strat)
+    # Section 5.2's PART (one after another) beside the scan form, same bulk
+    part_forms = None
+    if args.workload == "bank":
+        part_forms = {}
+        for scan in (0, 1):
+            eng.set_options(part_scan=scan)
+            eng.truncate_appends()
+            step("PART")
             torch.cuda.synchronize()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record(stream)
-            reps = 3
-            for _ in range(reps):
-                step(strat)
+            for _ in range(3):
+                step("PART")
             b.record(stream)
             torch.cuda.synchronize()
             sx = gputx.stats_from(stats)
-            ms = a.elapsed_time(b) / reps
-            extra[strat] = {"ms_per_bulk": round(ms, 3), "txn_per_s": round(sx.committed / (ms / 1e3)),
-                            "error": sx.error}
-            log(f"[bench] {strat}: {ms:.3f} ms/bulk")
+            ms = a.elapsed_time(b) / 3
+            part_forms[sx.label] = {"ms_per_bulk": round(ms, 3),
+                                    "txn_per_s": round(sx.committed / (ms / 1e3)), "error": int(sx.error)}
+        eng.set_options(part_scan=args.part_scan)
+        log(f"[bench] PART forms: {part_forms}")
 
-    cpu = None
+    cpu = cpu_part = None
     if not args.no_cpu:
-        log("[bench] timing the serial oracle on the host")
+        log("[bench] timing the serial oracle and the partitioned counterpart on the host")
         cpu = oracle_baseline(w, bulk, width)
+        cpu_part = partitioned_baseline(w, bulk, width, part_size)
+        log(f"[bench] CPU: oracle {cpu['value'] / 1e6:.2f}M txn/s (1 core), partitioned "
+            f"{cpu_part['value'] / 1e6:.2f}M txn/s ({cpu_part['cores']} threads, "
+            f"parity={cpu_part['parity_vs_oracle']})")
 
     out = {
         "metric": METRIC,
@@ -517,8 +657,8 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": wname, "form": "plain (one bulk per launch sequence)",
-                   "bulk_txns": n, "strategy": gputx.STRATEGY_NAME[s.chosen],
-                   "requested": args.strategy},
+                   "bulk_txns": n, "strategy": s.label, "requested": args.strategy,
+                   "timed": "bulk resident in HBM, results left in HBM; see pcie_inclusive_value"},
         "latency_ms": {"p50": round(float(np.percentile(per_step, 50)), 4),
                        "p99": round(float(np.percentile(per_step, 99)), 4)},
         "pcie_inclusive_value": round(pcie_value, 1),
@@ -527,24 +667,47 @@ def main():
         "phases_ms_per_bulk": {k: round(v / max(nb, 1), 4) for k, v in phases.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_partitioned": cpu_part,
     }
-    if extra:
-        out["strategies"] = extra
+    if part_forms:
+        out["part_forms"] = part_forms
     eng.close()
     del eng, dev, status, results
     torch.cuda.empty_cache()
+    if "ceilings" in sections:
+        c = ceilings(0, log)
+        out["ceilings"] = c
+        roofline["frac_of_gather_64MiB"] = round(achieved / c["gather_gbs_64MiB"], 6)
+        roofline["frac_of_gather_4GiB"] = round(achieved / c["gather_gbs_4GiB"], 6)
     if "grid" in sections:
         out["strategy_grid"] = bench_grid(args)
-        # the lock executor's counter increments against a random-atomic ceiling
-        ceil = random_atomic_ceiling(torch.device("cuda", 0), torch.cuda.current_stream())
-        log(f"[bench] random 4-byte atomic-add ceiling: {ceil / 1e9:.2f} G/s")
-        at = [r for r in out["strategy_grid"] if r["n"] == args.n and r["theta"] == args.theta]
-        if at:
-            t = at[0]["TPL"]
+        out["grid_parity"] = all(v["parity"] for r in out["strategy_grid"] for k, v in r.items()
+                                 if isinstance(v, dict))
+    if "configs" in sections:
+        out["configs"] = bench_configs(args)
+    if "ceilings" in sections and "grid" in sections:
+        # critical-path bound: every strategy must respect the longest chain
+        # of conflicting transactions, one lock hand-off per step for TPL and
+        # K-SET; the K-SET run gives the chain's length (waves = depth + 1)
+        hop = out["ceilings"]["handoff_ns_cross_xcd"]
+        bounds = []
+        for r in out["strategy_grid"]:
+            waves = r["KSET"]["waves"]
+            bound_ms = waves * hop / 1e6
+            bounds.append(dict(n=r["n"], theta=r["theta"], chain=waves, bound_ms=round(bound_ms, 3),
+                               TPL_ms=r["TPL"]["ms"], KSET_ms=r["KSET"]["ms"],
+                               TPL_x_bound=round(r["TPL"]["ms"] / bound_ms, 2) if bound_ms else None,
+                               KSET_x_bound=round(r["KSET"]["ms"] / bound_ms, 2) if bound_ms else None))
+        out["critical_path"] = {"handoff_ns": hop, "per_bulk": bounds}
+        tpl = [r for r in out["strategy_grid"] if r["n"] == args.n and r["theta"] == args.theta]
+        if tpl:
+            t = tpl[0]["TPL"]
+            per_s = t["n_ops"] / (t["ms"] / 1e3)
             out["atomics"] = {"kernel": "k_tpl", "workload": f"same bank bulk under TPL (n={args.n}, "
-                              f"theta={args.theta})", "per_bulk": t["atomics"], "ms": t["ms"],
-                              "per_s": t["atomics_per_s"], "random_atomic_ceiling_per_s": round(ceil),
-                              "frac_of_random_atomic": round(t["atomics_per_s"] / ceil, 6)}
+                              f"theta={args.theta})", "per_bulk": t["n_ops"], "ms": t["ms"],
+                              "per_s": round(per_s),
+                              "frac_of_random_atomic": round(per_s / out["ceilings"]["atomic_add_per_s_random_2^26_addr"], 6),
+                              "frac_of_64_addr": round(per_s / out["ceilings"]["atomic_add_per_s_64_addr"], 6)}
     if "batch" in sections:
         out["batched_vs_plain"] = bench_batch(args)
     if "serve" in sections:

@@ -363,6 +363,30 @@ const char* gputx_phase_name(int i);
  * synchronised.  Errors: GPUTX_E_ARG for a table that is not append-only. */
 int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, gputx_stream_t stream);
 
+/* ---- measurement probes ------------------------------------------------
+ * The ceilings the executors are measured against, taken on the device at
+ * hand (Appendix D calibrates Algorithm 1 on the machine it runs on).  Each
+ * call allocates and frees its own device memory, synchronises the device
+ * and checks its own result (GPUTX_E_INTERNAL if the check fails).  Errors
+ * are reported through gputx_last_error(NULL).
+ *
+ * gputx_probe_handoff: mean latency of one lock hand-off between two
+ *   workgroups (another XCD, or the same one when same_xcd != 0), each turn
+ *   being the lock executor's own sequence: spin on a counter, acquire
+ *   fence, read-modify-write of a cell, release fence, atomic add.  A chain
+ *   of dependent transactions costs at least this per step, so
+ *   (depth + 1) x ns_per_hop bounds TPL and K-SET from below.
+ *   hops in [2, 2^24]; GPUTX_E_DEADLOCK if a turn waits more than 2 s.
+ * gputx_probe_atomic_add: 32-bit device atomic adds per second over n_addr
+ *   addresses (1, 64, 640: contended lock counters; large: uniform random),
+ *   n_updates >= 2^18 in total.
+ * gputx_probe_gather: gathered bytes per second (1e9) of 8-byte loads at
+ *   uniform random rows of a table_bytes table (a power of two >= 4096):
+ *   64 MiB stays in the Infinity Cache, 4 GiB does not.  n_gathers >= 2^18. */
+int gputx_probe_handoff(int hip_device, int32_t hops, int32_t same_xcd, double* ns_per_hop);
+int gputx_probe_atomic_add(int hip_device, int64_t n_addr, int64_t n_updates, double* updates_per_s);
+int gputx_probe_gather(int hip_device, int64_t table_bytes, int64_t n_gathers, double* gb_per_s);
+
 /* Message of the last error on this context (static storage, never NULL). */
 const char* gputx_last_error(gputx_handle h);
 

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgputx.so")
-SOURCES = ["runtime.hip", "serve.hip", "kernels_front.hip", "kernels_exec.hip", "sort.hip"]
+SOURCES = ["runtime.hip", "serve.hip", "kernels_front.hip", "kernels_exec.hip", "sort.hip",
+           "probes.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed fp32 instructions stay off: some of their forms have produced

@@ -137,6 +137,9 @@ def _load() -> ctypes.CDLL:
         "gputx_batch_destroy": (c_int32, [H]),
         "gputx_serve": (c_int32, [H, POINTER(Trace), POINTER(ServeOpts), c_void_p, c_void_p,
                                   POINTER(ServeBulk), c_int64, POINTER(ServeReport)]),
+        "gputx_probe_handoff": (c_int32, [c_int32, c_int32, c_int32, POINTER(ctypes.c_double)]),
+        "gputx_probe_atomic_add": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
+        "gputx_probe_gather": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -151,7 +154,8 @@ EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_
            "gputx_workspace_size_ops",
            "gputx_execute_bulk", "gputx_row_count", "gputx_set_row_count", "gputx_last_error", "gputx_phase_timing",
            "gputx_phase_times", "gputx_phase_name", "gputx_batch_create", "gputx_batch_launch",
-           "gputx_batch_destroy", "gputx_serve")
+           "gputx_batch_destroy", "gputx_serve", "gputx_probe_handoff", "gputx_probe_atomic_add",
+           "gputx_probe_gather")
 
 
 class GputxError(RuntimeError):
@@ -274,6 +278,27 @@ def gputx_serve(h, trace: Trace, opts: ServeOpts, status: torch.Tensor, results:
     n = min(rep.n_bulks, bulk_capacity)
     arr = np.ctypeslib.as_array(recs)[:n].copy() if n else np.zeros(0)
     return rep, arr
+
+
+def gputx_probe_handoff(device: int, hops: int, same_xcd: bool = False) -> float:
+    """ns per lock hand-off between two workgroups (see the header)."""
+    v = ctypes.c_double()
+    _check(None, lib.gputx_probe_handoff(device, hops, 1 if same_xcd else 0, ctypes.byref(v)))
+    return v.value
+
+
+def gputx_probe_atomic_add(device: int, n_addr: int, n_updates: int) -> float:
+    """Device atomic adds per second over n_addr addresses."""
+    v = ctypes.c_double()
+    _check(None, lib.gputx_probe_atomic_add(device, n_addr, n_updates, ctypes.byref(v)))
+    return v.value
+
+
+def gputx_probe_gather(device: int, table_bytes: int, n_gathers: int) -> float:
+    """GB/s of 8-byte gathers at uniform random rows of a table_bytes table."""
+    v = ctypes.c_double()
+    _check(None, lib.gputx_probe_gather(device, table_bytes, n_gathers, ctypes.byref(v)))
+    return v.value
 
 
 def stats_from(t: torch.Tensor) -> BulkStats:
