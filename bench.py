@@ -315,6 +315,83 @@ def bench_configs(args):
     return out
 
 
+def bench_micro(args):
+    """Branch-divergence micro benchmark (Figures 3 and 12): n independent
+    transactions of T types, 100 x mixing rounds each, run in input order
+    (basic) and grouped by type into p groups (stable 1-bit radix passes on
+    the top log2 p bits), with p calibrated on a sample bulk; sampled
+    tuples are checked against the oracle."""
+    import torch
+    from oracle import micro
+    from paper_1103_3105_amd import gputx
+    n = args.micro_n
+    rng = np.random.default_rng(1103_012)
+    tup0 = rng.integers(-2**62, 2**62, n, dtype=np.int64)
+    dv = torch.empty(n, dtype=torch.int64, device="cuda")
+    ws = torch.empty(gputx.gputx_micro_workspace_size(n), dtype=torch.uint8, device="cuda")
+    sample = rng.choice(n, 512, replace=False)
+
+    def timed(dt, T, x, groups, phase):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        gputx.gputx_micro_run(dt, dv, T, x, groups, ws, phase=phase)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    def timed_total(dt, m, T, x, groups):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        gputx.gputx_micro_run(dt, dv[:m], T, x, groups, ws)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    def run(t_np, T, x, groups):
+        """(grouping ms, execution ms, parity on the sample) of one bulk."""
+        dt = torch.from_numpy(t_np).cuda()
+        dv.copy_(torch.from_numpy(tup0))
+        gputx.gputx_micro_run(dt, dv, T, x, groups, ws)          # warm-up (applies once)
+        dv.copy_(torch.from_numpy(tup0))
+        g_ms = timed(dt, T, x, groups, 1) if groups > 1 else 0.0
+        e_ms = timed(dt, T, x, groups, 2)
+        got = dv.cpu().numpy()[sample]
+        want = micro.execute(t_np[sample], tup0[sample], T, x)
+        return g_ms, e_ms, bool(np.array_equal(got, want))
+
+    fig3, parity = [], True
+    for x in (1, 16):
+        for T in (1, 2, 4, 8, 16, 32):
+            t_np = rng.integers(0, T, n).astype(np.int32)
+            g0, e0, ok0 = run(t_np, T, x, 1)
+            # calibration (Appendix D): the partition count that is fastest
+            # (grouping plus execution) on a sample bulk of the same mix
+            ns = min(n, 1 << 16)
+            dts = torch.from_numpy(t_np[:ns]).cuda()
+            best, best_ms = 1, None
+            for p in [1 << k for k in range(int(T - 1).bit_length() + 1)]:
+                gputx.gputx_micro_run(dts, dv[:ns], T, x, p, ws)
+                ms = timed_total(dts, ns, T, x, p)
+                if best_ms is None or ms < best_ms:
+                    best, best_ms = p, ms
+            g1, e1, ok1 = run(t_np, T, x, best)
+            parity = parity and ok0 and ok1
+            fig3.append(dict(x=x, T=T, basic_txn_per_s=round(n / (e0 / 1e3)),
+                             grouped_txn_per_s=round(n / ((g1 + e1) / 1e3)), groups=best,
+                             grouping_ms=round(g1, 4), exec_ms=round(e1, 4), basic_ms=round(e0, 4)))
+            log(f"[bench] micro x={x} T={T}: basic {e0:.3f} ms, grouped p={best} "
+                f"{g1:.3f}+{e1:.3f} ms, parity={ok0 and ok1}")
+    fig12 = []
+    t_np = rng.integers(0, 16, n).astype(np.int32)
+    for p in (1, 2, 4, 8, 16):
+        g, e, ok = run(t_np, 16, 32, p)
+        parity = parity and ok
+        fig12.append(dict(groups=p, grouping_ms=round(g, 4), exec_ms=round(e, 4), total_ms=round(g + e, 4)))
+    log(f"[bench] micro breakdown (T=16, x=32): {fig12}")
+    return dict(workload=f"{n} independent transactions, 100 x integer mixing rounds each, types "
+                         f"uniform", by_types=fig3, breakdown_T16_x32=fig12, parity_sampled=parity)
+
+
 def pcie_inclusive(eng, dev, status, results, width, step, reps):
     """Transactions per second with every bulk's signatures copied in from
     pinned host memory and its statuses and results copied back: one stream
@@ -500,12 +577,13 @@ def main():
                     help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
-    ap.add_argument("--sections", default="grid,configs,ceilings,batch,serve",
-                    help="extra sections after the headline bulk: grid,configs,ceilings,batch,serve "
-                         "(or none)")
+    ap.add_argument("--sections", default="grid,configs,ceilings,micro,batch,serve",
+                    help="extra sections after the headline bulk: grid,configs,ceilings,micro,batch,"
+                         "serve (or none)")
     ap.add_argument("--grid-n", type=lambda v: [int(x) for x in v.split(",")],
                     default=[1 << 16, 1 << 18, 1 << 20])
     ap.add_argument("--order-n", type=int, default=1 << 18)
+    ap.add_argument("--micro-n", type=int, default=1 << 20)
     ap.add_argument("--serve-points", type=lambda v: [(float(p.split(':')[0]), float(p.split(':')[1]))
                                                       for p in v.split(",")],
                     default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 200.0)],
@@ -708,6 +786,8 @@ def main():
                               "per_s": round(per_s),
                               "frac_of_random_atomic": round(per_s / out["ceilings"]["atomic_add_per_s_random_2^26_addr"], 6),
                               "frac_of_64_addr": round(per_s / out["ceilings"]["atomic_add_per_s_64_addr"], 6)}
+    if "micro" in sections:
+        out["divergence_micro"] = bench_micro(args)
     if "batch" in sections:
         out["batched_vs_plain"] = bench_batch(args)
     if "serve" in sections:

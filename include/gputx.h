@@ -244,6 +244,30 @@ int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strategy, void* 
                        size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
                        gputx_bulk_stats* stats, gputx_stream_t stream);
 
+/* Execute one bulk without the timestamp constraint (Appendix G): the
+ * result is serializable -- equal to running the bulk's transactions one by
+ * one in SOME order -- but that order need not be the timestamp order, so
+ * neither the timestamp sort nor the operation sort and ranking run.
+ *   strategy GPUTX_TPL: basic 0/1 spin locks (Figure 10) taken with
+ *     compare-and-swap on every item's lock word, all or none at a time;
+ *   strategy GPUTX_PART: transactions grouped by partition with
+ *     per-partition counters and a prefix sum instead of a sort, then each
+ *     partition run one transaction after another; a bulk with
+ *     cross-partition transactions runs under the TPL form (Section 5.2).
+ *   serial_key_out: device int64[n]; after the bulk, ordering the committed
+ *     and aborted transactions by this key (ties in any order: tied
+ *     transactions do not conflict) gives a serial order equivalent to the
+ *     execution; invalid transactions get -1.
+ *   Timestamps are not checked and serve only as values (appended rows);
+ *   appended rows take slots in input order.  Other arguments, workspace
+ *   size, ordering and errors as gputx_execute_bulk; stats->w0, depth and
+ *   waves are 0. */
+int gputx_execute_bulk_relaxed(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
+                               size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
+                               int64_t* serial_key_out, gputx_bulk_stats* stats, gputx_stream_t stream);
+
+
+
 /* ---- batched form: many bulks, one graph launch ------------------------
  * Each item is one bulk with its own workspace and outputs.  Items of one
  * lane share tables and run in item order (so the serial order across them is
@@ -279,15 +303,90 @@ int gputx_batch_launch(gputx_batch b, gputx_stream_t stream);
 /* Free the graph. */
 int gputx_batch_destroy(gputx_batch b);
 
-/* ---- served form: continuous batching over an arrival trace ------------
- * Transactions enter the transaction pool at their arrival times and every
- * bulk interval (Section 6.3's fixed interval t) everything that has arrived
- * is cut into a bulk and issued; results return to the caller's host arrays
- * (the result pool, Section 3.2).  Up to `slots` bulks are in flight: the
- * bulk generation of a new bulk overlaps the execution of earlier ones, and
- * executions keep arrival order.  Admission is bounded by an HBM budget: a
- * cut waits for a free slot, and whatever arrives meanwhile joins it.  Runs
- * on the calling thread until the whole trace has been answered. */
+/* ---- served form: continuous batching (Sections 3.2, 6.3) --------------
+ * A server owns a transaction pool and a result pool in host memory and a
+ * native thread.  Callers submit signatures into the transaction pool; at
+ * every bulk interval (Section 6.3's fixed interval t) the thread cuts
+ * everything submitted so far into a bulk (up to max_bulk transactions) and
+ * issues it; finished bulks' statuses and results land in the result pool,
+ * where gputx_serve_poll collects them in submission order.  Up to `slots`
+ * bulks are in flight: the bulk generation of a new bulk overlaps the
+ * execution of earlier ones, and executions keep submission order, so the
+ * database sees the transactions in ticket order (ids must ascend).
+ * Admission is bounded by an HBM budget: the slots it allows are allocated
+ * at open; a cut waits for a free slot, and whatever arrives meanwhile joins
+ * it.  Bulks are padded to a size class (four per octave) with invalid
+ * transactions, which have no effect. */
+typedef struct {
+    int64_t deadline_ns;        /* bulk interval                                    */
+    int32_t slots;              /* bulks in flight at most (>= 1)                   */
+    int32_t strategy;           /* GPUTX_AUTO ..                                    */
+    int64_t max_bulk;           /* largest bulk; a bigger backlog is cut in pieces  */
+    int64_t hbm_budget;         /* device bytes the slots may use (0: no cap)       */
+    int32_t width;              /* result values per transaction                    */
+    int32_t max_ops;            /* per-transaction op bound (0: context maximum)    */
+} gputx_serve_opts;
+
+typedef struct {
+    int64_t first;              /* first ticket of the bulk                         */
+    int64_t count;
+    int64_t cut_ns;             /* server clock when the bulk was cut               */
+    int64_t done_ns;            /* server clock when its results were in host memory */
+    int32_t error;              /* bulk error, 0 = none                             */
+    int32_t slot;
+} gputx_serve_bulk;
+
+typedef struct {
+    int64_t n_bulks;            /* bulks issued                                     */
+    int64_t committed;
+    int64_t aborted;
+    int64_t invalid;
+    int64_t elapsed_ns;         /* open .. last results back                        */
+    int32_t slots_used;         /* slots the HBM budget allowed                     */
+    int32_t reserved;
+    int64_t slot_bytes;         /* device bytes one slot takes                      */
+} gputx_serve_report;
+
+typedef struct gputx_server_t* gputx_server;
+
+/* Open a server on a context whose tables and types are loaded.  n_params:
+ * parameters per submitted signature; pool_capacity: transactions the pools
+ * hold (submitted but not yet polled).  Allocates the slots (device), their
+ * graphs and pinned staging, then starts the server thread; the server
+ * clock starts here.  Errors: GPUTX_E_ARG, GPUTX_E_CAPACITY (budget below
+ * one slot, pool too large), GPUTX_E_HIP. */
+int gputx_serve_open(gputx_handle h, const gputx_serve_opts* opts, int32_t n_params,
+                     int64_t pool_capacity, gputx_server* out);
+
+/* Put n signatures into the transaction pool (host arrays: type[n],
+ * params[k * ld + i] for parameter k of transaction i, ts[n] ascending and
+ * above every id submitted before).  They arrive now (server clock) and get
+ * consecutive tickets starting at *first_ticket (may be NULL).  Nothing is
+ * taken on error: GPUTX_E_ARG (ids out of order), GPUTX_E_CAPACITY (pool
+ * full until results are polled), GPUTX_E_STATE (closing). */
+int gputx_serve_submit(gputx_server s, int64_t n, const int32_t* type, const int64_t* params,
+                       int64_t ld, const int64_t* ts, int64_t* first_ticket);
+
+/* Take up to max finished transactions from the result pool, in ticket
+ * order, without waiting: ticket[j], status[j], results[j * width ..],
+ * latency_ns[j] (results in host memory minus arrival); any output pointer
+ * may be NULL.  *n_out receives the count.  Returns a bulk error latched by
+ * the server (its transactions then read GPUTX_INVALID), else GPUTX_OK. */
+int gputx_serve_poll(gputx_server s, int64_t max, int64_t* ticket, int32_t* status, int64_t* results,
+                     int64_t* latency_ns, int64_t* n_out);
+
+/* Run every submitted transaction, stop the thread and free the server
+ * (results not polled are dropped).  report may be NULL.  Returns the first
+ * bulk error, if any. */
+int gputx_serve_close(gputx_server s, gputx_serve_report* report);
+
+/* Replay an arrival trace through a server: each transaction is submitted
+ * once its arrival time (ns from open) has passed, and the results are
+ * polled into status_out [n] / results_out [n][width] (host).  bulks[]
+ * receives up to bulk_capacity per-bulk records in issue order (first =
+ * trace index).  Per-transaction commit latency is done_ns of its bulk
+ * minus its arrival time.  Errors: GPUTX_E_ARG (trace not in arrival order,
+ * bad options), those of gputx_serve_open, a device bulk error code. */
 typedef struct {
     int64_t n;                  /* transactions                                     */
     const int64_t* arrival_ns;  /* [n] host, non-decreasing, ns from the start      */
@@ -297,45 +396,17 @@ typedef struct {
     const int64_t* ts;          /* [n] host, ascending (ids in arrival order)       */
 } gputx_trace;
 
-typedef struct {
-    int64_t deadline_ns;        /* bulk interval                                    */
-    int32_t slots;              /* bulks in flight at most (>= 1)                   */
-    int32_t strategy;           /* GPUTX_AUTO ..                                    */
-    int64_t max_bulk;           /* largest bulk; a bigger cut is issued in pieces   */
-    int64_t hbm_budget;         /* device bytes the slots may use (0: no cap)       */
-    int32_t width;              /* result values per transaction                    */
-    int32_t max_ops;            /* per-transaction op bound (0: context maximum)    */
-} gputx_serve_opts;
-
-typedef struct {
-    int64_t first;              /* first transaction (trace index) of the bulk      */
-    int64_t count;
-    int64_t cut_ns;             /* host clock when the bulk was cut                 */
-    int64_t done_ns;            /* host clock when its results were in host memory  */
-    int32_t error;              /* bulk error, 0 = none                             */
-    int32_t slot;
-} gputx_serve_bulk;
-
-typedef struct {
-    int64_t n_bulks;            /* bulks issued (records beyond the capacity dropped) */
-    int64_t committed;
-    int64_t aborted;
-    int64_t invalid;
-    int64_t elapsed_ns;         /* start .. last results back                       */
-    int32_t slots_used;         /* slots the HBM budget allowed                     */
-    int32_t reserved;
-    int64_t slot_bytes;         /* device bytes one slot takes                      */
-} gputx_serve_report;
-
-/* Serve a whole trace.  status_out [n] / results_out [n][width] are host
- * arrays (page-locked for overlap), bulks[] receives up to bulk_capacity
- * per-bulk records in issue order.  Per-transaction commit latency is
- * done_ns of its bulk minus its arrival time.  Errors: GPUTX_E_ARG (trace not
- * in arrival order, bad options), GPUTX_E_CAPACITY (budget below one slot), a
- * device bulk error code, GPUTX_E_HIP. */
 int gputx_serve(gputx_handle h, const gputx_trace* trace, const gputx_serve_opts* opts,
                 int32_t* status_out, int64_t* results_out, gputx_serve_bulk* bulks,
                 int64_t bulk_capacity, gputx_serve_report* report);
+
+/* Copy rows [row0, row0 + n) of column col of a loaded table into host_dst
+ * (4-byte elements for GPUTX_I32 columns, 8-byte for GPUTX_I64), ordered on
+ * the stream and synchronised: the database as the bulks left it (Section
+ * 3.2's tables stay resident on the device).  Rows must lie within the
+ * table's capacity.  Errors: GPUTX_E_ARG, GPUTX_E_HIP. */
+int gputx_read_table(gputx_handle h, int32_t table_id, int32_t col, int64_t row0, int64_t n,
+                     void* host_dst, gputx_stream_t stream);
 
 /* Current row count of a table (append tables advance on the device);
  * synchronises the stream. */
@@ -386,6 +457,31 @@ int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, gputx_strea
 int gputx_probe_handoff(int hip_device, int32_t hops, int32_t same_xcd, double* ns_per_hop);
 int gputx_probe_atomic_add(int hip_device, int64_t n_addr, int64_t n_updates, double* updates_per_s);
 int gputx_probe_gather(int hip_device, int64_t table_bytes, int64_t n_gathers, double* gb_per_s);
+
+/* ---- branch-divergence micro benchmark (Section 6.2, Figures 3 and 12) --
+ * n independent transactions; transaction i has type type[i] in [0, n_types)
+ * and reads tuples[i], runs its type's case of one switch -- 100 * x rounds
+ * of v <- (v xor (v >> 29)) * M_k + (k + 1) with M_k = 0x9E3779B97F4A7C15 +
+ * 2k (uint64 arithmetic) for type k -- and writes the result back.  With
+ * groups > 1 the transaction order is first radix-partitioned on the top
+ * log2(groups) bits of the type id, one stable 1-bit pass per bit (Appendix
+ * D's grouping with a tunable number of partitions), so lanes of one wave
+ * share fewer case bodies.  groups = 1 runs the bulk in input order.
+ *   type, tuples: device arrays of n; n_types in [1, 32]; x in [0, 1000];
+ *   groups a power of two <= n_types.
+ *   workspace: device, 256-byte aligned, >= gputx_micro_workspace_size(n)
+ *     (unused when groups == 1).
+ *   phase: 0 both steps, 1 the grouping only, 2 the execution only (after a
+ *     phase-1 call with the same arguments and workspace), for timing them
+ *     apart.  After the grouping, the grouped order (int32 transaction
+ *     indices, n of them) sits at byte 0 of the workspace when log2(groups)
+ *     is odd and at byte round_up(4 n, 256) when it is even.
+ * Ordered on the stream; errors GPUTX_E_ARG, GPUTX_E_CAPACITY, GPUTX_E_HIP
+ * through gputx_last_error(NULL). */
+size_t gputx_micro_workspace_size(int64_t n);
+int gputx_micro_run(int64_t n, const int32_t* type, int64_t* tuples, int32_t n_types, int32_t x,
+                    int32_t groups, void* workspace, size_t ws_bytes, int32_t phase,
+                    gputx_stream_t stream);
 
 /* Message of the last error on this context (static storage, never NULL). */
 const char* gputx_last_error(gputx_handle h);

@@ -137,6 +137,13 @@ struct SideLane {
 // bulk's stream waits for them after the features
 hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm,
                         const SideLane* side = nullptr);
+// bulk generation without the timestamp constraint (Appendix G): validation,
+// count scans and basic operations only (kernels_front.hip)
+void launch_front_relaxed(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
+// execution without the timestamp constraint (kernels_exec.hip): TPL with
+// 0/1 spin locks, or PART grouped by per-partition counters; serial_key[i]
+// receives a key whose order is a serial order the execution is equivalent to
+void launch_exec_relaxed(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, int64_t* serial_key);
 // the lock and k-set executors' per-operation records (kernels_front.hip),
 // gated on the choice
 void launch_rank_full(const BulkArgs& a, hipStream_t s);

@@ -510,6 +510,237 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Without the timestamp constraint (Appendix G): serializability only.
+//
+// TPL takes basic 0/1 spin locks (Figure 10): a transaction acquires the
+// locks of all its items with compare-and-swap, in ascending lock order, and
+// gives back what it holds when one is taken, so no lane ever waits while
+// holding a lock (a wave64 cannot wait on one of its own lanes).  Locks are
+// 64-bit words in a table of power-of-two size indexed by a hash of the
+// item key; items sharing a word only lock more coarsely.  A word holds a
+// logical clock besides the held bit: the holder takes 1 + the largest clock
+// of its words as its key and releases every word with that clock, so two
+// conflicting transactions get keys in the order they ran, and sorting by
+// key gives a serial order the execution is equivalent to.
+//
+// PART groups transactions by partition with per-partition counters
+// instead of a sort: each transaction takes its position in its partition
+// from its partition's counter, a prefix sum over the counters gives the
+// groups' starts, and a scatter places it.  Partitions are then executed by
+// the PART kernels, in that (arbitrary) order inside each partition; the
+// grouped position is the serial key.
+
+__device__ __forceinline__ uint32_t lock_hash(uint32_t key) {
+    uint32_t h = key * 0x9E3779B1u;
+    return h ^ (h >> 15);
+}
+
+__global__ void k_relaxed_choose(BulkArgs a) {
+    GtxState* st = a.ws.st;
+    if (threadIdx.x != 0 || st->error) return;
+    // Section 5.2: transactions that span partitions go to the lock executor
+    const int chosen = (a.strategy == GPUTX_PART && st->cross == 0) ? GPUTX_PART : GPUTX_TPL;
+    st->chosen = chosen;
+    st->run_part = chosen == GPUTX_PART;
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_lock_clear(BulkArgs a, uint64_t* locks, int64_t n_locks) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_TPL) return;
+    for (int64_t i = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; i < n_locks; i += (int64_t)gridDim.x * GTX_BLOCK)
+        locks[i] = 0;
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_tpl_relaxed(BulkArgs a, uint64_t* locks, uint32_t lock_mask,
+                                                           int64_t* serial_key) {
+    GtxState* st = a.ws.st;
+    if (failed(st) || st->chosen != GPUTX_TPL) return;
+    const int64_t stride = (int64_t)gridDim.x * GTX_BLOCK;
+    for (int64_t base = (int64_t)blockIdx.x * GTX_BLOCK + wave_id() * 64; base < a.n; base += stride) {
+        const int64_t p = base + lane_id();
+        const int32_t t = p < a.n ? a.ws.tty[p] : -1;
+        bool done = t < 0;
+        if (p < a.n && done) serial_key[p] = -1;  // invalid: never runs
+        // the transaction's lock words, ascending and distinct
+        uint32_t slot[GTX_MAX_OPS];
+#pragma unroll
+        for (int j = 0; j < GTX_MAX_OPS; ++j) slot[j] = 0xffffffffu;
+        int nk = 0;
+        TxnIn x;
+        if (!done) {
+            load_txn(a, p, t, x);
+            const int64_t o0 = op_begin(a, p), o1 = op_end(a, p);
+            for (int64_t o = o0; o < o1; ++o) {
+                const uint32_t v = lock_hash(a.ws.pk[0][o]) & lock_mask;
+                bool dup = false;
+#pragma unroll
+                for (int j = 0; j < GTX_MAX_OPS; ++j) dup = dup || (j < nk && slot[j] == v);
+                if (dup) continue;
+#pragma unroll
+                for (int j = 0; j < GTX_MAX_OPS; ++j)
+                    if (j == nk) slot[j] = v;
+                ++nk;
+            }
+            // ascending (unused entries hold the largest value and stay last)
+#pragma unroll
+            for (int i = 0; i < GTX_MAX_OPS - 1; ++i)
+#pragma unroll
+                for (int j = 0; j < GTX_MAX_OPS - 1 - i; ++j) {
+                    const uint32_t lo = min(slot[j], slot[j + 1]), hi = max(slot[j], slot[j + 1]);
+                    slot[j] = lo;
+                    slot[j + 1] = hi;
+                }
+        }
+        uint64_t held[GTX_MAX_OPS];
+        uint64_t t0 = 0;
+        while (__any(!done)) {
+            bool got = false;
+            if (!done) {
+                got = true;
+                int taken = 0;
+#pragma unroll
+                for (int j = 0; j < GTX_MAX_OPS; ++j) {
+                    if (j < nk && got) {
+                        const uint64_t cur = ld_relaxed(&locks[slot[j]]);
+                        if ((cur & 1ull) ||
+                            atomicCAS((unsigned long long*)&locks[slot[j]], (unsigned long long)cur,
+                                      (unsigned long long)(cur | 1ull)) != cur) {
+                            got = false;
+                        } else {
+                            held[j] = cur;
+                            taken = j + 1;
+                        }
+                    }
+                }
+                if (!got) {  // give back what was taken, unchanged
+#pragma unroll
+                    for (int j = 0; j < GTX_MAX_OPS; ++j)
+                        if (j < taken) st_relaxed(&locks[slot[j]], held[j]);
+                }
+            }
+            if (__any(got)) {
+                fence_acquire();  // see the writes of the previous holders
+                int32_t s = 0;
+                if (got) s = exec_txn(a, x);
+                fence_release();  // publish this transaction's writes before unlocking
+                if (got) {
+                    uint64_t c = 0;
+#pragma unroll
+                    for (int j = 0; j < GTX_MAX_OPS; ++j)
+                        if (j < nk) c = max(c, held[j] >> 1);
+                    c += 1;
+#pragma unroll
+                    for (int j = 0; j < GTX_MAX_OPS; ++j)
+                        if (j < nk) st_relaxed(&locks[slot[j]], c << 1);
+                    serial_key[x.i] = (int64_t)c;
+                    done = true;
+                }
+                count_status(st, got, s);
+                t0 = 0;
+            } else {
+                if (t0 == 0) t0 = now_ticks();
+                else if (now_ticks() - t0 > a.spin_ticks) {
+                    fail(st, GPUTX_E_DEADLOCK);
+                    break;
+                }
+                if (failed(st)) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (failed(st)) break;
+    }
+}
+
+// ---- PART grouping by per-partition counters ------------------------------
+constexpr int kGroupTile = 1024;       // transactions per counting workgroup
+constexpr int kGroupLdsBins = 4096;    // partitions counted in LDS first
+
+// Each transaction's position within its partition (kept in tsv[0]); the
+// counters end up holding the partition sizes.
+__global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_count(BulkArgs a, int32_t* counter) {
+    GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || !st->run_part) return;
+    __shared__ int hist[kGroupLdsBins];
+    __shared__ int base[kGroupLdsBins];
+    const int64_t bins = a.n_parts + 1;  // the last bin: transactions PART does not run
+    const bool lds = bins <= kGroupLdsBins;
+    if (lds) {
+        for (int b = threadIdx.x; b < bins; b += GTX_BLOCK) hist[b] = 0;
+        __syncthreads();
+    }
+    const int64_t t0 = (int64_t)blockIdx.x * kGroupTile;
+    int local[kGroupTile / GTX_BLOCK];
+    uint32_t pid[kGroupTile / GTX_BLOCK];
+#pragma unroll
+    for (int k = 0; k < kGroupTile / GTX_BLOCK; ++k) {
+        const int64_t p = t0 + k * GTX_BLOCK + threadIdx.x;
+        pid[k] = p < a.n ? a.ws.qk[0][p] : 0;
+        local[k] = 0;
+        if (p < a.n) local[k] = lds ? atomicAdd(&hist[pid[k]], 1) : atomicAdd(&counter[pid[k]], 1);
+    }
+    if (!lds) {
+#pragma unroll
+        for (int k = 0; k < kGroupTile / GTX_BLOCK; ++k) {
+            const int64_t p = t0 + k * GTX_BLOCK + threadIdx.x;
+            if (p < a.n) a.ws.tsv[0][p] = (uint32_t)local[k];
+        }
+        return;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < bins; b += GTX_BLOCK)
+        base[b] = hist[b] ? atomicAdd(&counter[b], hist[b]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kGroupTile / GTX_BLOCK; ++k) {
+        const int64_t p = t0 + k * GTX_BLOCK + threadIdx.x;
+        if (p < a.n) a.ws.tsv[0][p] = (uint32_t)(base[pid[k]] + local[k]);
+    }
+}
+
+__global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_clear(BulkArgs a, int32_t* counter) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || !st->run_part) return;
+    for (int64_t b = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; b <= a.n_parts; b += (int64_t)gridDim.x * GTX_BLOCK)
+        counter[b] = 0;
+}
+
+// One workgroup: exclusive scan of the counters in place (group starts).
+__global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_scan(BulkArgs a, int32_t* counter) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || !st->run_part) return;
+    __shared__ int lds[GTX_WAVES + 1];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int64_t bins = a.n_parts + 1;
+    for (int64_t c0 = 0; c0 < bins; c0 += GTX_BLOCK) {
+        const int64_t b = c0 + threadIdx.x;
+        const int v = b < bins ? counter[b] : 0;
+        int tot;
+        const int ex = block_excl_sum(v, &tot, lds);
+        if (b < bins) counter[b] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+}
+
+// Place every transaction in its group: the grouped arrays are the ones the
+// partition sort would have produced (partition ids and serial positions).
+__global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_scatter(BulkArgs a, const int32_t* start, int64_t* serial_key) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || !st->run_part) return;
+    const int fb = a.part_passes & 1;
+    for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * GTX_BLOCK) {
+        const uint32_t pid = a.ws.qk[0][p];
+        const int64_t dst = (int64_t)start[pid] + a.ws.tsv[0][p];
+        a.ws.qk[fb][dst] = pid;
+        a.ws.qv[fb][dst] = (uint32_t)p;
+        serial_key[p] = a.ws.tty[p] >= 0 ? dst : -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // PART
 
 // ---- PART partitions ------------------------------------------------------
@@ -1711,6 +1942,13 @@ static void launch_part_gather(const BulkArgs& a, hipStream_t s) {
                        dim3(GTX_BLOCK), 0, s, a);
 }
 
+static void launch_part_heads(const BulkArgs& a, hipStream_t s) {
+    const unsigned nbh = (unsigned)std::max<int64_t>(1, (a.n + kHeadTile - 1) / kHeadTile);
+    hipLaunchKernelGGL(k_heads_up, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+    hipLaunchKernelGGL(k_heads_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, (int)nbh);
+    hipLaunchKernelGGL(k_heads_down, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+}
+
 void launch_part_sort(const BulkArgs& a, hipStream_t s) {
     SortPlan sp{};
     sp.key_bytes = 4;
@@ -1721,11 +1959,90 @@ void launch_part_sort(const BulkArgs& a, hipStream_t s) {
     sp.gate = a.part_early ? nullptr : &a.ws.st->run_part;
     sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
     sort_pairs(sp, s);
-    const unsigned nbh = (unsigned)std::max<int64_t>(1, (a.n + kHeadTile - 1) / kHeadTile);
-    hipLaunchKernelGGL(k_heads_up, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
-    hipLaunchKernelGGL(k_heads_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, (int)nbh);
-    hipLaunchKernelGGL(k_heads_down, dim3(nbh), dim3(GTX_BLOCK), 0, s, a);
+    launch_part_heads(a, s);
     if (a.part_early) launch_part_gather(a, s);
+}
+
+// The partition kernels over the grouped transactions: long partitions get a
+// workgroup each with the LDS cell table (chunks of 256 transactions staged
+// by four waves where the LDS fits, else 128 or 64, e.g. for new-order's
+// wide signature); short ones a lane each.
+static void launch_part_kernels(const BulkArgs& a, hipStream_t s) {
+    BulkArgs b = a;
+    const bool pipe256 = part_pipe_fits(a, 256);
+    const bool pipe128 = !pipe256 && part_pipe_fits(a, 128);
+    const bool pipe64 = !pipe256 && !pipe128 && part_pipe_fits(a, 64);
+    const bool wave = !pipe256 && !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
+    b.long_part = (pipe256 || pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
+    const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
+    if (pipe256)
+        hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 * kPipeSerial + 256), part_pipe_lds(a, 256), s, b);
+    else if (pipe128)
+        hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 * kPipeSerial + 128), part_pipe_lds(a, 128), s, b);
+    else if (pipe64)
+        hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 * kPipeSerial + 64), part_pipe_lds(a, 64), s, b);
+    else if (wave)
+        hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
+    const unsigned lanes = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((std::min<int64_t>(a.n, a.n_parts) + GTX_BLOCK - 1) / GTX_BLOCK, 4096));
+    hipLaunchKernelGGL(k_part, dim3(lanes), dim3(GTX_BLOCK), 0, s, b);
+}
+
+// serial keys of PART after the partition sort: each transaction's grouped position
+__global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_keys(BulkArgs a, int64_t* serial_key) {
+    const GtxState* st = a.ws.st;
+    if (ld_relaxed(&st->error) != 0 || !st->run_part) return;
+    const int fb = a.part_passes & 1;
+    for (int64_t d = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; d < a.n; d += (int64_t)gridDim.x * GTX_BLOCK) {
+        const uint32_t p = a.ws.qv[fb][d];
+        serial_key[p] = a.ws.tty[p] >= 0 ? d : -1;
+    }
+}
+
+void launch_exec_relaxed(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, int64_t* serial_key) {
+    hipLaunchKernelGGL(k_relaxed_choose, dim3(1), dim3(64), 0, s, a);
+    pm.mark(PH_FEATURES, s);
+    hipLaunchKernelGGL(k_exec_gate, dim3(1), dim3(64), 0, s, a);
+    const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096));
+    if (a.strategy == GPUTX_PART) {
+        int32_t* counter = a.ws.grp_cnt;  // [mcap] ints, free without the op sort
+        if (a.n_parts + 1 <= a.mcap) {
+            hipLaunchKernelGGL(k_pgroup_clear, dim3(nb), dim3(GTX_BLOCK), 0, s, a, counter);
+            hipLaunchKernelGGL(k_pgroup_count, dim3((unsigned)((a.n + kGroupTile - 1) / kGroupTile)), dim3(GTX_BLOCK),
+                               0, s, a, counter);
+            hipLaunchKernelGGL(k_pgroup_scan, dim3(1), dim3(GTX_BLOCK), 0, s, a, counter);
+            hipLaunchKernelGGL(k_pgroup_scatter, dim3(nb), dim3(GTX_BLOCK), 0, s, a, (const int32_t*)counter,
+                               serial_key);
+            launch_part_heads(a, s);
+        } else {
+            // more partitions than the counters' room in the workspace: group
+            // with the partition sort instead
+            BulkArgs b = a;
+            b.part_early = 0;
+            launch_part_sort(b, s);
+            hipLaunchKernelGGL(k_pgroup_keys, dim3(nb), dim3(GTX_BLOCK), 0, s, a, serial_key);
+        }
+        pm.mark(PH_PARTSORT, s);
+        launch_part_gather(a, s);
+        pm.mark(PH_PARTGATHER, s);
+        launch_part_kernels(a, s);
+    } else {
+        pm.mark(PH_PARTSORT, s);
+        pm.mark(PH_PARTGATHER, s);
+    }
+    pm.mark(PH_PART, s);
+    // lock words in the op-record region (unused without the op sort)
+    int64_t n_locks = 4;
+    while (n_locks * 2 <= a.mcap * (int64_t)(sizeof(OpInfo) / sizeof(uint64_t)) && n_locks < ((int64_t)1 << 22))
+        n_locks *= 2;
+    uint64_t* locks = reinterpret_cast<uint64_t*>(a.ws.op_info);
+    hipLaunchKernelGGL(k_lock_clear, dim3(nb), dim3(GTX_BLOCK), 0, s, a, locks, n_locks);
+    hipLaunchKernelGGL(k_tpl_relaxed, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a, locks, (uint32_t)(n_locks - 1),
+                       serial_key);
+    pm.mark(PH_TPL, s);
+    pm.mark(PH_KSET, s);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    pm.mark(PH_FINAL, s);
 }
 
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
@@ -1736,29 +2053,9 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     if (part && !a.part_early) launch_part_sort(a, s);
     pm.mark(PH_PARTSORT, s);
     if (part) {
-        // long partitions: a workgroup each with the LDS cell table (chunks of
-        // 256 transactions staged by four waves where the LDS fits, else 128
-        // or 64, e.g. for new-order's wide signature); short ones: a lane each
-        BulkArgs b = a;
-        const bool pipe256 = part_pipe_fits(a, 256);
-        const bool pipe128 = !pipe256 && part_pipe_fits(a, 128);
-        const bool pipe64 = !pipe256 && !pipe128 && part_pipe_fits(a, 64);
-        const bool wave = !pipe256 && !pipe128 && !pipe64 && part_wave_lds(a) <= g_part_lds_limit;
-        b.long_part = (pipe256 || pipe128 || pipe64 || wave) ? kLongPart : INT32_MAX;
-        const unsigned groups = (unsigned)std::min<int64_t>(a.n / kLongPart + 1, 2048);
         if (!a.part_early) launch_part_gather(a, s);
         pm.mark(PH_PARTGATHER, s);
-        if (pipe256)
-            hipLaunchKernelGGL(k_part_pipe<256>, dim3(groups), dim3(64 * kPipeSerial + 256), part_pipe_lds(a, 256), s, b);
-        else if (pipe128)
-            hipLaunchKernelGGL(k_part_pipe<128>, dim3(groups), dim3(64 * kPipeSerial + 128), part_pipe_lds(a, 128), s, b);
-        else if (pipe64)
-            hipLaunchKernelGGL(k_part_pipe<64>, dim3(groups), dim3(64 * kPipeSerial + 64), part_pipe_lds(a, 64), s, b);
-        else if (wave)
-            hipLaunchKernelGGL(k_part_wave, dim3(groups), dim3(64), part_wave_lds(a), s, b);
-        const unsigned lanes = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>((std::min<int64_t>(a.n, a.n_parts) + GTX_BLOCK - 1) / GTX_BLOCK, 4096));
-        hipLaunchKernelGGL(k_part, dim3(lanes), dim3(GTX_BLOCK), 0, s, b);
+        launch_part_kernels(a, s);
     } else {
         pm.mark(PH_PARTGATHER, s);
     }

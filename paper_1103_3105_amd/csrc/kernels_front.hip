@@ -621,6 +621,26 @@ hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, 
     return e;
 }
 
+// Bulk generation without the timestamp constraint (Appendix G): no
+// timestamp order, no operation sort, no ranking -- validation, the count
+// scans (append slots in input order) and the basic operations only.
+void launch_front_relaxed(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
+    pm.mark(PH_START, s);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(GTX_BLOCK), 0, s, a.ws.st);
+    pm.mark(PH_ORDER, s);
+    hipLaunchKernelGGL(k_prepare, dim3(std::min<unsigned>(kPrepBlocks, blocks_for(a.n, GTX_BLOCK))), dim3(GTX_BLOCK), 0, s, a);
+    const int K = 1 + a.n_app;
+    const int nb = (int)blocks_for(a.n, kScanTile);
+    hipLaunchKernelGGL(k_scan_up, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
+    hipLaunchKernelGGL(k_scan_mid, dim3(K + 1), dim3(GTX_BLOCK), 0, s, a, K, nb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(GTX_BLOCK), 0, s, a, K, nb);
+    pm.mark(PH_PREPARE, s);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(a.n, GTX_BLOCK)), dim3(GTX_BLOCK), 0, s, a);
+    pm.mark(PH_EMIT, s);
+    pm.mark(PH_OPSORT, s);
+    pm.mark(PH_RANK, s);
+}
+
 void launch_rank_full(const BulkArgs& a, hipStream_t s) {
     const int nbr = (int)blocks_for(a.mcap, kRankTile);
     hipLaunchKernelGGL(k_rank_down<true>, dim3(nbr), dim3(GTX_BLOCK), 0, s, a, nbr);

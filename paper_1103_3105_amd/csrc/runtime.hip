@@ -593,6 +593,36 @@ extern "C" int gputx_execute_bulk(gputx_handle h, const gputx_bulk* b, int strat
     return GPUTX_OK;
 }
 
+extern "C" int gputx_execute_bulk_relaxed(gputx_handle h, const gputx_bulk* b, int strategy, void* workspace,
+                                          size_t ws_bytes, int32_t* status_out, int64_t* results_out,
+                                          int32_t width, int64_t* serial_key_out, gputx_bulk_stats* stats,
+                                          gputx_stream_t stream) {
+    if (!h) return gtx_set_err(h, GPUTX_E_ARG, "null handle");
+    if (strategy != GPUTX_TPL && strategy != GPUTX_PART)
+        return gtx_set_err(h, GPUTX_E_ARG, "relaxed execution runs GPUTX_TPL or GPUTX_PART, not %d", strategy);
+    if (b && b->n > 0 && !serial_key_out) return gtx_set_err(h, GPUTX_E_ARG, "null serial_key_out");
+    HIP_OK(h, hipSetDevice(h->device));
+    BulkArgs a;
+    int rc = gtx_make_args(h, b, strategy, workspace, ws_bytes, status_out, results_out, width, stats,
+                           gtx_grid_for(h, 1), &a);
+    if (rc) return rc;
+    a.part_early = 0;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    PhaseMarks pm;
+    if (h->timing && h->ev && h->ring_used < gputx_ctx::kRing && b->n > 0)
+        pm.ev = h->ev + (h->ring_used++) * PH_COUNT;
+    if (b->n == 0) {
+        launch_empty(a, s);
+    } else {
+        launch_front_relaxed(a, s, pm);
+        launch_exec_relaxed(a, s, pm, serial_key_out);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return gtx_set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return GPUTX_OK;
+}
+
 // ---- batched form: many bulks in one HIP graph ------------------------------
 struct gputx_batch_t {
     gputx_handle h = nullptr;
@@ -740,6 +770,26 @@ extern "C" int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, 
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     int64_t v = n;
     HIP_OK(h, hipMemcpyAsync(h->d_rowcount + T.app_idx, &v, 8, hipMemcpyHostToDevice, s));
+    HIP_OK(h, hipStreamSynchronize(s));
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_read_table(gputx_handle h, int32_t table_id, int32_t col, int64_t row0, int64_t n,
+                                void* host_dst, gputx_stream_t stream) {
+    if (!h) return gtx_set_err(h, GPUTX_E_ARG, "null handle");
+    if (table_id < 0 || table_id >= GPUTX_MAX_TABLES || !h->tabs[table_id].present)
+        return gtx_set_err(h, GPUTX_E_ARG, "unknown table %d", table_id);
+    const gputx_table_desc& d = h->tabs[table_id].d;
+    if (col < 0 || col >= d.n_cols) return gtx_set_err(h, GPUTX_E_ARG, "table %d has no column %d", table_id, col);
+    if (row0 < 0 || n < 0 || row0 + n > d.capacity || (n > 0 && !host_dst))
+        return gtx_set_err(h, GPUTX_E_ARG, "rows [%lld, %lld) outside table %d's %lld rows", (long long)row0,
+                           (long long)(row0 + n), table_id, (long long)d.capacity);
+    if (n == 0) return GPUTX_OK;
+    const size_t es = d.col_dtype[col] == GPUTX_I32 ? 4 : 8;
+    HIP_OK(h, hipSetDevice(h->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_OK(h, hipMemcpyAsync(host_dst, (const char*)d.col_ptr[col] + (size_t)row0 * es, (size_t)n * es,
+                             hipMemcpyDeviceToHost, s));
     HIP_OK(h, hipStreamSynchronize(s));
     return GPUTX_OK;
 }

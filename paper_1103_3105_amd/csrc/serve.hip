@@ -1,25 +1,37 @@
-// Served form: continuous batching over an arrival trace (Sections 3.2, 6.3).
+// Served form: continuous batching (Sections 3.2, 6.3).
 //
-// Transactions arrive into the transaction pool at their trace times; every
-// bulk interval t (the paper's fixed interval, here `deadline_ns`) the loop
-// cuts everything that has arrived into a bulk and issues it; results go back
-// to the result pool (host memory) and each bulk's completion time is
-// recorded, so the caller gets per-transaction commit latency.
+// Section 3.2's pipeline: transactions enter a transaction pool, a bulk is
+// formed from the pool at every interval t and runs on the GPU, and the
+// results land in a result pool.  A server (gputx_serve_open) owns both pools
+// in host memory and a native thread that cuts, issues and retires bulks:
+//   * gputx_serve_submit copies signatures into the transaction pool and
+//     hands out tickets (consecutive sequence numbers);
+//   * every interval the thread cuts everything submitted so far (up to the
+//     largest bulk) and issues it on a free slot;
+//   * a finished bulk's statuses and results are copied into the result
+//     pool, where gputx_serve_poll picks them up in ticket order;
+//   * gputx_serve_close waits for everything submitted, then frees the slots.
+// gputx_serve replays an arrival trace through the same server: a driver
+// loop submits each transaction once its arrival time has passed and polls
+// the results.
 //
 // MI355X mapping:
 //  * K slots, each with its own device bulk arrays, workspace and outputs, and
 //    pre-instantiated HIP graphs (bulk generation and execution separately)
-//    for power-of-two bulk sizes; a bulk is padded to its size class with
-//    invalid transactions (no effect, outputs ignored).  Issuing a bulk costs
-//    one host-to-device copy, two graph launches and two result copies.
+//    for a ladder of bulk sizes (four per octave, multiples of 256); a bulk is
+//    padded to its size class with invalid transactions (no effect, outputs
+//    ignored), at most a fifth more work.
 //  * Bulk generation of a bulk runs on its slot's stream and overlaps the
 //    execution of earlier bulks; executions are ordered on one stream, so the
-//    database sees the bulks in arrival order.
+//    database sees the bulks in ticket order.
 //  * Admission: the number of slots is capped by an HBM byte budget; a cut
-//    waits for a free slot, and everything that arrived meanwhile joins it.
+//    waits for a free slot, and everything submitted meanwhile joins it.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -35,7 +47,7 @@ constexpr int64_t kMinBucket = 256;
 struct Slot {
     char* dev = nullptr;             // device buffer (bulk arrays, workspace, outputs, stats)
     char* stage = nullptr;           // pinned host staging of the bulk arrays
-    gputx_bulk_stats* stats_h = nullptr;  // pinned
+    char* out_h = nullptr;           // pinned host copy of statuses, results and stats
     hipStream_t fs = nullptr;
     hipEvent_t ready = nullptr, done = nullptr;
     std::vector<hipGraphExec_t> front, exec;
@@ -61,49 +73,66 @@ BucketLayout layout_for(int64_t n, int np) {
     return L;
 }
 
+// Size classes: four per octave from 256 up, rounded up to multiples of 256,
+// the last one covering `maxb`.
+std::vector<int64_t> size_ladder(int64_t maxb) {
+    std::vector<int64_t> v;
+    for (int64_t oct = kMinBucket; v.empty() || v.back() < maxb; oct <<= 1)
+        for (int q = 0; q < 4 && (v.empty() || v.back() < maxb); ++q) {
+            int64_t s = (oct * (4 + q) / 4 + 255) / 256 * 256;
+            if (v.empty() || s > v.back()) v.push_back(std::min(s, std::max(maxb, kMinBucket)));
+        }
+    return v;
+}
+
 inline int64_t since(Clock::time_point t0) {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
 }
 
 }  // namespace
 
-extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_serve_opts* o,
-                           int32_t* status_out, int64_t* results_out, gputx_serve_bulk* bulks,
-                           int64_t bulk_capacity, gputx_serve_report* rep) {
-    if (!h || !tr || !o || !rep || (tr->n > 0 && (!tr->arrival_ns || !tr->type || !tr->params ||
-                                                   !tr->ts || !status_out || !results_out)))
-        return gtx_set_err(h, GPUTX_E_ARG, "null argument");
-    if (o->deadline_ns <= 0 || o->slots < 1 || o->max_bulk < 1 || o->width < 1 || tr->n_params < 1 ||
-        tr->n_params > GTX_MAX_PARAMS || o->strategy < GPUTX_AUTO || o->strategy > GPUTX_KSET)
-        return gtx_set_err(h, GPUTX_E_ARG, "bad serving options");
-    for (int64_t i = 1; i < tr->n; ++i)
-        if (tr->arrival_ns[i] < tr->arrival_ns[i - 1] || tr->ts[i] <= tr->ts[i - 1])
-            return gtx_set_err(h, GPUTX_E_ARG, "trace must be in arrival order with ascending ids");
-    std::memset(rep, 0, sizeof *rep);
-    HIP_OK(h, hipSetDevice(h->device));
-
-    const int np = tr->n_params;
-    const int W = o->width;
-    int64_t maxb = kMinBucket;
-    while (maxb < o->max_bulk) maxb <<= 1;
-    std::vector<int64_t> sizes;
-    for (int64_t b = kMinBucket; b <= maxb; b <<= 1) sizes.push_back(b);
-    const BucketLayout big = layout_for(maxb, np);
-    const size_t ws_bytes = gputx_workspace_size_ops(h, maxb, o->max_ops);
-    const size_t off_ws = up256(big.bytes);
-    const size_t off_status = off_ws + up256(ws_bytes);
-    const size_t off_results = off_status + up256((size_t)maxb * 4);
-    const size_t off_stats = off_results + up256((size_t)maxb * 8 * W);
-    const size_t slot_bytes = off_stats + up256(sizeof(gputx_bulk_stats));
-    rep->slot_bytes = (int64_t)slot_bytes;
-    int nslots = o->slots;
-    if (o->hbm_budget > 0) nslots = (int)std::min<int64_t>(nslots, o->hbm_budget / (int64_t)slot_bytes);
-    if (nslots < 1) return gtx_set_err(h, GPUTX_E_CAPACITY, "HBM budget below one slot (%zu bytes)", slot_bytes);
-
-    std::vector<Slot> slots(nslots);
+struct gputx_server_t {
+    gputx_handle h = nullptr;
+    gputx_serve_opts o{};
+    int np = 0, W = 0;
+    int64_t cap = 0;  // pool capacity in transactions (both pools)
+    // transaction pool and result pool: rings indexed by ticket % cap
+    std::vector<int32_t> p_type;
+    std::vector<int64_t> p_params;  // [np][cap]
+    std::vector<int64_t> p_ts, p_arrival;
+    std::vector<int32_t> r_status;
+    std::vector<int64_t> r_results;  // [cap][W]
+    std::vector<int64_t> r_done;
+    std::atomic<int64_t> submitted{0};  // tickets handed out
+    std::atomic<int64_t> answered{0};   // tickets whose results are in the result pool
+    std::atomic<int64_t> polled{0};     // tickets handed back by poll (ring entries free)
+    int64_t last_ts = INT64_MIN;        // submit side: ids must ascend
+    bool any_ts = false;
+    // device side (server thread only once running)
+    std::vector<Slot> slots;
     hipStream_t es = nullptr;
-    int rc = GPUTX_OK;
-    auto release = [&]() {
+    std::vector<int64_t> sizes;
+    int64_t maxb = 0;
+    size_t off_ws = 0, off_status = 0, off_results = 0, off_stats = 0, slot_bytes = 0, ws_bytes = 0;
+    Clock::time_point t0;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    std::atomic<int> err{0};
+    std::mutex err_mu;
+    std::string err_msg;
+    std::mutex log_mu;
+    std::vector<gputx_serve_bulk> log;
+    gputx_serve_report rep{};
+    int64_t last_done = 0;
+
+    void set_error(int code, const std::string& msg) {
+        std::lock_guard<std::mutex> lk(err_mu);
+        if (!err.load()) {
+            err_msg = msg;
+            err.store(code);
+        }
+    }
+    void release() {
         for (auto& s : slots) {
             for (auto g : s.front) (void)hipGraphExecDestroy(g);
             for (auto g : s.exec) (void)hipGraphExecDestroy(g);
@@ -113,30 +142,227 @@ extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_se
             if (s.fs) (void)hipStreamDestroy(s.fs);
             if (s.dev) (void)hipFree(s.dev);
             if (s.stage) (void)hipHostFree(s.stage);
-            if (s.stats_h) (void)hipHostFree(s.stats_h);
+            if (s.out_h) (void)hipHostFree(s.out_h);
         }
+        slots.clear();
         if (es) (void)hipStreamDestroy(es);
-    };
-#define SERVE_OK(call)                                                                        \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess) {                                                               \
-            rc = gtx_set_err(h, GPUTX_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
-            release();                                                                        \
-            return rc;                                                                        \
-        }                                                                                     \
-    } while (0)
+        es = nullptr;
+    }
+    void run();
+    bool retire(std::vector<int>& fifo, size_t& head, bool block);
+    bool issue(int si, int64_t first, int64_t cnt, int64_t now);
+};
 
-    SERVE_OK(hipStreamCreateWithFlags(&es, hipStreamNonBlocking));
+// Copy a finished bulk into the result pool (ticket order) and log it.
+bool gputx_server_t::retire(std::vector<int>& fifo, size_t& head, bool block) {
+    while (head < fifo.size()) {
+        Slot& s = slots[fifo[head]];
+        hipError_t q = block ? hipEventSynchronize(s.done) : hipEventQuery(s.done);
+        if (q == hipErrorNotReady) return true;
+        if (q != hipSuccess) {
+            set_error(GPUTX_E_HIP, std::string("bulk completion: ") + hipGetErrorString(q));
+            return false;
+        }
+        const int64_t t = since(t0);
+        last_done = t;
+        const int32_t* st = reinterpret_cast<const int32_t*>(s.out_h);
+        const int64_t* rs = reinterpret_cast<const int64_t*>(s.out_h + up256((size_t)maxb * 4));
+        const gputx_bulk_stats* bs =
+            reinterpret_cast<const gputx_bulk_stats*>(s.out_h + up256((size_t)maxb * 4) + up256((size_t)maxb * 8 * W));
+        for (int64_t j = 0; j < s.count; ++j) {
+            const int64_t k = (s.first + j) % cap;
+            r_status[k] = bs->error ? GPUTX_INVALID : st[j];
+            std::memcpy(&r_results[(size_t)k * W], rs + (size_t)j * W, sizeof(int64_t) * W);
+            r_done[k] = t;
+        }
+        {
+            std::lock_guard<std::mutex> lk(log_mu);
+            gputx_serve_bulk r{};
+            r.first = s.first;
+            r.count = s.count;
+            r.cut_ns = s.cut_ns;
+            r.done_ns = t;
+            r.error = bs->error;
+            r.slot = fifo[head];
+            log.push_back(r);
+            rep.committed += bs->committed;
+            rep.aborted += bs->aborted;
+            rep.invalid += bs->invalid - s.pad;  // padding is not part of the pool
+        }
+        if (bs->error)
+            set_error(bs->error, "bulk at ticket " + std::to_string(s.first) + " failed on the device");
+        answered.store(s.first + s.count, std::memory_order_release);
+        s.busy = false;
+        ++head;
+        block = false;
+    }
+    return true;
+}
+
+// Pack tickets [first, first + cnt) from the pool into slot si and launch it.
+bool gputx_server_t::issue(int si, int64_t first, int64_t cnt, int64_t now) {
+    Slot& s = slots[si];
+    int bi = 0;
+    while (sizes[bi] < cnt) ++bi;
+    const BucketLayout L = layout_for(sizes[bi], np);
+    int32_t* st = reinterpret_cast<int32_t*>(s.stage + L.off_type);
+    int64_t* sp = reinterpret_cast<int64_t*>(s.stage + L.off_params);
+    int64_t* sts = reinterpret_cast<int64_t*>(s.stage + L.off_ts);
+    // the ring may wrap inside the bulk: copy in at most two pieces
+    const int64_t k0 = first % cap;
+    const int64_t c0 = std::min(cnt, cap - k0), c1 = cnt - c0;
+    std::memcpy(st, &p_type[k0], c0 * 4);
+    if (c1) std::memcpy(st + c0, &p_type[0], c1 * 4);
+    std::fill(st + cnt, st + L.n, -1);  // padding: invalid transactions
+    for (int k = 0; k < np; ++k) {
+        int64_t* dst = sp + (int64_t)k * L.n;
+        const int64_t* src = &p_params[(size_t)k * cap];
+        std::memcpy(dst, src + k0, c0 * 8);
+        if (c1) std::memcpy(dst + c0, src, c1 * 8);
+        std::fill(dst + cnt, dst + L.n, 0);
+    }
+    std::memcpy(sts, &p_ts[k0], c0 * 8);
+    if (c1) std::memcpy(sts + c0, &p_ts[0], c1 * 8);
+    const int64_t tlast = sts[cnt - 1];
+    for (int64_t j = cnt; j < L.n; ++j) sts[j] = tlast + 1 + (j - cnt);
+    s.first = first;
+    s.count = cnt;
+    s.pad = L.n - cnt;
+    s.cut_ns = now;
+    s.busy = true;
+    char* oh = s.out_h;
+    const size_t o_res = up256((size_t)maxb * 4), o_stats = o_res + up256((size_t)maxb * 8 * W);
+    hipError_t e = hipMemcpyAsync(s.dev, s.stage, L.bytes, hipMemcpyHostToDevice, s.fs);
+    if (e == hipSuccess) e = hipGraphLaunch(s.front[bi], s.fs);
+    if (e == hipSuccess) e = hipEventRecord(s.ready, s.fs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(es, s.ready, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(s.exec[bi], es);
+    if (e == hipSuccess) e = hipMemcpyAsync(oh, s.dev + off_status, cnt * 4, hipMemcpyDeviceToHost, es);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(oh + o_res, s.dev + off_results, (size_t)cnt * 8 * W, hipMemcpyDeviceToHost, es);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(oh + o_stats, s.dev + off_stats, sizeof(gputx_bulk_stats), hipMemcpyDeviceToHost, es);
+    if (e == hipSuccess) e = hipEventRecord(s.done, es);
+    if (e != hipSuccess) {
+        set_error(GPUTX_E_HIP, std::string("issuing a bulk failed: ") + hipGetErrorString(e));
+        return false;
+    }
+    return true;
+}
+
+// The server thread: every interval, cut what the pool holds into a bulk.
+void gputx_server_t::run() {
+    (void)hipSetDevice(h->device);
+    const int64_t D = o.deadline_ns;
+    std::vector<int> fifo;  // in-flight slots in issue order
+    size_t head = 0;
+    int64_t issued = 0, deadline = D;
+    int next_slot = 0;
+    const int nslots = (int)slots.size();
+    while (true) {
+        if (!retire(fifo, head, false)) break;
+        if (head == fifo.size()) {  // nothing in flight: compact the fifo
+            fifo.clear();
+            head = 0;
+        }
+        const int64_t sub = submitted.load(std::memory_order_acquire);
+        const bool stopping = stop.load(std::memory_order_acquire);
+        if (stopping && issued == sub && head == fifo.size()) break;
+        const int64_t now = since(t0);
+        if (issued < sub && (now >= deadline || stopping)) {
+            if (slots[next_slot].busy) {  // admission: wait for the oldest bulk in flight
+                std::this_thread::yield();
+                continue;
+            }
+            const int64_t cnt = std::min(sub - issued, maxb);
+            if (!issue(next_slot, issued, cnt, now)) break;
+            fifo.push_back(next_slot);
+            next_slot = (next_slot + 1) % nslots;
+            issued += cnt;
+            if (issued == sub) deadline = (now / D) * D + D;
+        } else {
+            if (now >= deadline) deadline = (now / D) * D + D;
+            std::this_thread::yield();
+        }
+    }
+    (void)retire(fifo, head, true);
+    (void)hipStreamSynchronize(es);
+    std::lock_guard<std::mutex> lk(log_mu);
+    rep.n_bulks = (int64_t)log.size();
+    rep.elapsed_ns = last_done;
+    rep.slots_used = nslots;
+    rep.slot_bytes = (int64_t)slot_bytes;
+}
+
+extern "C" int gputx_serve_open(gputx_handle h, const gputx_serve_opts* o, int32_t n_params,
+                                int64_t pool_capacity, gputx_server* out) {
+    if (!h || !o || !out) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
+    *out = nullptr;
+    if (o->deadline_ns <= 0 || o->slots < 1 || o->max_bulk < 1 || o->width < 1 || n_params < 1 ||
+        n_params > GTX_MAX_PARAMS || o->strategy < GPUTX_AUTO || o->strategy > GPUTX_KSET || o->max_ops < 0 ||
+        pool_capacity < 1 || pool_capacity > ((int64_t)1 << 32))
+        return gtx_set_err(h, GPUTX_E_ARG, "bad serving options");
+    HIP_OK(h, hipSetDevice(h->device));
+    gputx_server_t* S = new gputx_server_t();
+    S->h = h;
+    S->o = *o;
+    S->np = n_params;
+    S->W = o->width;
+    S->cap = pool_capacity;
+    S->maxb = std::max<int64_t>(kMinBucket, (o->max_bulk + 255) / 256 * 256);
+    S->sizes = size_ladder(S->maxb);
+    S->maxb = S->sizes.back();
+    const int np = n_params, W = o->width;
+    const BucketLayout big = layout_for(S->maxb, np);
+    S->ws_bytes = gputx_workspace_size_ops(h, S->maxb, o->max_ops);
+    S->off_ws = up256(big.bytes);
+    S->off_status = S->off_ws + up256(S->ws_bytes);
+    S->off_results = S->off_status + up256((size_t)S->maxb * 4);
+    S->off_stats = S->off_results + up256((size_t)S->maxb * 8 * W);
+    S->slot_bytes = S->off_stats + up256(sizeof(gputx_bulk_stats));
+    int nslots = o->slots;
+    if (o->hbm_budget > 0) nslots = (int)std::min<int64_t>(nslots, o->hbm_budget / (int64_t)S->slot_bytes);
+    if (nslots < 1) {
+        const size_t sb = S->slot_bytes;
+        delete S;
+        return gtx_set_err(h, GPUTX_E_CAPACITY, "HBM budget below one slot (%zu bytes)", sb);
+    }
+    try {
+        S->p_type.assign((size_t)S->cap, -1);
+        S->p_params.assign((size_t)S->cap * np, 0);
+        S->p_ts.assign((size_t)S->cap, 0);
+        S->p_arrival.assign((size_t)S->cap, 0);
+        S->r_status.assign((size_t)S->cap, 0);
+        S->r_results.assign((size_t)S->cap * W, 0);
+        S->r_done.assign((size_t)S->cap, 0);
+    } catch (...) {
+        delete S;
+        return gtx_set_err(h, GPUTX_E_CAPACITY, "pool of %lld transactions does not fit in host memory",
+                           (long long)pool_capacity);
+    }
+    S->slots.resize(nslots);
+#define OPEN_OK(call)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) {                                                                   \
+            const int rc_ = gtx_set_err(h, GPUTX_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+            S->release();                                                                         \
+            delete S;                                                                             \
+            return rc_;                                                                           \
+        }                                                                                         \
+    } while (0)
+    OPEN_OK(hipStreamCreateWithFlags(&S->es, hipStreamNonBlocking));
     const int grid = gtx_grid_for(h, 1);
-    for (auto& s : slots) {
-        SERVE_OK(hipMalloc(&s.dev, slot_bytes));
-        SERVE_OK(hipHostMalloc(&s.stage, big.bytes, hipHostMallocDefault));
-        SERVE_OK(hipHostMalloc(&s.stats_h, sizeof(gputx_bulk_stats), hipHostMallocDefault));
-        SERVE_OK(hipStreamCreateWithFlags(&s.fs, hipStreamNonBlocking));
-        SERVE_OK(hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
-        SERVE_OK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
-        for (int64_t n : sizes) {
+    const size_t out_bytes = up256((size_t)S->maxb * 4) + up256((size_t)S->maxb * 8 * W) +
+                             up256(sizeof(gputx_bulk_stats));
+    for (auto& s : S->slots) {
+        OPEN_OK(hipMalloc(&s.dev, S->slot_bytes));
+        OPEN_OK(hipHostMalloc(&s.stage, big.bytes, hipHostMallocDefault));
+        OPEN_OK(hipHostMalloc(&s.out_h, out_bytes, hipHostMallocDefault));
+        OPEN_OK(hipStreamCreateWithFlags(&s.fs, hipStreamNonBlocking));
+        OPEN_OK(hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
+        OPEN_OK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        for (int64_t n : S->sizes) {
             const BucketLayout L = layout_for(n, np);
             gputx_bulk b{};
             b.n = n;
@@ -147,149 +373,158 @@ extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_se
             b.ts_sorted = 1;
             b.max_ops = o->max_ops;
             BulkArgs a;
-            rc = gtx_make_args(h, &b, o->strategy, s.dev + off_ws, ws_bytes,
-                               reinterpret_cast<int32_t*>(s.dev + off_status),
-                               reinterpret_cast<int64_t*>(s.dev + off_results), W,
-                               reinterpret_cast<gputx_bulk_stats*>(s.dev + off_stats), grid, &a);
+            int rc = gtx_make_args(h, &b, o->strategy, s.dev + S->off_ws, S->ws_bytes,
+                                   reinterpret_cast<int32_t*>(s.dev + S->off_status),
+                                   reinterpret_cast<int64_t*>(s.dev + S->off_results), W,
+                                   reinterpret_cast<gputx_bulk_stats*>(s.dev + S->off_stats), grid, &a);
             if (rc) {
-                release();
+                S->release();
+                delete S;
                 return rc;
             }
             PhaseMarks none;
             hipGraph_t gf = nullptr, ge = nullptr;
             hipGraphExec_t xf = nullptr, xe = nullptr;
-            SERVE_OK(hipStreamBeginCapture(s.fs, hipStreamCaptureModeThreadLocal));
+            OPEN_OK(hipStreamBeginCapture(s.fs, hipStreamCaptureModeThreadLocal));
             (void)launch_front(a, s.fs, none);
-            SERVE_OK(hipStreamEndCapture(s.fs, &gf));
+            OPEN_OK(hipStreamEndCapture(s.fs, &gf));
             s.graphs.push_back(gf);
-            SERVE_OK(hipGraphInstantiate(&xf, gf, nullptr, nullptr, 0));
+            OPEN_OK(hipGraphInstantiate(&xf, gf, nullptr, nullptr, 0));
             s.front.push_back(xf);
             // upload now, so that the first bulk of this size class on this
-            // slot does not pay for it in the middle of the trace
-            SERVE_OK(hipGraphUpload(xf, s.fs));
-            SERVE_OK(hipStreamBeginCapture(es, hipStreamCaptureModeThreadLocal));
-            launch_exec(a, es, none);
-            SERVE_OK(hipStreamEndCapture(es, &ge));
+            // slot does not pay for it while serving
+            OPEN_OK(hipGraphUpload(xf, s.fs));
+            OPEN_OK(hipStreamBeginCapture(S->es, hipStreamCaptureModeThreadLocal));
+            launch_exec(a, S->es, none);
+            OPEN_OK(hipStreamEndCapture(S->es, &ge));
             s.graphs.push_back(ge);
-            SERVE_OK(hipGraphInstantiate(&xe, ge, nullptr, nullptr, 0));
+            OPEN_OK(hipGraphInstantiate(&xe, ge, nullptr, nullptr, 0));
             s.exec.push_back(xe);
-            SERVE_OK(hipGraphUpload(xe, es));
+            OPEN_OK(hipGraphUpload(xe, S->es));
         }
     }
-    SERVE_OK(hipDeviceSynchronize());
-
-    const int64_t n = tr->n;
-    const int64_t D = o->deadline_ns;
-    std::vector<int> fifo;  // in-flight slots in issue order
-    fifo.reserve(nslots);
-    size_t head = 0;
-    int64_t next_first = 0, deadline = D, nb = 0, last_done = 0;
-    int next_slot = 0;
-    const Clock::time_point t0 = Clock::now();
-
-    auto retire = [&](bool block) -> int {
-        while (head < fifo.size()) {
-            Slot& s = slots[fifo[head]];
-            hipError_t q = block ? hipEventSynchronize(s.done) : hipEventQuery(s.done);
-            if (q == hipErrorNotReady) return GPUTX_OK;
-            if (q != hipSuccess) return gtx_set_err(h, GPUTX_E_HIP, "bulk completion: %s", hipGetErrorString(q));
-            const int64_t t = since(t0);
-            last_done = t;
-            if (nb < bulk_capacity && bulks) {
-                gputx_serve_bulk& r = bulks[nb];
-                r.first = s.first;
-                r.count = s.count;
-                r.cut_ns = s.cut_ns;
-                r.done_ns = t;
-                r.error = s.stats_h->error;
-                r.slot = fifo[head];
-            }
-            ++nb;
-            rep->committed += s.stats_h->committed;
-            rep->aborted += s.stats_h->aborted;
-            rep->invalid += s.stats_h->invalid - s.pad;  // padding is not part of the trace
-            if (s.stats_h->error && !rc) rc = gtx_set_err(h, s.stats_h->error, "bulk at %lld failed on the device", (long long)s.first);
-            s.busy = false;
-            ++head;
-            block = false;
-        }
-        return GPUTX_OK;
-    };
-
-    while (next_first < n || head < fifo.size()) {
-        int r2 = retire(false);
-        if (r2) {
-            rc = r2;
-            break;
-        }
-        const int64_t now = since(t0);
-        if (next_first < n && now >= deadline) {
-            Slot& s = slots[next_slot];
-            if (s.busy) {  // admission: wait for the oldest bulk in flight
-                std::this_thread::yield();
-                continue;
-            }
-            const int64_t boundary = (now / D) * D;  // latest passed bulk interval
-            const int64_t* last_p = std::lower_bound(tr->arrival_ns + next_first, tr->arrival_ns + n, boundary);
-            const int64_t last = last_p - tr->arrival_ns;
-            if (last == next_first) {
-                deadline = boundary + D;
-                continue;
-            }
-            const int64_t cnt = std::min<int64_t>(last - next_first, maxb);
-            int bi = 0;
-            while (sizes[bi] < cnt) ++bi;
-            const BucketLayout L = layout_for(sizes[bi], np);
-            // pack the bulk (param-major at its size class), padded with invalid
-            // transactions whose ids follow the bulk's last id
-            int32_t* st = reinterpret_cast<int32_t*>(s.stage + L.off_type);
-            int64_t* sp = reinterpret_cast<int64_t*>(s.stage + L.off_params);
-            int64_t* sts = reinterpret_cast<int64_t*>(s.stage + L.off_ts);
-            std::memcpy(st, tr->type + next_first, cnt * 4);
-            std::fill(st + cnt, st + L.n, -1);
-            for (int k = 0; k < np; ++k) {
-                std::memcpy(sp + (int64_t)k * L.n, tr->params + (int64_t)k * n + next_first, cnt * 8);
-                std::fill(sp + (int64_t)k * L.n + cnt, sp + (int64_t)(k + 1) * L.n, 0);
-            }
-            std::memcpy(sts, tr->ts + next_first, cnt * 8);
-            const int64_t tlast = tr->ts[next_first + cnt - 1];
-            for (int64_t j = cnt; j < L.n; ++j) sts[j] = tlast + 1 + (j - cnt);
-            s.first = next_first;
-            s.count = cnt;
-            s.pad = L.n - cnt;
-            s.cut_ns = now;
-            s.busy = true;
-            hipError_t e = hipMemcpyAsync(s.dev, s.stage, L.bytes, hipMemcpyHostToDevice, s.fs);
-            if (e == hipSuccess) e = hipGraphLaunch(s.front[bi], s.fs);
-            if (e == hipSuccess) e = hipEventRecord(s.ready, s.fs);
-            if (e == hipSuccess) e = hipStreamWaitEvent(es, s.ready, 0);
-            if (e == hipSuccess) e = hipGraphLaunch(s.exec[bi], es);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(status_out + next_first, s.dev + off_status, cnt * 4, hipMemcpyDeviceToHost, es);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(results_out + next_first * W, s.dev + off_results, (size_t)cnt * 8 * W,
-                                   hipMemcpyDeviceToHost, es);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(s.stats_h, s.dev + off_stats, sizeof(gputx_bulk_stats), hipMemcpyDeviceToHost, es);
-            if (e == hipSuccess) e = hipEventRecord(s.done, es);
-            if (e != hipSuccess) {
-                rc = gtx_set_err(h, GPUTX_E_HIP, "issuing a bulk failed: %s", hipGetErrorString(e));
-                break;
-            }
-            fifo.push_back(next_slot);
-            next_slot = (next_slot + 1) % nslots;
-            next_first += cnt;
-            if (next_first == last) deadline = boundary + D;
-        } else {
-            std::this_thread::yield();
-        }
+    OPEN_OK(hipDeviceSynchronize());
+#undef OPEN_OK
+    S->t0 = Clock::now();
+    try {
+        S->worker = std::thread([S] { S->run(); });
+    } catch (...) {
+        S->release();
+        delete S;
+        return gtx_set_err(h, GPUTX_E_STATE, "could not start the server thread");
     }
-    (void)retire(true);
-    (void)hipStreamSynchronize(es);
-    rep->n_bulks = nb;
-    rep->elapsed_ns = last_done;
-    rep->slots_used = nslots;
-    release();
-#undef SERVE_OK
+    *out = S;
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_serve_submit(gputx_server S, int64_t n, const int32_t* type, const int64_t* params,
+                                  int64_t ld, const int64_t* ts, int64_t* first_ticket) {
+    if (!S) return gtx_set_err(nullptr, GPUTX_E_ARG, "null server");
+    if (n < 0 || (n > 0 && (!type || !params || !ts)) || ld < n)
+        return gtx_set_err(S->h, GPUTX_E_ARG, "bad submission");
+    if (S->stop.load()) return gtx_set_err(S->h, GPUTX_E_STATE, "server is closing");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t prev = i ? ts[i - 1] : S->last_ts;
+        if ((i || S->any_ts) && ts[i] <= prev)
+            return gtx_set_err(S->h, GPUTX_E_ARG, "ids must ascend across submissions (at %lld)", (long long)i);
+    }
+    const int64_t sub = S->submitted.load(std::memory_order_relaxed);
+    if (sub + n - S->polled.load(std::memory_order_acquire) > S->cap)
+        return gtx_set_err(S->h, GPUTX_E_CAPACITY, "pool full: poll results first");
+    const int64_t now = since(S->t0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = (sub + i) % S->cap;
+        S->p_type[k] = type[i];
+        for (int q = 0; q < S->np; ++q) S->p_params[(size_t)q * S->cap + k] = params[(int64_t)q * ld + i];
+        S->p_ts[k] = ts[i];
+        S->p_arrival[k] = now;
+    }
+    if (n) {
+        S->last_ts = ts[n - 1];
+        S->any_ts = true;
+    }
+    if (first_ticket) *first_ticket = sub;
+    S->submitted.store(sub + n, std::memory_order_release);
+    return GPUTX_OK;
+}
+
+extern "C" int gputx_serve_poll(gputx_server S, int64_t max, int64_t* ticket, int32_t* status, int64_t* results,
+                                int64_t* latency_ns, int64_t* n_out) {
+    if (!S || !n_out || max < 0) return gtx_set_err(S ? S->h : nullptr, GPUTX_E_ARG, "bad poll");
+    *n_out = 0;
+    const int64_t done = S->answered.load(std::memory_order_acquire);
+    const int64_t p0 = S->polled.load(std::memory_order_relaxed);
+    const int64_t cnt = std::min(max, done - p0);
+    for (int64_t j = 0; j < cnt; ++j) {
+        const int64_t t = p0 + j, k = t % S->cap;
+        if (ticket) ticket[j] = t;
+        if (status) status[j] = S->r_status[k];
+        if (results) std::memcpy(results + (size_t)j * S->W, &S->r_results[(size_t)k * S->W], sizeof(int64_t) * S->W);
+        if (latency_ns) latency_ns[j] = S->r_done[k] - S->p_arrival[k];
+    }
+    S->polled.store(p0 + cnt, std::memory_order_release);
+    *n_out = cnt;
+    const int e = S->err.load();
+    if (e) {
+        std::lock_guard<std::mutex> lk(S->err_mu);
+        return gtx_set_err(S->h, e, "%s", S->err_msg.c_str());
+    }
+    return GPUTX_OK;
+}
+
+// Server clock (ns since open) and the bulk log, for the trace driver.
+static int64_t server_now(gputx_server S) { return since(S->t0); }
+
+extern "C" int gputx_serve_close(gputx_server S, gputx_serve_report* report) {
+    if (!S) return gtx_set_err(nullptr, GPUTX_E_ARG, "null server");
+    S->stop.store(true, std::memory_order_release);
+    if (S->worker.joinable()) S->worker.join();
+    int rc = GPUTX_OK;
+    const int e = S->err.load();
+    if (e) rc = gtx_set_err(S->h, e, "%s", S->err_msg.c_str());
+    if (report) *report = S->rep;
+    S->release();
+    delete S;
     return rc;
+}
+
+extern "C" int gputx_serve(gputx_handle h, const gputx_trace* tr, const gputx_serve_opts* o,
+                           int32_t* status_out, int64_t* results_out, gputx_serve_bulk* bulks,
+                           int64_t bulk_capacity, gputx_serve_report* rep) {
+    if (!h || !tr || !o || !rep || (tr->n > 0 && (!tr->arrival_ns || !tr->type || !tr->params ||
+                                                   !tr->ts || !status_out || !results_out)))
+        return gtx_set_err(h, GPUTX_E_ARG, "null argument");
+    for (int64_t i = 1; i < tr->n; ++i)
+        if (tr->arrival_ns[i] < tr->arrival_ns[i - 1] || tr->ts[i] <= tr->ts[i - 1])
+            return gtx_set_err(h, GPUTX_E_ARG, "trace must be in arrival order with ascending ids");
+    std::memset(rep, 0, sizeof *rep);
+    const int64_t n = tr->n;
+    gputx_server S = nullptr;
+    int rc = gputx_serve_open(h, o, tr->n_params, std::max<int64_t>(n, 1), &S);
+    if (rc) return rc;
+    const int W = o->width;
+    int64_t next = 0, got = 0;
+    std::vector<int64_t> tk(4096);
+    while (got < n) {
+        const int64_t now = server_now(S);
+        // release every transaction whose arrival time has passed
+        const int64_t last = std::upper_bound(tr->arrival_ns + next, tr->arrival_ns + n, now) - tr->arrival_ns;
+        if (last > next) {
+            rc = gputx_serve_submit(S, last - next, tr->type + next, tr->params + next, n, tr->ts + next, nullptr);
+            if (rc) break;
+            next = last;
+        }
+        int64_t k = 0;
+        rc = gputx_serve_poll(S, (int64_t)tk.size(), tk.data(), status_out + got, results_out + got * W, nullptr, &k);
+        got += k;
+        if (rc) break;
+        if (!k && last == next) std::this_thread::yield();
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->log_mu);
+        for (size_t b = 0; b < S->log.size() && (int64_t)b < bulk_capacity; ++b)
+            if (bulks) bulks[b] = S->log[b];
+    }
+    const int rc2 = gputx_serve_close(S, rep);
+    return rc ? rc : rc2;
 }

@@ -126,6 +126,8 @@ def _load() -> ctypes.CDLL:
         "gputx_workspace_size_ops": (c_size_t, [H, c_int64, c_int32]),
         "gputx_execute_bulk": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
                                          c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+        "gputx_execute_bulk_relaxed": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
+                                                 c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
         "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
         "gputx_set_row_count": (c_int32, [H, c_int32, c_int64, c_void_p]),
         "gputx_last_error": (ctypes.c_char_p, [H]),
@@ -137,6 +139,16 @@ def _load() -> ctypes.CDLL:
         "gputx_batch_destroy": (c_int32, [H]),
         "gputx_serve": (c_int32, [H, POINTER(Trace), POINTER(ServeOpts), c_void_p, c_void_p,
                                   POINTER(ServeBulk), c_int64, POINTER(ServeReport)]),
+        "gputx_serve_open": (c_int32, [H, POINTER(ServeOpts), c_int32, c_int64, POINTER(H)]),
+        "gputx_serve_submit": (c_int32, [H, c_int64, c_void_p, c_void_p, c_int64, c_void_p,
+                                         POINTER(c_int64)]),
+        "gputx_serve_poll": (c_int32, [H, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       POINTER(c_int64)]),
+        "gputx_serve_close": (c_int32, [H, POINTER(ServeReport)]),
+        "gputx_read_table": (c_int32, [H, c_int32, c_int32, c_int64, c_int64, c_void_p, c_void_p]),
+        "gputx_micro_workspace_size": (c_size_t, [c_int64]),
+        "gputx_micro_run": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
+                                      c_size_t, c_int32, c_void_p]),
         "gputx_probe_handoff": (c_int32, [c_int32, c_int32, c_int32, POINTER(ctypes.c_double)]),
         "gputx_probe_atomic_add": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
         "gputx_probe_gather": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
@@ -155,7 +167,9 @@ EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_
            "gputx_execute_bulk", "gputx_row_count", "gputx_set_row_count", "gputx_last_error", "gputx_phase_timing",
            "gputx_phase_times", "gputx_phase_name", "gputx_batch_create", "gputx_batch_launch",
            "gputx_batch_destroy", "gputx_serve", "gputx_probe_handoff", "gputx_probe_atomic_add",
-           "gputx_probe_gather")
+           "gputx_probe_gather", "gputx_serve_open",
+           "gputx_serve_submit", "gputx_serve_poll", "gputx_serve_close", "gputx_read_table",
+           "gputx_micro_workspace_size", "gputx_micro_run", "gputx_execute_bulk_relaxed")
 
 
 class GputxError(RuntimeError):
@@ -210,6 +224,10 @@ def gputx_workspace_size_ops(h, n: int, max_ops: int) -> int:
     return int(lib.gputx_workspace_size_ops(h, n, max_ops))
 
 
+def _stream(stream) -> int:
+    return (stream or torch.cuda.current_stream()).cuda_stream
+
+
 def gputx_execute_bulk(h, bulk: BulkDesc, strategy: int, workspace: torch.Tensor,
                        status: torch.Tensor, results: torch.Tensor, stats: torch.Tensor,
                        stream: Optional[torch.cuda.Stream] = None) -> None:
@@ -218,6 +236,60 @@ def gputx_execute_bulk(h, bulk: BulkDesc, strategy: int, workspace: torch.Tensor
                                      workspace.numel() * workspace.element_size(),
                                      status.data_ptr(), results.data_ptr(), results.shape[1],
                                      stats.data_ptr(), s))
+
+
+def gputx_execute_bulk_relaxed(h, bulk: BulkDesc, strategy: int, workspace: torch.Tensor,
+                               status: torch.Tensor, results: torch.Tensor, serial_key: torch.Tensor,
+                               stats: torch.Tensor, stream=None) -> None:
+    _check(h, lib.gputx_execute_bulk_relaxed(h, ctypes.byref(bulk), strategy, workspace.data_ptr(),
+                                             workspace.numel() * workspace.element_size(),
+                                             status.data_ptr(), results.data_ptr(), results.shape[1],
+                                             serial_key.data_ptr(), stats.data_ptr(), _stream(stream)))
+
+
+def gputx_serve_open(h, opts: ServeOpts, n_params: int, pool_capacity: int) -> c_void_p:
+    s = c_void_p()
+    _check(h, lib.gputx_serve_open(h, ctypes.byref(opts), n_params, pool_capacity, ctypes.byref(s)))
+    return s
+
+
+def gputx_serve_submit(h, s, type_arr: np.ndarray, params: np.ndarray, ts: np.ndarray) -> int:
+    """Submit host arrays (type[n] int32, params[P][n] int64, ts[n] int64);
+    returns the first ticket."""
+    n = int(type_arr.shape[0])
+    t = np.ascontiguousarray(type_arr, dtype=np.int32)
+    p = np.ascontiguousarray(params, dtype=np.int64)
+    x = np.ascontiguousarray(ts, dtype=np.int64)
+    first = c_int64()
+    _check(h, lib.gputx_serve_submit(s, n, t.ctypes.data, p.ctypes.data, p.shape[1] if p.ndim == 2 else n,
+                                     x.ctypes.data, ctypes.byref(first)))
+    return first.value
+
+
+def gputx_serve_poll(h, s, max_n: int, width: int):
+    """Up to max_n finished transactions: (tickets, status, results, latency_ns)."""
+    tk = np.zeros(max(max_n, 1), np.int64)
+    st = np.zeros(max(max_n, 1), np.int32)
+    rs = np.zeros((max(max_n, 1), width), np.int64)
+    lat = np.zeros(max(max_n, 1), np.int64)
+    got = c_int64()
+    _check(h, lib.gputx_serve_poll(s, max_n, tk.ctypes.data, st.ctypes.data, rs.ctypes.data,
+                                   lat.ctypes.data, ctypes.byref(got)))
+    k = got.value
+    return tk[:k], st[:k], rs[:k], lat[:k]
+
+
+def gputx_serve_close(h, s) -> "ServeReport":
+    rep = ServeReport()
+    _check(h, lib.gputx_serve_close(s, ctypes.byref(rep)))
+    return rep
+
+
+def gputx_read_table(h, table_id: int, col: int, row0: int, n: int, dtype, stream=None) -> np.ndarray:
+    out = np.zeros(max(n, 0), dtype=dtype)
+    _check(h, lib.gputx_read_table(h, table_id, col, row0, n, out.ctypes.data if n else None,
+                                   _stream(stream)))
+    return out
 
 
 def gputx_row_count(h, table_id: int, stream: Optional[torch.cuda.Stream] = None) -> int:
@@ -299,6 +371,19 @@ def gputx_probe_gather(device: int, table_bytes: int, n_gathers: int) -> float:
     v = ctypes.c_double()
     _check(None, lib.gputx_probe_gather(device, table_bytes, n_gathers, ctypes.byref(v)))
     return v.value
+
+
+def gputx_micro_workspace_size(n: int) -> int:
+    return int(lib.gputx_micro_workspace_size(n))
+
+
+def gputx_micro_run(type_arr: torch.Tensor, tuples: torch.Tensor, n_types: int, x: int, groups: int,
+                    workspace: Optional[torch.Tensor] = None, phase: int = 0, stream=None) -> None:
+    """Branch-divergence micro benchmark on device arrays (see the header)."""
+    n = int(type_arr.shape[0])
+    ws_ptr, ws_bytes = (workspace.data_ptr(), workspace.numel()) if workspace is not None else (None, 0)
+    _check(None, lib.gputx_micro_run(n, type_arr.data_ptr(), tuples.data_ptr(), n_types, x, groups,
+                                     ws_ptr, ws_bytes, phase, _stream(stream)))
 
 
 def stats_from(t: torch.Tensor) -> BulkStats:
@@ -411,6 +496,19 @@ class Engine:
         gputx_execute_bulk(self.h, self.bulk_desc(dev, ts_sorted), strategy, ws, status, results,
                            stats, stream)
         return status, results, stats
+
+    def execute_relaxed(self, dev: dict, strategy: int, width: int, stream=None):
+        """One bulk without the timestamp constraint (gputx_execute_bulk_relaxed).
+        Returns (status, results, serial_key, stats) device tensors."""
+        n = dev["type"].shape[0]
+        status = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        results = torch.empty((max(n, 1), width), dtype=torch.int64, device=self.device)
+        key = torch.empty(max(n, 1), dtype=torch.int64, device=self.device)
+        stats = torch.empty(STATS_BYTES, dtype=torch.uint8, device=self.device)
+        ws = self.workspace(max(n, 1))
+        gputx_execute_bulk_relaxed(self.h, self.bulk_desc(dev, False), strategy, ws, status, results, key,
+                                   stats, stream)
+        return status, results, key, stats
 
     def batch(self, jobs: Sequence[dict]) -> "Batch":
         """jobs: dicts with dev (device bulk), lane, strategy, width and

@@ -1,4 +1,5 @@
-"""Served form: a Poisson arrival trace answered by ``gputx_serve``.
+"""Served form: a live server (``gputx_serve_open`` / submit / poll / close)
+and a Poisson arrival trace replayed through it (``gputx_serve``).
 
 Arrivals follow a Poisson process of rate lambda; each arrival is a
 subscriber transaction (mix and key skew of the subscriber workload).  The
@@ -102,3 +103,39 @@ def serve(eng, trace: Trace, deadline_us: float, slots: int = 4, width: int = 14
         lat[f:f + c] = int(r["done_ns"]) - arrival[f:f + c]
     return ServeResult(st, res, recs, rep.committed, rep.aborted, rep.invalid, rep.elapsed_ns,
                        rep.slots_used, rep.slot_bytes, lat)
+
+
+class Server:
+    """A live server (``gputx_serve_open``): submit signatures as they
+    arrive, poll finished transactions in submission order, close when done.
+
+    Tickets are consecutive submission numbers starting at 0."""
+
+    def __init__(self, eng, n_params: int, width: int, deadline_us: float, slots: int = 4,
+                 strategy: int = 0, max_bulk: int = 1 << 17, hbm_budget: int = 0, max_ops: int = 1,
+                 pool_capacity: int = 1 << 20):
+        from . import gputx
+        self._g = gputx
+        self.eng = eng
+        self.width = width
+        o = gputx.ServeOpts()
+        o.deadline_ns = int(deadline_us * 1000)
+        o.slots = slots
+        o.strategy = strategy
+        o.max_bulk = max_bulk
+        o.hbm_budget = hbm_budget
+        o.width = width
+        o.max_ops = max_ops
+        self.s = gputx.gputx_serve_open(eng.h, o, n_params, pool_capacity)
+
+    def submit(self, type_arr, params, ts) -> int:
+        return self._g.gputx_serve_submit(self.eng.h, self.s, type_arr, params, ts)
+
+    def poll(self, max_n: int = 1 << 16):
+        return self._g.gputx_serve_poll(self.eng.h, self.s, max_n, self.width)
+
+    def close(self):
+        if self.s:
+            s, self.s = self.s, None
+            return self._g.gputx_serve_close(self.eng.h, s)
+        return None

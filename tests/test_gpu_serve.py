@@ -117,3 +117,107 @@ def test_served_alone_equals_in_the_mix():
     assert np.array_equal(r1.results, r4.results)
     for k in t1:
         assert all(np.array_equal(x, y) for x, y in zip(t1[k], t4[k])), k
+
+
+def test_live_server_submit_poll_matches_oracle():
+    """gputx_serve_open/submit/poll/close: signatures submitted in uneven
+    pieces while earlier bulks run, results polled as they finish.  Every
+    ticket's status and results, and the tables read back through
+    gputx_read_table, equal the oracle run over all submissions in order."""
+    import time
+    import torch
+    from paper_1103_3105_amd import gputx
+    rng = np.random.default_rng(34)
+    tabs = wl.sub_tables(rng, 10_000, occupancy=0.4)
+    bulk = wl.sub_bulk(rng, 30_000, 10_000, 0.8)
+    eng = gputx.Engine(tabs, wl.sub_types(), part_size=16)
+    got_t, got_s, got_r, got_l = [], [], [], []
+    try:
+        srv = serving.Server(eng, bulk.params.shape[0], 14, deadline_us=150, slots=3, max_bulk=4096,
+                             pool_capacity=40_000)
+        try:
+            pos, sizes = 0, [1, 7, 500, 3000, 64, 9000, 2500, 15000]
+            for k, m in enumerate(sizes):
+                m = min(m, bulk.n - pos)
+                first = srv.submit(bulk.type[pos:pos + m], bulk.params[:, pos:pos + m], bulk.ts[pos:pos + m])
+                assert first == pos
+                pos += m
+                time.sleep(0.0002 * (k % 3))
+                t, s, r, l = srv.poll()
+                got_t.append(t); got_s.append(s); got_r.append(r); got_l.append(l)
+            if pos < bulk.n:
+                srv.submit(bulk.type[pos:], bulk.params[:, pos:], bulk.ts[pos:])
+            deadline = time.time() + 30
+            while sum(len(x) for x in got_t) < bulk.n and time.time() < deadline:
+                t, s, r, l = srv.poll()
+                got_t.append(t); got_s.append(s); got_r.append(r); got_l.append(l)
+        finally:
+            rep = srv.close()
+        torch.cuda.synchronize()
+        g_sub = [gputx.gputx_read_table(eng.h, eng.table_id["subscriber"], c, 0, 10_000,
+                                        np.int64 if c == 0 else np.int32) for c in range(15)]
+        g_cf = [gputx.gputx_read_table(eng.h, eng.table_id["call_fwd"], c, 0, 120_000,
+                                       np.int64 if c == 2 else np.int32) for c in range(3)]
+    finally:
+        eng.close()
+    tk = np.concatenate(got_t)
+    assert np.array_equal(tk, np.arange(bulk.n))         # every ticket once, in order
+    o_tabs = util.copy_tables(tabs)
+    rc, o_st, o_res = oracle.run_serial(o_tabs, wl.sub_types(), bulk.type, bulk.params, bulk.ts, 14)
+    assert rc == 0
+    assert np.array_equal(np.concatenate(got_s), o_st)
+    assert np.array_equal(np.concatenate(got_r), o_res)
+    assert np.all(np.concatenate(got_l) > 0)
+    for c in range(15):
+        assert np.array_equal(g_sub[c], o_tabs["subscriber"].cols[c]), c
+    for c in range(3):
+        assert np.array_equal(g_cf[c], o_tabs["call_fwd"].cols[c]), c
+    assert rep.committed == int((o_st == 0).sum()) and rep.n_bulks >= 2
+
+
+def test_live_server_pool_capacity_and_order():
+    """A full pool refuses a submission (nothing taken) until results are
+    polled; ids that do not ascend are refused."""
+    import time
+    from paper_1103_3105_amd import gputx
+    rng = np.random.default_rng(35)
+    tabs = wl.sub_tables(rng, 2000, occupancy=0.4)
+    bulk = wl.sub_bulk(rng, 1500, 2000, 0.8)
+    eng = gputx.Engine(tabs, wl.sub_types(), part_size=16)
+    try:
+        srv = serving.Server(eng, bulk.params.shape[0], 14, deadline_us=100, slots=2, max_bulk=1024,
+                             pool_capacity=1000)
+        try:
+            srv.submit(bulk.type[:800], bulk.params[:, :800], bulk.ts[:800])
+            with pytest.raises(gputx.GputxError) as ei:
+                srv.submit(bulk.type[800:1100], bulk.params[:, 800:1100], bulk.ts[800:1100])
+            assert ei.value.code == gputx.E_CAPACITY
+            with pytest.raises(gputx.GputxError) as ei:   # id below the last one
+                srv.submit(bulk.type[:5], bulk.params[:, :5], bulk.ts[:5])
+            assert ei.value.code == gputx.E_ARG
+            n_got, deadline = 0, time.time() + 30
+            while n_got < 800 and time.time() < deadline:
+                n_got += len(srv.poll()[0])
+            assert n_got == 800
+            assert srv.submit(bulk.type[800:1100], bulk.params[:, 800:1100], bulk.ts[800:1100]) == 800
+        finally:
+            srv.close()
+    finally:
+        eng.close()
+
+
+def test_read_table_bounds():
+    from paper_1103_3105_amd import gputx
+    rng = np.random.default_rng(36)
+    tabs = wl.sub_tables(rng, 3000, occupancy=0.4)
+    eng = gputx.Engine(tabs, wl.sub_types(), part_size=16)
+    try:
+        tid = eng.table_id["subscriber"]
+        got = gputx.gputx_read_table(eng.h, tid, 3, 1000, 500, np.int32)
+        assert np.array_equal(got, tabs["subscriber"].cols[3][1000:1500])
+        for bad in ((tid, 3, 2900, 200), (tid, 99, 0, 1), (31, 0, 0, 1), (tid, 0, -1, 2)):
+            with pytest.raises(gputx.GputxError) as ei:
+                gputx.gputx_read_table(eng.h, *bad, np.int64)
+            assert ei.value.code == gputx.E_ARG
+    finally:
+        eng.close()
