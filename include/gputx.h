@@ -266,7 +266,24 @@ int gputx_execute_bulk_relaxed(gputx_handle h, const gputx_bulk* b, int strategy
                                size_t ws_bytes, int32_t* status_out, int64_t* results_out, int32_t width,
                                int64_t* serial_key_out, gputx_bulk_stats* stats, gputx_stream_t stream);
 
-
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * bulk execution as gputx_execute_bulk, with its workspace in a static
+ * device array of GPUTX_SCRATCH_BYTES (64 MiB) that each GPU the library
+ * runs on holds until the process ends.  The call allocates nothing; the
+ * caller still passes the bulk and the outputs.
+ *   Bulks whose workspace (gputx_workspace_size_ops(h, b->n, b->max_ops))
+ *   exceeds GPUTX_SCRATCH_BYTES are rejected with GPUTX_E_CAPACITY before
+ *   anything is launched (e.g. about 2^17 debit-credits fit).
+ *   Every call on one GPU uses that GPU's one array: calls that overlap on
+ *   one GPU (other streams, other contexts, other host threads) race and
+ *   must be serialised by the caller.  Nothing needs to start at zero: each
+ *   bulk clears the state it reads.
+ * Other arguments, ordering and errors as gputx_execute_bulk. */
+#define GPUTX_SCRATCH_BYTES ((size_t)64 << 20)
+int gputx_execute_bulk_noalloc(gputx_handle h, const gputx_bulk* b, int strategy,
+                               int32_t* status_out, int64_t* results_out, int32_t width,
+                               gputx_bulk_stats* stats, gputx_stream_t stream);
 
 /* ---- batched form: many bulks, one graph launch ------------------------
  * Each item is one bulk with its own workspace and outputs.  Items of one

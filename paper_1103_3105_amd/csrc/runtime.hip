@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,27 @@ extern "C" int gputx_default_options(gputx_options* o) {
 
 static int refresh_layout(gputx_handle h);
 
+// ---- workspace for callers that cannot allocate ----------------------------
+// gputx_execute_bulk_noalloc runs a bulk with its workspace in this array.
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// device address of each GPU's copy is taken once per device when a context
+// is created (with that device current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[GPUTX_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static int scratch_init(int dev) {
+    if (dev < 0 || dev >= 64) return gtx_set_err(nullptr, GPUTX_E_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return GPUTX_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return gtx_set_err(nullptr, GPUTX_E_HIP, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+    return GPUTX_OK;
+}
+
 extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out) {
     if (!out) return gtx_set_err(nullptr, GPUTX_E_ARG, "out is null");
     *out = nullptr;
@@ -96,6 +118,11 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     h->ncu = ncu;
     h->wall_khz = khz > 0 ? (uint64_t)khz : 100000;
     exec_init_attributes(dev);
+    const int src = scratch_init(dev);  // device current: this GPU's copy of the array
+    if (src) {
+        gputx_destroy(h);
+        return src;
+    }
     *out = h;
     return GPUTX_OK;
 }
@@ -621,6 +648,26 @@ extern "C" int gputx_execute_bulk_relaxed(gputx_handle h, const gputx_bulk* b, i
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return gtx_set_err(h, GPUTX_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
     return GPUTX_OK;
+}
+
+extern "C" int gputx_execute_bulk_noalloc(gputx_handle h, const gputx_bulk* b, int strategy,
+                                          int32_t* status_out, int64_t* results_out, int32_t width,
+                                          gputx_bulk_stats* stats, gputx_stream_t stream) {
+    if (!h || !b) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
+    if (b->n < 0 || b->max_ops < 0) return gtx_set_err(h, GPUTX_E_ARG, "bad bulk");
+    const size_t need = gputx_workspace_size_ops(h, b->n, b->max_ops);
+    if (need > (size_t)GPUTX_SCRATCH_BYTES)
+        return gtx_set_err(h, GPUTX_E_CAPACITY,
+                           "bulk of %lld transactions needs %zu workspace bytes; the static workspace holds %zu",
+                           (long long)b->n, need, (size_t)GPUTX_SCRATCH_BYTES);
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ws = (h->device >= 0 && h->device < 64) ? g_scratch_ptr[h->device] : nullptr;
+    }
+    if (!ws) return gtx_set_err(h, GPUTX_E_STATE, "no static workspace address for device %d", h->device);
+    return gputx_execute_bulk(h, b, strategy, ws, (size_t)GPUTX_SCRATCH_BYTES, status_out, results_out, width,
+                              stats, stream);
 }
 
 // ---- batched form: many bulks in one HIP graph ------------------------------

@@ -128,6 +128,8 @@ def _load() -> ctypes.CDLL:
                                          c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
         "gputx_execute_bulk_relaxed": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_size_t,
                                                  c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p]),
+        "gputx_execute_bulk_noalloc": (c_int32, [H, POINTER(BulkDesc), c_int32, c_void_p, c_void_p,
+                                                 c_int32, c_void_p, c_void_p]),
         "gputx_row_count": (c_int32, [H, c_int32, POINTER(c_int64), c_void_p]),
         "gputx_set_row_count": (c_int32, [H, c_int32, c_int64, c_void_p]),
         "gputx_last_error": (ctypes.c_char_p, [H]),
@@ -167,9 +169,10 @@ EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_
            "gputx_execute_bulk", "gputx_row_count", "gputx_set_row_count", "gputx_last_error", "gputx_phase_timing",
            "gputx_phase_times", "gputx_phase_name", "gputx_batch_create", "gputx_batch_launch",
            "gputx_batch_destroy", "gputx_serve", "gputx_probe_handoff", "gputx_probe_atomic_add",
-           "gputx_probe_gather", "gputx_serve_open",
+           "gputx_probe_gather", "gputx_execute_bulk_noalloc", "gputx_serve_open",
            "gputx_serve_submit", "gputx_serve_poll", "gputx_serve_close", "gputx_read_table",
            "gputx_micro_workspace_size", "gputx_micro_run", "gputx_execute_bulk_relaxed")
+SCRATCH_BYTES = 64 << 20   # GPUTX_SCRATCH_BYTES: static workspace of gputx_execute_bulk_noalloc
 
 
 class GputxError(RuntimeError):
@@ -245,6 +248,13 @@ def gputx_execute_bulk_relaxed(h, bulk: BulkDesc, strategy: int, workspace: torc
                                              workspace.numel() * workspace.element_size(),
                                              status.data_ptr(), results.data_ptr(), results.shape[1],
                                              serial_key.data_ptr(), stats.data_ptr(), _stream(stream)))
+
+
+def gputx_execute_bulk_noalloc(h, bulk: BulkDesc, strategy: int, status: torch.Tensor,
+                               results: torch.Tensor, stats: torch.Tensor, stream=None) -> None:
+    _check(h, lib.gputx_execute_bulk_noalloc(h, ctypes.byref(bulk), strategy, status.data_ptr(),
+                                             results.data_ptr(), results.shape[1], stats.data_ptr(),
+                                             _stream(stream)))
 
 
 def gputx_serve_open(h, opts: ServeOpts, n_params: int, pool_capacity: int) -> c_void_p:
@@ -509,6 +519,22 @@ class Engine:
         gputx_execute_bulk_relaxed(self.h, self.bulk_desc(dev, False), strategy, ws, status, results, key,
                                    stats, stream)
         return status, results, key, stats
+
+    def execute_noalloc(self, dev: dict, strategy: int, width: int, ts_sorted: bool = False,
+                        status: Optional[torch.Tensor] = None, results: Optional[torch.Tensor] = None,
+                        stats: Optional[torch.Tensor] = None, stream=None):
+        """Launch one bulk through gputx_execute_bulk_noalloc (workspace in the
+        library's static device array).  Returns (status, results, stats)."""
+        n = dev["type"].shape[0]
+        if status is None:
+            status = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        if results is None:
+            results = torch.empty((max(n, 1), width), dtype=torch.int64, device=self.device)
+        if stats is None:
+            stats = torch.empty(STATS_BYTES, dtype=torch.uint8, device=self.device)
+        gputx_execute_bulk_noalloc(self.h, self.bulk_desc(dev, ts_sorted), strategy, status, results,
+                                   stats, stream)
+        return status, results, stats
 
     def batch(self, jobs: Sequence[dict]) -> "Batch":
         """jobs: dicts with dev (device bulk), lane, strategy, width and
