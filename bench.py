@@ -573,6 +573,9 @@ def main():
                     help="PART's per-cell map scan for cellwise procedures (1) or Section 5.2's "
                          "one-after-another run throughout (0)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines")
+    ap.add_argument("--no-part-forms", action="store_true",
+                    help="skip timing PART in both forms on the headline bulk (for kernel profiles "
+                         "of the headline configuration alone)")
     ap.add_argument("--part-pipeline", type=int, default=1, choices=[0, 1],
                     help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
@@ -692,7 +695,7 @@ def main():
 
     # Section 5.2's PART (one after another) beside the scan form, same bulk
     part_forms = None
-    if args.workload == "bank":
+    if args.workload == "bank" and not args.no_part_forms:
         part_forms = {}
         for scan in (0, 1):
             eng.set_options(part_scan=scan)

@@ -95,6 +95,11 @@ enum {
  *   UPD_SUB_FIELD (sid, f < 4, v) / UPD_LOC (sid, l < 10, v) -> previous value.
  *   INS_CF (sid, slot, end, number): ABORT if occupied; -> (previous occupied).
  *   DEL_CF (sid, slot): ABORT if empty; -> (1, end, number) of the deleted row.
+ *   NEW_ORDER_RB (same signature as NEW_ORDER): new-order that is NOT
+ *       two-phase (Appendix D): an item id equal to ipw names an unused item;
+ *       the procedure updates the stock of the items before it in order,
+ *       meets the unused one, and rolls those updates back from its undo log:
+ *       ABORT, no effect, results 0.  Otherwise as NEW_ORDER.  Items <= ipw.
  * Dimensions are derived from the bound tables: ipw = stock rows / warehouses,
  * dpw = districts / warehouses, cpd = customers / districts; a call_fwd slot is
  * sid * 12 + slot.  Arithmetic on int64 values wraps modulo 2^64.
@@ -109,7 +114,8 @@ enum {
     GPUTX_UPD_SUB_FIELD = 7,
     GPUTX_UPD_LOC = 8,
     GPUTX_INS_CF = 9,
-    GPUTX_DEL_CF = 10
+    GPUTX_DEL_CF = 10,
+    GPUTX_NEW_ORDER_RB = 11
 };
 
 enum { GPUTX_I32 = 1, GPUTX_I64 = 2 };
@@ -303,6 +309,11 @@ typedef struct {
     int64_t* results_out;       /* device int64[n][width]                           */
     int32_t width;
     gputx_bulk_stats* stats;    /* device                                           */
+    int32_t grid_blocks;        /* persistent grid of this bulk's lock / k-set executor
+                                   (0: the context's; capped so that every lane's grid
+                                   stays resident)                                  */
+    int32_t kset_narrow;        /* K-SET narrow-wave width for this bulk (0: the
+                                   context's)                                       */
 } gputx_batch_item;
 
 typedef struct gputx_batch_t* gputx_batch;
@@ -474,6 +485,58 @@ int gputx_set_row_count(gputx_handle h, int32_t table_id, int64_t n, gputx_strea
 int gputx_probe_handoff(int hip_device, int32_t hops, int32_t same_xcd, double* ns_per_hop);
 int gputx_probe_atomic_add(int hip_device, int64_t n_addr, int64_t n_updates, double* updates_per_s);
 int gputx_probe_gather(int hip_device, int64_t table_bytes, int64_t n_gathers, double* gb_per_s);
+
+/* ---- K-SET over a standing pool (Section 5.3, incremental k-set) --------
+ * A pool holds pending transactions across bulks.  gputx_pool_add puts a
+ * bulk in (its basic operations are sorted and merged into the pool's
+ * operations, sorted by item and timestamp); gputx_pool_step runs the pool's
+ * 0-set -- every pending transaction none of whose operations has a
+ * conflicting predecessor still pending -- without locks and removes it, as
+ * many times as asked.  The 1-set then becomes the 0-set, so any
+ * interleaving of adds and steps executes the transactions with the result
+ * of running them serially in timestamp order (Definition 1): bulks must be
+ * added in timestamp order (every id above those already added).  Results
+ * stay in the pool until fetched, in sequence order.  A bulk error
+ * (duplicate or out-of-order ids, append overflow) puts the pool in an error
+ * state: nothing runs afterwards.  Appended rows are reserved when a bulk is
+ * added (in timestamp order) and written when their transaction runs. */
+typedef struct gputx_pool_t* gputx_pool;
+
+typedef struct {
+    int32_t error;        /* sticky bulk error, 0 = none                      */
+    int32_t reserved;
+    int64_t added;        /* transactions added (their sequence numbers 0..)  */
+    int64_t done_prefix;  /* every transaction below this has run            */
+    int64_t pending_ops;  /* operations of pending transactions              */
+    int64_t waves;        /* steps that ran at least one transaction         */
+    int64_t executed;     /* transactions run by steps                       */
+    int64_t committed;
+    int64_t aborted;
+    int64_t invalid;      /* invalid transactions (done when added)          */
+    int64_t last_width;   /* transactions the last step ran                  */
+    int64_t fetched;      /* results handed back                             */
+} gputx_pool_stats;
+
+/* Create a pool for up to `capacity` transactions added and not yet fetched
+ * (rounded up to a power of two), bulks of at most max_add transactions with
+ * n_params parameters, results of `width` values, max_ops operations per
+ * transaction (0: the context's maximum).  Allocates device memory. */
+int gputx_pool_create(gputx_handle h, int64_t capacity, int32_t n_params, int32_t width, int32_t max_ops,
+                      int64_t max_add, gputx_pool* out);
+/* Add a bulk (device arrays as for gputx_execute_bulk); ordered on the
+ * stream.  GPUTX_E_CAPACITY (host-side) when the pool lacks free slots. */
+int gputx_pool_add(gputx_pool p, const gputx_bulk* b, gputx_stream_t stream);
+/* Run `waves` successive 0-sets; ordered on the stream. */
+int gputx_pool_step(gputx_pool p, int32_t waves, gputx_stream_t stream);
+/* Counters of the pool (synchronises the stream). */
+int gputx_pool_state(gputx_pool p, gputx_pool_stats* out, gputx_stream_t stream);
+/* Copy the status and results of the next n transactions in sequence order
+ * (all of them must have run: n <= done_prefix - fetched) into status[n],
+ * results[n][width] (host or device); their slots become free.
+ * GPUTX_E_STATE when fewer have run.  Synchronises the stream. */
+int gputx_pool_results(gputx_pool p, int64_t n, int32_t* status, int64_t* results, gputx_stream_t stream);
+/* Free the pool (synchronises the device). */
+int gputx_pool_destroy(gputx_pool p);
 
 /* ---- branch-divergence micro benchmark (Section 6.2, Figures 3 and 12) --
  * n independent transactions; transaction i has type type[i] in [0, n_types)

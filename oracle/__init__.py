@@ -35,7 +35,7 @@ ROLES = ("account", "teller", "branch", "history", "warehouse", "district", "cus
          "stock", "orders", "order_line", "subscriber", "call_fwd")
 PROC_ID = {name: i + 1 for i, name in enumerate(
     ("DEBIT_CREDIT", "NEW_ORDER", "PAYMENT", "ORDER_STATUS", "GET_SUB", "GET_CF",
-     "UPD_SUB_FIELD", "UPD_LOC", "INS_CF", "DEL_CF"))}
+     "UPD_SUB_FIELD", "UPD_LOC", "INS_CF", "DEL_CF", "NEW_ORDER_RB"))}
 OK, E_ARG, E_DUP_TS, E_CAPACITY = 0, -1, -3, -4
 COMMIT, ABORT, INVALID = 0, 1, 2
 

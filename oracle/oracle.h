@@ -16,7 +16,8 @@ enum { ORC_COMMIT = 0, ORC_ABORT = 1, ORC_INVALID = 2 };
 /* procedures (registered types map onto these) */
 enum {
     ORC_DEBIT_CREDIT = 1, ORC_NEW_ORDER, ORC_PAYMENT, ORC_ORDER_STATUS,
-    ORC_GET_SUB, ORC_GET_CF, ORC_UPD_SUB_FIELD, ORC_UPD_LOC, ORC_INS_CF, ORC_DEL_CF
+    ORC_GET_SUB, ORC_GET_CF, ORC_UPD_SUB_FIELD, ORC_UPD_LOC, ORC_INS_CF, ORC_DEL_CF,
+    ORC_NEW_ORDER_RB
 };
 
 /* table roles */
@@ -70,7 +71,7 @@ int orc_execute_partitioned(int64_t n, const int32_t* type, const int64_t* param
 
 /* Pieces of the serial executor the partitioned one reuses (serial.c). */
 int orc_is_valid(int proc, const int64_t* p, const orc_table* R);
-void orc_appends_of(int proc, const int64_t* p, int64_t* h, int64_t* o, int64_t* ol);
+void orc_appends_of(int proc, const int64_t* p, const orc_table* R, int64_t* h, int64_t* o, int64_t* ol);
 int32_t orc_run_one(int proc, const int64_t* p, int64_t ts, orc_table* R, int64_t* res);
 
 #ifdef __cplusplus

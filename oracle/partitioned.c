@@ -120,7 +120,7 @@ static void* pt_worker(void* arg) {
         load_params(J, i, p);
         J->ok[i] = (unsigned char)(proc > 0 && orc_is_valid(proc, p, J->tables));
         int64_t h = 0, o = 0, l = 0;
-        if (J->ok[i]) orc_appends_of(proc, p, &h, &o, &l);
+        if (J->ok[i]) orc_appends_of(proc, p, J->tables, &h, &o, &l);
         J->slot[i] = h;
         J->slot[n + i] = o;
         J->slot[2 * n + i] = l;

@@ -58,16 +58,18 @@ def valid(proc: str, p: Sequence[int], sizes: Dict[str, int]) -> bool:
     if proc == "DEBIT_CREDIT":
         return (_in(p[0], sizes.get("account", 0)) and _in(p[1], sizes.get("teller", 0))
                 and _in(p[2], sizes.get("branch", 0)))
-    if proc in ("NEW_ORDER", "PAYMENT", "ORDER_STATUS"):
+    if proc in ("NEW_ORDER", "NEW_ORDER_RB", "PAYMENT", "ORDER_STATUS"):
         d = _dims(sizes)
         if d is None or not (_in(p[0], d["nw"]) and _in(p[1], d["dpw"]) and _in(p[2], d["cpd"])):
             return False
-        if proc != "NEW_ORDER":
+        if proc not in ("NEW_ORDER", "NEW_ORDER_RB"):
             return True
         k = p[3]
         if not 1 <= k <= NO_MAX_ITEMS:
             return False
-        return all(_in(p[4 + j], d["ipw"]) and 1 <= p[4 + NO_MAX_ITEMS + j] <= 1000
+        # the variant that is not two-phase also names the unused item id ipw
+        items = d["ipw"] + (1 if proc == "NEW_ORDER_RB" else 0)
+        return all(_in(p[4 + j], items) and 1 <= p[4 + NO_MAX_ITEMS + j] <= 1000
                    for j in range(k))
     ns = sizes.get("subscriber", 0)
     if proc == "GET_SUB":
@@ -89,12 +91,13 @@ def raw_accesses(proc: str, p: Sequence[int], sizes: Dict[str, int]) -> List[Tup
     any transaction reads, so they are not listed."""
     if proc == "DEBIT_CREDIT":
         return [("account", p[0], True), ("teller", p[1], True), ("branch", p[2], True)]
-    if proc in ("NEW_ORDER", "PAYMENT", "ORDER_STATUS"):
+    if proc in ("NEW_ORDER", "NEW_ORDER_RB", "PAYMENT", "ORDER_STATUS"):
         d = _dims(sizes)
         drow = p[0] * d["dpw"] + p[1]
         crow = drow * d["cpd"] + p[2]
-        if proc == "NEW_ORDER":
-            return [("stock", p[0] * d["ipw"] + p[4 + j], True) for j in range(p[3])]
+        if proc in ("NEW_ORDER", "NEW_ORDER_RB"):   # the unused item has no row
+            return [("stock", p[0] * d["ipw"] + p[4 + j], True) for j in range(p[3])
+                    if p[4 + j] < d["ipw"]]
         if proc == "PAYMENT":
             return [("warehouse", p[0], True), ("district", drow, True), ("customer", crow, True)]
         return [("customer", crow, False)]
@@ -362,11 +365,13 @@ def py_execute(tables: Dict[str, object], types, type_arr, params, ts, width: in
                 H.cols[c][H.n_rows] = v
             H.n_rows += 1
             res[:3] = [int(A[p[0]]), int(T[p[1]]), int(B[p[2]])]
-        elif proc in ("NEW_ORDER", "PAYMENT", "ORDER_STATUS"):
+        elif proc == "NEW_ORDER_RB" and any(p[4 + j] == _dims(sizes)["ipw"] for j in range(p[3])):
+            st = ABORT   # rolled back: no effect, results 0 (Appendix D)
+        elif proc in ("NEW_ORDER", "NEW_ORDER_RB", "PAYMENT", "ORDER_STATUS"):
             d = _dims(sizes)
             drow = p[0] * d["dpw"] + p[1]
             crow = drow * d["cpd"] + p[2]
-            if proc == "NEW_ORDER":
+            if proc in ("NEW_ORDER", "NEW_ORDER_RB"):
                 S = tables["stock"].cols[0]
                 L, O = tables["order_line"], tables["orders"]
                 res[0] = p[3]

@@ -59,11 +59,22 @@ static int order_dims(const orc_table* R, orc_odims* d) {
     return 1;
 }
 
+/* A new-order that is not two-phase (Appendix D) rolls back when one of its
+ * items is the unused item id; a rolled-back transaction has no effect. */
+static int names_unused_item(const int64_t* p, const orc_table* R) {
+    orc_odims od = {0, 0, 0, 0};
+    if (!order_dims(R, &od)) return 0;
+    for (int64_t j = 0; j < p[3] && j < ORC_NO_MAX_ITEMS; ++j)
+        if (p[4 + j] == od.ipw) return 1;   /* the unused item id */
+    return 0;
+}
+
 /* Number of rows a valid transaction appends to history / orders / order_line. */
-void orc_appends_of(int proc, const int64_t* p, int64_t* h, int64_t* o, int64_t* ol) {
+void orc_appends_of(int proc, const int64_t* p, const orc_table* R, int64_t* h, int64_t* o, int64_t* ol) {
     *h = *o = *ol = 0;
     if (proc == ORC_DEBIT_CREDIT) *h = 1;
     if (proc == ORC_NEW_ORDER) { *o = 1; *ol = p[3]; }
+    if (proc == ORC_NEW_ORDER_RB && !names_unused_item(p, R)) { *o = 1; *ol = p[3]; }
 }
 
 /* Parameter validity (INVALID otherwise). */
@@ -74,11 +85,13 @@ int orc_is_valid(int proc, const int64_t* p, const orc_table* R) {
         return in_range(p[0], R[ORC_R_ACCOUNT].n_rows) && in_range(p[1], R[ORC_R_TELLER].n_rows) &&
                in_range(p[2], R[ORC_R_BRANCH].n_rows);
     case ORC_NEW_ORDER:
+    case ORC_NEW_ORDER_RB:
         if (!order_dims(R, &od)) return 0;
         if (!(in_range(p[0], od.nw) && in_range(p[1], od.dpw) && in_range(p[2], od.cpd))) return 0;
         if (p[3] < 1 || p[3] > ORC_NO_MAX_ITEMS) return 0;
         for (int64_t j = 0; j < p[3]; ++j) {
-            if (!in_range(p[4 + j], od.ipw)) return 0;
+            /* the rollback variant also names the unused item id ipw */
+            if (!in_range(p[4 + j], od.ipw + (proc == ORC_NEW_ORDER_RB))) return 0;
             if (p[4 + ORC_NO_MAX_ITEMS + j] < 1 || p[4 + ORC_NO_MAX_ITEMS + j] > 1000) return 0;
         }
         return 1;
@@ -128,6 +141,11 @@ int32_t orc_run_one(int proc, const int64_t* p, int64_t ts, orc_table* R, int64_
         res[2] = B[p[2]];
         return ORC_COMMIT;
     }
+    case ORC_NEW_ORDER_RB:
+        /* rolls back when it names the unused item: no effect at all */
+        if (names_unused_item(p, R)) return ORC_ABORT;
+        /* otherwise exactly a new-order */
+        __attribute__((fallthrough));
     case ORC_NEW_ORDER: {
         order_dims(R, &od);
         int32_t* S = I32(&R[ORC_R_STOCK], 0);
@@ -253,7 +271,7 @@ int orc_execute(int64_t n, const int32_t* type, const int64_t* params, int32_t n
         ok[i] = (unsigned char)(proc > 0 && orc_is_valid(proc, p, tables));
         if (ok[i]) {
             int64_t h, o, ol;
-            orc_appends_of(proc, p, &h, &o, &ol);
+            orc_appends_of(proc, p, tables, &h, &o, &ol);
             need_h += h; need_o += o; need_ol += ol;
         }
     }

@@ -7,6 +7,11 @@ bulk's features (w0, depth, cross-partition count c) and each strategy's
 time, and picks the thresholds that minimise the total time Algorithm 1
 would have spent on the samples.  It also picks K-SET's narrow-wave width
 and the persistent grid size from a small candidate set.
+
+``tune_buckets`` tunes per bulk shape instead (database and size class): for
+each bucket it times a sample bulk under every executor and a set of launch
+shapes (persistent grid, K-SET narrow-wave width) and keeps the fastest; the
+batched form then runs every bulk with its bucket's choice.
 """
 from __future__ import annotations
 
@@ -114,3 +119,69 @@ def calibrate(tables, types, sample_bulks: Sequence[tuple], narrow=(64, 256, 102
     th.update(kset_narrow=best_narrow, grid_blocks=best_grid,
               samples=[dataclasses.asdict(s) for s in samples])
     return th
+
+
+def bucket_of(db: str, n: int) -> tuple:
+    """Shape bucket of a bulk: its database and the power of two below its size."""
+    return (db, max(0, int(n).bit_length() - 1))
+
+
+def tune_buckets(tables, types, jobs: Sequence[tuple], width: Dict[str, int], max_ops: Dict[str, int],
+                 grids=(64, 128, 256, 512), narrow=(64, 256, 1024), log=None, engine_opts=None) -> dict:
+    """Per shape bucket (database, log2 of the bulk size), the executor and
+    launch shape that ran a sample bulk of the bucket fastest on a scratch
+    copy of the database: strategy (TPL, PART or K-SET), the persistent grid
+    of TPL and K-SET, and K-SET's narrow-wave width.
+
+    jobs: (db, Bulk) pairs; the sample of a bucket is its median-size bulk.
+    A launch shape is tried only for an executor that came within twice the
+    best time so far with the default shape.  Returns {bucket: {strategy,
+    grid_blocks, kset_narrow, ms, tried}}."""
+    from . import gputx
+    by_bucket: Dict[tuple, list] = {}
+    for db, b in jobs:
+        by_bucket.setdefault(bucket_of(db, b.n), []).append((db, b))
+    scratch = {k: v.copy() for k, v in tables.items()}
+    biggest = max(b.n for _, b in jobs)
+    for t in scratch.values():
+        if t.append:
+            cap = biggest * 16
+            t.cols = [np.zeros(cap, c.dtype) for c in t.cols]
+            t.capacity, t.n_rows = cap, 0
+    eng = gputx.Engine(scratch, types, **(engine_opts or {}))
+    out = {}
+    try:
+        for key in sorted(by_bucket):
+            group = sorted(by_bucket[key], key=lambda j: j[1].n)
+            db, b = group[len(group) // 2]
+            dev = eng.bulk_to_device(b)
+            tried = {}
+
+            def run(strat, gb, nw):
+                eng.set_options(grid_blocks=gb, kset_narrow=nw)
+                ms, _ = _time(eng, dev, strat, width[db], max_ops[db], reps=1)
+                tried[f"{strat}/{gb}/{nw}"] = round(ms, 4)
+                return ms
+
+            best = ("PART", 0, 256, run("PART", 0, 256))
+            for strat in ("TPL", "KSET"):
+                ms = run(strat, 0, 256)
+                if ms < best[3]:
+                    best = (strat, 0, 256, ms)
+                if ms > 2 * best[3]:
+                    continue
+                for gb in grids:
+                    for nw in (narrow if strat == "KSET" else (256,)):
+                        if (gb, nw) == (0, 256):
+                            continue
+                        m2 = run(strat, gb, nw)
+                        if m2 < best[3]:
+                            best = (strat, gb, nw, m2)
+            out[key] = dict(strategy=best[0], grid_blocks=best[1], kset_narrow=best[2],
+                            ms=round(best[3], 4), tried=tried, sample_n=b.n)
+            if log:
+                log(f"[tune] bucket {key}: {best[0]} grid={best[1]} narrow={best[2]} "
+                    f"{best[3]:.3f} ms (sample n={b.n}, {len(tried)} runs)")
+    finally:
+        eng.close()
+    return out

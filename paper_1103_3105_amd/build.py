@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgputx.so")
 SOURCES = ["runtime.hip", "serve.hip", "kernels_front.hip", "kernels_exec.hip", "sort.hip",
-           "probes.hip", "micro.hip"]
+           "probes.hip", "micro.hip", "pool.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed fp32 instructions stay off: some of their forms have produced

@@ -48,8 +48,9 @@ struct Ws {
     uint32_t* qv[2];     // [n] PART sort: serial position
     int32_t* heads;      // [n + 1] PART: first sorted position of each non-empty partition
     int32_t* heads_tmp;  // [head blocks] PART: per-block head counts, then offsets
-    // PART: one record per serial position (k_part_gather): input index and
-    // type in the first word, then the parameters (zero past the type's own)
+    // PART: one record per partition-sorted position (k_part_gather): input
+    // index and type in the first word, then the parameters (zero past the
+    // type's own)
     int64_t* rec;        // [n][rec_words]
     int32_t* front[2];   // [n] K-SET frontiers
     uint32_t* sort_hist; // [8][256]

@@ -12,7 +12,8 @@
 //              Workgroups claim 256-transaction windows in timestamp order
 //              and group each window by type.
 //   k_part_gather PART: every transaction's record (input index, type,
-//              parameters) at its serial position, and its appended rows; in
+//              parameters) at its partition-sorted position, so that a
+//              partition's records lie together, and its appended rows; in
 //              the one-bulk call it runs ahead of the choice on a second stream.
 //   k_part_pipe PART (Section 5.2), few long partitions: one workgroup per
 //              partition; staging waves put each chunk's cells in an LDS
@@ -840,20 +841,32 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     // then fails it).
     for (int k = 0; k < a.n_app; ++k)
         if (st->app_total[k] > 0 && a.rowcount[k] + st->app_total[k] > a.capacity[k]) return;
-    for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
-         p += (int64_t)gridDim.x * GTX_BLOCK) {
+    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
+    for (int64_t q = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; q < a.n;
+         q += (int64_t)gridDim.x * GTX_BLOCK) {
+        // the appended rows of the transaction at serial position q
+        const int32_t tq = a.ws.tty[q];
+        if (tq >= 0) {
+            TxnIn y;
+            load_txn(a, q, tq, y);
+            AppendOnlyAcc ap;
+            int64_t unused[GTX_MAX_RESULTS];
+            (void)txn_exec_any(ap, a.types[tq], y.prm, y.ts, y.app0, y.app1, unused);
+        }
+        // the record of the transaction at partition-sorted position q, so
+        // that a partition's records lie together
+        const int32_t p = (int32_t)pos[q];
         const int32_t t = a.ws.tty[p];
         if (t < 0) continue;
-        TxnIn x;
-        load_txn(a, p, t, x);
-        int64_t* r = a.ws.rec + p * a.rec_words;
-        r[0] = (int64_t)(((uint64_t)(uint32_t)t << 32) | (uint32_t)x.i);
+        const DevType& T = a.types[t];
+        const int64_t i = in_index(a, p);
+        int64_t prm[GTX_MAX_PARAMS];
+        load_params(a.params, a.n, min(a.n_params, T.n_params), i, prm);
+        int64_t* r = a.ws.rec + q * a.rec_words;
+        r[0] = (int64_t)(((uint64_t)(uint32_t)t << 32) | (uint32_t)i);
 #pragma unroll
         for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-            if (k < a.prm_rows) r[1 + k] = x.prm[k];
-        AppendOnlyAcc ap;
-        int64_t unused[GTX_MAX_RESULTS];
-        (void)txn_exec_any(ap, a.types[t], x.prm, x.ts, x.app0, x.app1, unused);
+            if (k < a.prm_rows) r[1 + k] = prm[k];
     }
 }
 
@@ -1405,6 +1418,7 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         break;
                 GTX_ONE(GPUTX_DEBIT_CREDIT)
                 GTX_ONE(GPUTX_NEW_ORDER)
+                GTX_ONE(GPUTX_NEW_ORDER_RB)
                 GTX_ONE(GPUTX_PAYMENT)
                 GTX_ONE(GPUTX_ORDER_STATUS)
                 GTX_ONE(GPUTX_GET_SUB)
@@ -1561,6 +1575,7 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
         break;
                 GTX_CLAIM_CASE(GPUTX_DEBIT_CREDIT)
                 GTX_CLAIM_CASE(GPUTX_NEW_ORDER)
+                GTX_CLAIM_CASE(GPUTX_NEW_ORDER_RB)
                 GTX_CLAIM_CASE(GPUTX_PAYMENT)
                 GTX_CLAIM_CASE(GPUTX_ORDER_STATUS)
                 GTX_CLAIM_CASE(GPUTX_GET_SUB)
@@ -1603,10 +1618,10 @@ __device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChu
 }
 // Read and stage the chunk starting at c0 in one go (no read-ahead).
 __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                           const uint32_t* pos, int64_t c0, int64_t end, int lane) {
+                                           int64_t c0, int64_t end, int lane) {
     StagedTxn x;
     x.t = 0;
-    if (c0 + lane < end) stage_load(a, (int32_t)pos[c0 + lane], x);
+    if (c0 + lane < end) stage_load(a, (int32_t)(c0 + lane), x);
     part_stage_read(a, c, tab, x, c0, end, lane);
 }
 
@@ -1675,6 +1690,7 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
         return part_serial<P>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
         GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
         GTX_PART_CASE(GPUTX_NEW_ORDER)
+        GTX_PART_CASE(GPUTX_NEW_ORDER_RB)
         GTX_PART_CASE(GPUTX_PAYMENT)
         GTX_PART_CASE(GPUTX_ORDER_STATUS)
         GTX_PART_CASE(GPUTX_GET_SUB)
@@ -1725,7 +1741,6 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
     if (lane == 0) *tab.nlist = 0;
     __syncthreads();
 
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     const SerialWave sw{0, 1, tab.tag};
     int64_t committed = 0, aborted = 0;
@@ -1733,7 +1748,7 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
-            part_stage(a, c, tab, pos, c0, end, lane);
+            part_stage(a, c, tab, c0, end, lane);
             __syncthreads();
             const bool written = part_run_chunk(a, c, tab, sw, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
@@ -1783,7 +1798,6 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
     part_init_rows(buf(1), tab, tid, nthr);
     if (tid == 0) *tab.nlist = 0;
 
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     const int nh = st->n_heads;
     const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
     const SerialWave sw{ws, kPipeSerial, tab.tag + (serial ? ws : 0) * tab.tstride};
@@ -1793,30 +1807,24 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        // A staging lane reads its transaction's record for chunk k + 2 and
-        // the serial position of its transaction of chunk k + 3 while it
-        // claims the cells of chunk k + 1, so a step's global reads do not
-        // wait on one another.  xn: the next chunk to claim; pn: the position
-        // after it.
+        // A staging lane reads its transaction's record for chunk k + 2 (the
+        // records lie in partition order) while it claims the cells of chunk
+        // k + 1, so a step's global reads do not wait on one another.  xn:
+        // the next chunk to claim.
         StagedTxn xn;
         xn.t = 0;
-        int32_t pn = 0;
         if (!serial) {
-            const int64_t j0 = lo + sl, j1 = j0 + cw, j2 = j1 + cw;
-            const int32_t p0 = j0 < end ? (int32_t)pos[j0] : 0;
-            const int32_t p1 = j1 < end ? (int32_t)pos[j1] : 0;
-            pn = j2 < end ? (int32_t)pos[j2] : 0;
+            const int64_t j0 = lo + sl, j1 = j0 + cw;
             StagedTxn x0;
             x0.t = 0;
-            if (j0 < end) stage_load(a, p0, x0);
-            if (j1 < end) stage_load(a, p1, xn);
+            if (j0 < end) stage_load(a, (int32_t)j0, x0);
+            if (j1 < end) stage_load(a, (int32_t)j1, xn);
             part_stage_read(a, buf(0), tab, x0, lo, end, sl);
         }
         __syncthreads();
         for (int64_t k = 0; k < nch; ++k) {
             const int64_t c0 = lo + cw * k;
             StagedTxn xa = xn;
-            int32_t pa = 0;
             if (serial) {
                 const int cnt = (int)min<int64_t>(cw, end - c0);
                 if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted))
@@ -1825,9 +1833,8 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
                 bool flush = false;
                 if (k + 1 < nch) {
                     flush = *tab.nlist + cw * a.cells_max > part_pipe_fill(cap);
-                    const int64_t j2 = c0 + 2 * cw + sl, j3 = j2 + cw;
-                    if (j3 < end) pa = (int32_t)pos[j3];
-                    if (j2 < end) stage_load(a, pn, xa);
+                    const int64_t j2 = c0 + 2 * cw + sl;
+                    if (j2 < end) stage_load(a, (int32_t)j2, xa);
                     if (!flush) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 }
                 if (sl == 0) flag[k & 1] = flush;
@@ -1842,7 +1849,6 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
                 __syncthreads();
             }
             xn = xa;
-            pn = pa;
         }
         // every staged cell; the table is empty after
         part_flush(tab, tid, nthr);

@@ -51,15 +51,18 @@ __device__ inline bool txn_valid(const DevType& T, const int64_t* p) {
     switch (T.proc) {
     case GPUTX_DEBIT_CREDIT:
         return in_range(p[0], T.rows[0]) && in_range(p[1], T.rows[1]) && in_range(p[2], T.rows[2]);
-    case GPUTX_NEW_ORDER: {
+    case GPUTX_NEW_ORDER:
+    case GPUTX_NEW_ORDER_RB: {
         if (!(in_range(p[0], T.dims[0]) && in_range(p[1], T.dims[1]) && in_range(p[2], T.dims[2])))
             return false;
         int64_t k = p[3];
         if (k < 1 || k > 15) return false;
+        // the rollback variant also takes the unused item id (== items per warehouse)
+        const int64_t items = T.dims[3] + (T.proc == GPUTX_NEW_ORDER_RB ? 1 : 0);
         bool ok = true;
 #pragma unroll
         for (int j = 0; j < 15; ++j)
-            if (j < k) ok = ok && in_range(p[4 + j], T.dims[3]) && p[19 + j] >= 1 && p[19 + j] <= 1000;
+            if (j < k) ok = ok && in_range(p[4 + j], items) && p[19 + j] >= 1 && p[19 + j] <= 1000;
         return ok;
     }
     case GPUTX_PAYMENT:
@@ -80,12 +83,22 @@ __device__ inline bool txn_valid(const DevType& T, const int64_t* p) {
     return false;
 }
 
+// A rollback new-order that names the unused item rolls back (and appends
+// nothing); whether it does depends on its parameters alone.
+__device__ __forceinline__ bool no_rb_rolls_back(const DevType& T, const int64_t* p) {
+    bool rb = false;
+#pragma unroll
+    for (int j = 0; j < 15; ++j) rb = rb || (j < p[3] && p[4 + j] == T.dims[3]);
+    return rb;
+}
+
 // Rows appended to the procedure's append tables (slot 0, slot 1).
 __device__ __forceinline__ void txn_appends(const DevType& T, const int64_t* p, int* a0, int* a1) {
     *a0 = 0;
     *a1 = 0;
     if (T.proc == GPUTX_DEBIT_CREDIT) *a0 = 1;
     if (T.proc == GPUTX_NEW_ORDER) { *a0 = 1; *a1 = (int)p[3]; }
+    if (T.proc == GPUTX_NEW_ORDER_RB && !no_rb_rolls_back(T, p)) { *a0 = 1; *a1 = (int)p[3]; }
 }
 
 __device__ __forceinline__ void op_add(OpList& L, const DevType& T, int role, int64_t row, bool w) {
@@ -123,9 +136,10 @@ __device__ inline void txn_ops(const DevType& T, const int64_t* p, OpList& L) {
         op_add(L, T, 2, p[2], true);
         break;
     case GPUTX_NEW_ORDER:
+    case GPUTX_NEW_ORDER_RB:  // the unused item has no row
 #pragma unroll
         for (int j = 0; j < 15; ++j)
-            if (j < p[3]) op_add(L, T, 3, p[0] * T.dims[3] + p[4 + j], true);
+            if (j < p[3] && p[4 + j] < T.dims[3]) op_add(L, T, 3, p[0] * T.dims[3] + p[4 + j], true);
         break;
     case GPUTX_PAYMENT: {
         int64_t drow = p[0] * T.dims[1] + p[1];
@@ -186,11 +200,12 @@ __device__ __forceinline__ void txn_cells(const DevType& T, const int64_t* p, F&
         f.cell(1, colp<int64_t>(T, 1, 0) + p[1], true);
         f.cell(2, colp<int64_t>(T, 2, 0) + p[2], true);
         break;
-    case GPUTX_NEW_ORDER: {
+    case GPUTX_NEW_ORDER:
+    case GPUTX_NEW_ORDER_RB: {
         GTX_GLOBAL int32_t* S = colp<int32_t>(T, 3, 0) + p[0] * T.dims[3];
 #pragma unroll
         for (int j = 0; j < 15; ++j)
-            if (j < p[3]) f.cell(j, S + p[4 + j], true);
+            if (j < p[3] && p[4 + j] < T.dims[3]) f.cell(j, S + p[4 + j], true);
         break;
     }
     case GPUTX_PAYMENT: {
@@ -227,13 +242,13 @@ __device__ __forceinline__ void txn_cells(const DevType& T, const int64_t* p, F&
 // Roles (bound tables) whose rows txn_cells names for procedure P.
 __host__ __device__ constexpr uint32_t proc_cell_roles(int proc) {
     return (proc == GPUTX_DEBIT_CREDIT || proc == GPUTX_PAYMENT) ? 0x7u
-         : proc == GPUTX_NEW_ORDER ? 0x8u : proc == GPUTX_ORDER_STATUS ? 0x4u
+         : (proc == GPUTX_NEW_ORDER || proc == GPUTX_NEW_ORDER_RB) ? 0x8u : proc == GPUTX_ORDER_STATUS ? 0x4u
          : (proc == GPUTX_GET_SUB || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 0x1u
          : (proc == GPUTX_GET_CF || proc == GPUTX_INS_CF || proc == GPUTX_DEL_CF) ? 0x2u : 0xffu;
 }
 // Most cells txn_cells lists for one transaction of procedure P (0: any).
 __host__ __device__ constexpr int proc_cells(int proc) {
-    return proc == GPUTX_NEW_ORDER ? 15 : proc == GPUTX_GET_SUB ? 14
+    return (proc == GPUTX_NEW_ORDER || proc == GPUTX_NEW_ORDER_RB) ? 15 : proc == GPUTX_GET_SUB ? 14
          : (proc == GPUTX_ORDER_STATUS || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 1
          : proc == 0 ? 15 : 3;
 }
@@ -287,7 +302,8 @@ struct NoAppendAcc : DirectAcc {
 
 // Parameters procedure P reads (0: any procedure, the widest signature).
 __host__ __device__ constexpr int proc_params(int proc) {
-    return proc == GPUTX_DEBIT_CREDIT ? 4 : proc == GPUTX_NEW_ORDER ? 34 : proc == GPUTX_PAYMENT ? 4
+    return proc == GPUTX_DEBIT_CREDIT ? 4 : (proc == GPUTX_NEW_ORDER || proc == GPUTX_NEW_ORDER_RB) ? 34
+         : proc == GPUTX_PAYMENT ? 4
          : proc == GPUTX_ORDER_STATUS ? 3 : proc == GPUTX_GET_SUB ? 1
          : (proc == GPUTX_GET_CF || proc == GPUTX_DEL_CF) ? 2
          : (proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC) ? 3 : proc == GPUTX_INS_CF ? 4 : 34;
@@ -297,7 +313,7 @@ __host__ __device__ constexpr int proc_params(int proc) {
 // Not so for new-order, whose item ordinals all name the stock column, nor
 // for a mixed chunk (P == 0).
 __host__ __device__ constexpr bool proc_typed_cells(int proc) {
-    return proc != 0 && proc != GPUTX_NEW_ORDER;
+    return proc != 0 && proc != GPUTX_NEW_ORDER && proc != GPUTX_NEW_ORDER_RB;
 }
 // Procedures whose effect on each of their cells depends only on that cell's
 // old value and the parameters: no cell's value decides what happens to
@@ -316,7 +332,7 @@ __host__ __device__ constexpr bool proc_cell_writes(int proc) {
 }
 // Results procedure P can write (0: any procedure).
 __host__ __device__ constexpr int proc_results(int proc) {
-    return proc == GPUTX_NEW_ORDER ? 16 : proc == GPUTX_GET_SUB ? 14
+    return (proc == GPUTX_NEW_ORDER || proc == GPUTX_NEW_ORDER_RB) ? 16 : proc == GPUTX_GET_SUB ? 14
          : (proc == GPUTX_ORDER_STATUS || proc == GPUTX_UPD_SUB_FIELD || proc == GPUTX_UPD_LOC ||
             proc == GPUTX_INS_CF) ? 1
          : proc == 0 ? GTX_MAX_RESULTS : 3;
@@ -362,6 +378,55 @@ __device__ __forceinline__ int32_t txn_exec_p(Acc& acc, const DevType& T, const 
                 int32_t s32 = to_i32(s);
                 S.set(s32);
                 res[1 + j] = s32;
+                int64_t r = app1 + j;
+                acc.app(colp<int64_t>(T, 5, 0) + r, ts);
+                acc.app(colp<int64_t>(T, 5, 1) + r, (int64_t)j);
+                acc.app(colp<int64_t>(T, 5, 2) + r, p[4 + j]);
+                acc.app(colp<int64_t>(T, 5, 3) + r, p[19 + j]);
+                acc.app(colp<int64_t>(T, 5, 4) + r, p[0]);
+            }
+        }
+        acc.app(colp<int64_t>(T, 4, 0) + app0, ts);
+        acc.app(colp<int64_t>(T, 4, 1) + app0, p[0]);
+        acc.app(colp<int64_t>(T, 4, 2) + app0, p[1]);
+        acc.app(colp<int64_t>(T, 4, 3) + app0, p[2]);
+        acc.app(colp<int64_t>(T, 4, 4) + app0, k);
+        return GPUTX_COMMIT;
+    }
+    case GPUTX_NEW_ORDER_RB: {
+        // Not two-phase: each stock row is updated as its item is reached,
+        // with the old value written to the transaction's undo log first; on
+        // reaching the unused item the log is replayed backwards and the
+        // transaction aborts.  Nothing else can see the rows meanwhile (the
+        // executors hand a row on only after the transaction is over), so the
+        // rollback touches this transaction alone.
+        int64_t k = p[3];
+        int32_t undo[15];
+        GTX_GLOBAL int32_t* S0 = colp<int32_t>(T, 3, 0) + p[0] * T.dims[3];
+#pragma unroll
+        for (int j = 0; j < 15; ++j) {
+            if (j < k) {
+                if (p[4 + j] == T.dims[3]) {
+#pragma unroll
+                    for (int q = j - 1; q >= 0; --q) acc.ref(q, S0 + p[4 + q]).set(undo[q]);
+#pragma unroll
+                    for (int r = 0; r < GTX_MAX_RESULTS; ++r) res[r] = 0;
+                    return GPUTX_ABORT;
+                }
+                auto S = acc.ref(j, S0 + p[4 + j]);
+                const int32_t old = S.get();
+                undo[j] = old;
+                int64_t s = (int64_t)old - p[19 + j];
+                if (s < 10) s += 91;
+                int32_t s32 = to_i32(s);
+                S.set(s32);
+                res[1 + j] = s32;
+            }
+        }
+        res[0] = k;
+#pragma unroll
+        for (int j = 0; j < 15; ++j) {
+            if (j < k) {
                 int64_t r = app1 + j;
                 acc.app(colp<int64_t>(T, 5, 0) + r, ts);
                 acc.app(colp<int64_t>(T, 5, 1) + r, (int64_t)j);
@@ -520,6 +585,7 @@ __device__ __forceinline__ int32_t txn_exec_any(Acc& acc, const DevType& T, cons
     switch (T.proc) {
     case GPUTX_DEBIT_CREDIT: return txn_exec_p<GPUTX_DEBIT_CREDIT>(acc, T, p, ts, app0, app1, res);
     case GPUTX_NEW_ORDER: return txn_exec_p<GPUTX_NEW_ORDER>(acc, T, p, ts, app0, app1, res);
+    case GPUTX_NEW_ORDER_RB: return txn_exec_p<GPUTX_NEW_ORDER_RB>(acc, T, p, ts, app0, app1, res);
     case GPUTX_PAYMENT: return txn_exec_p<GPUTX_PAYMENT>(acc, T, p, ts, app0, app1, res);
     case GPUTX_ORDER_STATUS: return txn_exec_p<GPUTX_ORDER_STATUS>(acc, T, p, ts, app0, app1, res);
     case GPUTX_GET_SUB: return txn_exec_p<GPUTX_GET_SUB>(acc, T, p, ts, app0, app1, res);

@@ -291,15 +291,18 @@ static bool proc_spec(int proc, ProcSpec* s) {
         role(0, 0, {L}); role(1, 0, {L}); role(2, 0, {L}); role(3, 1, {L, L, L, L, L});
         return true;
     case GPUTX_NEW_ORDER:
+    case GPUTX_NEW_ORDER_RB:
     case GPUTX_PAYMENT:
-    case GPUTX_ORDER_STATUS:
+    case GPUTX_ORDER_STATUS: {
+        const bool no = proc == GPUTX_NEW_ORDER || proc == GPUTX_NEW_ORDER_RB;
         s->n_roles = 6;
-        s->min_params = proc == GPUTX_NEW_ORDER ? 34 : (proc == GPUTX_PAYMENT ? 4 : 3);
-        s->max_results = proc == GPUTX_NEW_ORDER ? 16 : (proc == GPUTX_PAYMENT ? 3 : 1);
-        s->ops = proc == GPUTX_NEW_ORDER ? 15 : (proc == GPUTX_PAYMENT ? 3 : 1);
+        s->min_params = no ? 34 : (proc == GPUTX_PAYMENT ? 4 : 3);
+        s->max_results = no ? 16 : (proc == GPUTX_PAYMENT ? 3 : 1);
+        s->ops = no ? 15 : (proc == GPUTX_PAYMENT ? 3 : 1);
         role(0, 0, {L}); role(1, 0, {L}); role(2, 0, {L}); role(3, 0, {I});
         role(4, 1, {L, L, L, L, L}); role(5, 1, {L, L, L, L, L});
         return true;
+    }
     case GPUTX_GET_SUB:
     case GPUTX_GET_CF:
     case GPUTX_UPD_SUB_FIELD:
@@ -369,11 +372,13 @@ extern "C" int gputx_register_types(gputx_handle h, const gputx_type_desc* t, in
                     return gtx_set_err(h, GPUTX_E_TYPE, "type %d: root-key mode but table %d has no root", d.type_id, tid);
             }
             if (ps.append[r]) {
-                if (d.proc == GPUTX_DEBIT_CREDIT || d.proc == GPUTX_NEW_ORDER) D.app_idx[app_slot] = T.app_idx;
+                if (d.proc == GPUTX_DEBIT_CREDIT || d.proc == GPUTX_NEW_ORDER || d.proc == GPUTX_NEW_ORDER_RB)
+                    D.app_idx[app_slot] = T.app_idx;
                 ++app_slot;
             }
         }
-        if (d.proc == GPUTX_NEW_ORDER || d.proc == GPUTX_PAYMENT || d.proc == GPUTX_ORDER_STATUS) {
+        if (d.proc == GPUTX_NEW_ORDER || d.proc == GPUTX_NEW_ORDER_RB || d.proc == GPUTX_PAYMENT ||
+            d.proc == GPUTX_ORDER_STATUS) {
             int64_t nw = D.rows[0], nd = D.rows[1];
             if (nw < 1 || nd < 1) return gtx_set_err(h, GPUTX_E_TYPE, "type %d: empty warehouse/district", d.type_id);
             D.dims[0] = nw;
@@ -689,12 +694,16 @@ extern "C" int gputx_batch_create(gputx_handle h, const gputx_batch_item* items,
         lanes = std::max(lanes, items[k].lane + 1);
     }
     const int grid = gtx_grid_for(h, lanes);
+    const int cap = std::max(1, resident_capacity(h) / std::max(lanes, 1));  // every lane's grid resident
     std::vector<BulkArgs> args(n);
     for (int k = 0; k < n; ++k) {
         const gputx_batch_item& it = items[k];
+        if (it.grid_blocks < 0 || it.kset_narrow < 0) return gtx_set_err(h, GPUTX_E_ARG, "item %d: bad launch shape", k);
+        const int g = it.grid_blocks > 0 ? std::min(it.grid_blocks, cap) : grid;
         int rc = gtx_make_args(h, &it.bulk, it.strategy, it.workspace, it.ws_bytes, it.status_out,
-                           it.results_out, it.width, it.stats, grid, &args[k]);
+                           it.results_out, it.width, it.stats, g, &args[k]);
         if (rc) return rc;
+        if (it.kset_narrow > 0) args[k].kset_narrow = it.kset_narrow;
     }
     // Two streams per lane: bulk generation (front) and execution.  A lane's
     // executions stay in order; the front phase of a bulk only waits for the

@@ -29,7 +29,7 @@ STRATEGY_NAME = {v: k for k, v in STRATEGY.items()}
 COMMIT, ABORT, INVALID = 0, 1, 2
 I32, I64 = 1, 2
 PROC = {"DEBIT_CREDIT": 1, "NEW_ORDER": 2, "PAYMENT": 3, "ORDER_STATUS": 4, "GET_SUB": 5,
-        "GET_CF": 6, "UPD_SUB_FIELD": 7, "UPD_LOC": 8, "INS_CF": 9, "DEL_CF": 10}
+        "GET_CF": 6, "UPD_SUB_FIELD": 7, "UPD_LOC": 8, "INS_CF": 9, "DEL_CF": 10, "NEW_ORDER_RB": 11}
 MAX_TYPES, MAX_TABLES, MAX_COLS, MAX_ROLES = 16, 32, 16, 8
 
 
@@ -106,7 +106,18 @@ class ServeReport(ctypes.Structure):
 class BatchItem(ctypes.Structure):
     _fields_ = [("bulk", BulkDesc), ("strategy", c_int32), ("lane", c_int32),
                 ("workspace", c_void_p), ("ws_bytes", c_size_t), ("status_out", c_void_p),
-                ("results_out", c_void_p), ("width", c_int32), ("stats", c_void_p)]
+                ("results_out", c_void_p), ("width", c_int32), ("stats", c_void_p),
+                ("grid_blocks", c_int32), ("kset_narrow", c_int32)]
+
+
+class PoolStats(ctypes.Structure):
+    _fields_ = [("error", c_int32), ("reserved", c_int32), ("added", c_int64), ("done_prefix", c_int64),
+                ("pending_ops", c_int64), ("waves", c_int64), ("executed", c_int64),
+                ("committed", c_int64), ("aborted", c_int64), ("invalid", c_int64),
+                ("last_width", c_int64), ("fetched", c_int64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 def _load() -> ctypes.CDLL:
@@ -151,6 +162,12 @@ def _load() -> ctypes.CDLL:
         "gputx_micro_workspace_size": (c_size_t, [c_int64]),
         "gputx_micro_run": (c_int32, [c_int64, c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p,
                                       c_size_t, c_int32, c_void_p]),
+        "gputx_pool_create": (c_int32, [H, c_int64, c_int32, c_int32, c_int32, c_int64, POINTER(H)]),
+        "gputx_pool_add": (c_int32, [H, POINTER(BulkDesc), c_void_p]),
+        "gputx_pool_step": (c_int32, [H, c_int32, c_void_p]),
+        "gputx_pool_state": (c_int32, [H, POINTER(PoolStats), c_void_p]),
+        "gputx_pool_results": (c_int32, [H, c_int64, c_void_p, c_void_p, c_void_p]),
+        "gputx_pool_destroy": (c_int32, [H]),
         "gputx_probe_handoff": (c_int32, [c_int32, c_int32, c_int32, POINTER(ctypes.c_double)]),
         "gputx_probe_atomic_add": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
         "gputx_probe_gather": (c_int32, [c_int32, c_int64, c_int64, POINTER(ctypes.c_double)]),
@@ -171,7 +188,8 @@ EXPORTS = ("gputx_default_options", "gputx_create", "gputx_destroy", "gputx_set_
            "gputx_batch_destroy", "gputx_serve", "gputx_probe_handoff", "gputx_probe_atomic_add",
            "gputx_probe_gather", "gputx_execute_bulk_noalloc", "gputx_serve_open",
            "gputx_serve_submit", "gputx_serve_poll", "gputx_serve_close", "gputx_read_table",
-           "gputx_micro_workspace_size", "gputx_micro_run", "gputx_execute_bulk_relaxed")
+           "gputx_micro_workspace_size", "gputx_micro_run", "gputx_execute_bulk_relaxed",
+           "gputx_pool_create", "gputx_pool_add", "gputx_pool_step", "gputx_pool_state", "gputx_pool_results", "gputx_pool_destroy")
 SCRATCH_BYTES = 64 << 20   # GPUTX_SCRATCH_BYTES: static workspace of gputx_execute_bulk_noalloc
 
 
@@ -594,6 +612,8 @@ class Batch:
             it.results_out = res.data_ptr()
             it.width = width
             it.stats = stats.data_ptr()
+            it.grid_blocks = int(j.get("grid_blocks", 0))
+            it.kset_narrow = int(j.get("kset_narrow", 0))
             items.append(it)
             self.outputs.append(dict(ws=ws, status=st, results=res, stats=stats, n=n))
         self.b = gputx_batch_create(eng.h, items)
@@ -608,6 +628,52 @@ class Batch:
         if self.b:
             gputx_batch_destroy(self.eng.h, self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """K-SET over a standing pool (gputx_pool_*): add bulks in timestamp
+    order, run 0-sets, fetch results in sequence order."""
+
+    def __init__(self, eng: "Engine", capacity: int, n_params: int, width: int, max_ops: int = 0,
+                 max_add: int = 1 << 16):
+        self.eng = eng
+        self.width = width
+        self.p = c_void_p()
+        _check(eng.h, lib.gputx_pool_create(eng.h, capacity, n_params, width, max_ops, max_add,
+                                            ctypes.byref(self.p)))
+        self._keep = []
+
+    def add(self, dev: dict, ts_sorted: bool = False, stream=None) -> None:
+        self._keep.append(dev)   # the bulk's arrays must live until the add has run
+        _check(self.eng.h, lib.gputx_pool_add(self.p, ctypes.byref(Engine.bulk_desc(dev, ts_sorted)),
+                                              _stream(stream)))
+
+    def step(self, waves: int = 1, stream=None) -> None:
+        _check(self.eng.h, lib.gputx_pool_step(self.p, waves, _stream(stream)))
+
+    def state(self, stream=None) -> PoolStats:
+        st = PoolStats()
+        _check(self.eng.h, lib.gputx_pool_state(self.p, ctypes.byref(st), _stream(stream)))
+        self._keep.clear()       # synchronised: earlier adds have run
+        return st
+
+    def results(self, n: int, stream=None):
+        status = np.zeros(max(n, 1), np.int32)
+        res = np.zeros((max(n, 1), self.width), np.int64)
+        _check(self.eng.h, lib.gputx_pool_results(self.p, n, status.ctypes.data, res.ctypes.data,
+                                                  _stream(stream)))
+        return status[:n], res[:n]
+
+    def close(self) -> None:
+        if self.p:
+            lib.gputx_pool_destroy(self.p)
+            self.p = None
 
     def __del__(self):
         try:

@@ -43,6 +43,7 @@ PROCS = (
     "UPD_LOC",
     "INS_CF",
     "DEL_CF",
+    "NEW_ORDER_RB",
 )
 
 # Role lists: the tables a procedure is bound to, in order.
@@ -256,18 +257,26 @@ def order_tables(rng: np.random.Generator, n_wh: int, d_per_w: int, c_per_d: int
     return {t.name: t for t in (wh, di, cu, st, orders, lines)}
 
 
-def order_types(root_key: bool = False) -> List[TypeDesc]:
+def order_types(root_key: bool = False, rollback: bool = False) -> List[TypeDesc]:
+    """rollback: new-order registered as the procedure that is not two-phase
+    (an unused item id makes it roll back its stock updates)."""
     return [
-        TypeDesc(1, "NEW_ORDER", NO_PARAMS, 1 + NO_MAX_ITEMS, ORDER_ROLES, root_key=root_key),
+        TypeDesc(1, "NEW_ORDER_RB" if rollback else "NEW_ORDER", NO_PARAMS, 1 + NO_MAX_ITEMS,
+                 ORDER_ROLES, root_key=root_key),
         TypeDesc(2, "PAYMENT", 4, 3, ORDER_ROLES, root_key=root_key),
         TypeDesc(3, "ORDER_STATUS", 3, 1, ORDER_ROLES, root_key=root_key),
     ]
 
 
 def order_bulk(rng: np.random.Generator, n: int, n_wh: int, d_per_w: int, c_per_d: int,
-               items_per_w: int, ts0: int = 0, mix=(0.45, 0.43, 0.12)) -> Bulk:
+               items_per_w: int, ts0: int = 0, mix=(0.45, 0.43, 0.12),
+               rollback_frac: float = 0.0) -> Bulk:
     """Mixed bulk: new-order (k uniform 5..15 distinct items, q uniform 1..10),
-    payment (h uniform 1..5000), order-status; w, d, c uniform."""
+    payment (h uniform 1..5000), order-status; w, d, c uniform.
+
+    rollback_frac: that fraction of new-orders names the unused item id
+    (items_per_w) as its last item, as TPC-C's 1% of new-orders that roll
+    back (for new-order registered as NEW_ORDER_RB)."""
     kind = rng.choice(3, size=n, p=np.asarray(mix, dtype=np.float64))
     types = (kind + 1).astype(np.int32)
     params = np.zeros((NO_PARAMS, n), dtype=np.int64)
@@ -289,6 +298,9 @@ def order_bulk(rng: np.random.Generator, n: int, n_wh: int, d_per_w: int, c_per_
     q = rng.integers(1, 11, (no.size, NO_MAX_ITEMS))
     items = np.where(live, items, 0)
     q = np.where(live, q, 0)
+    if rollback_frac > 0 and no.size:
+        rb = np.nonzero(rng.random(no.size) < rollback_frac)[0]
+        items[rb, k[rb] - 1] = items_per_w
     params[3, no] = k
     params[4:4 + NO_MAX_ITEMS, no] = items.T
     params[4 + NO_MAX_ITEMS:, no] = q.T

@@ -395,3 +395,31 @@ def test_algorithm1_choice_matches_reference(bars, remote):
 def gputx_name(code):
     from paper_1103_3105_amd import gputx
     return gputx.STRATEGY_NAME[code]
+
+
+# ---------------------------------------------------------------------------
+# a type that is not two-phase: new-orders that roll back from an undo log
+
+@pytest.mark.parametrize("strategy", STRATS)
+def test_order_entry_with_rollbacks(strategy):
+    """5% of new-orders name the unused item after updating the stock of
+    their earlier items and roll those updates back (Appendix D's undo
+    logging); every executor leaves exactly the serial result."""
+    tabs, types, bulk = util.small_order(25, 20_000, n_wh=4, d_per_w=10, c_per_d=30, items_per_w=500,
+                                         rollback_frac=0.05)
+    _say("order with rollbacks", strategy)
+    s, g, o = run_both(tabs, types, bulk, 16, strategy)
+    assert_parity(s, g, o, bulk)
+    check_features(s, tabs, types, bulk)
+    assert s.aborted > 100
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_part_forms_with_rollbacks(pipeline):
+    """PART's LDS cell tables: the rollback restores the staged values."""
+    tabs, types, bulk = util.small_order(26, 20_000, n_wh=2, d_per_w=10, c_per_d=30, items_per_w=100,
+                                         rollback_frac=0.2)
+    s, g, o = run_both(tabs, types, bulk, 16, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2
+    assert_parity(s, g, o, bulk)
+    assert s.aborted > 100

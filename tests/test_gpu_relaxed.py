@@ -77,7 +77,7 @@ def check_serializable(tabs, types, bulk, width, g_tabs, g_st, g_res, key):
 
 
 @pytest.mark.parametrize("strategy", ["TPL", "PART"])
-@pytest.mark.parametrize("workload", ["bank", "bank_remote", "order", "sub"])
+@pytest.mark.parametrize("workload", ["bank", "bank_remote", "order", "order_rb", "sub"])
 def test_relaxed_is_serializable(workload, strategy):
     ps = 1
     if workload == "bank":
@@ -88,8 +88,9 @@ def test_relaxed_is_serializable(workload, strategy):
         tabs = wl.bank_tables(rng, 8, 80, 24_000, history_capacity=20_000)
         bulk = wl.bank_bulk(rng, 20_000, 8, 80, 24_000, 0.8, remote_frac=0.05)
         types, width = wl.bank_types(), 3
-    elif workload == "order":
-        tabs, types, bulk = util.small_order(73, 20_000, n_wh=4, d_per_w=10, c_per_d=30, items_per_w=500)
+    elif workload in ("order", "order_rb"):
+        tabs, types, bulk = util.small_order(73, 20_000, n_wh=4, d_per_w=10, c_per_d=30, items_per_w=500,
+                                             rollback_frac=0.05 if workload == "order_rb" else 0.0)
         width = 16
     else:
         tabs, types, bulk = util.small_sub(74, 20_000, n_sub=2000, theta=0.8)

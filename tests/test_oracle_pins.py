@@ -364,11 +364,14 @@ def test_subscriber_chains():
 
 def _mixed_tiny(seed, n):
     rng = np.random.default_rng(seed)
-    kind = int(rng.integers(0, 3))
+    kind = int(rng.integers(0, 4))
     if kind == 0:
         return util.small_bank(seed, n, n_branch=1, tpb=2, apt=2, theta=0.0), 3
     if kind == 1:
         return util.small_order(seed, n, n_wh=1, d_per_w=2, c_per_d=2, items_per_w=6), 16
+    if kind == 3:   # new-orders that are not two-phase, half of them rolling back
+        return util.small_order(seed, n, n_wh=1, d_per_w=2, c_per_d=2, items_per_w=6,
+                                rollback_frac=0.5), 16
     return util.small_sub(seed, n, n_sub=2, theta=0.0), 14
 
 
@@ -447,3 +450,42 @@ def test_generators_deterministic_and_skewed():
     ids = wl.zipf_ids(rng, 640_000, 0.8, 200_000)
     share = (ids < 10_000).mean()        # hottest branch of 64 at 10k accounts each
     assert 0.38 < share < 0.45
+
+
+# ---------------------------------------------------------------------------
+# a transaction type that is not two-phase (Appendix D)
+
+def test_rollback_new_order_has_no_effect():
+    """A new-order that names the unused item id rolls back: stock, orders
+    and order lines are as if it never ran, its status is ABORT and its
+    results 0; the others run as plain new-orders (checked against the same
+    bulk with the rolling-back transactions removed)."""
+    tabs, types, bulk = util.small_order(41, 400, n_wh=2, d_per_w=3, c_per_d=4, items_per_w=50,
+                                         rollback_frac=0.3)
+    ipw = 50
+    no = bulk.type == 1
+    k = bulk.params[3]
+    rb = no & np.array([(bulk.params[4:4 + 15, i][:k[i]] == ipw).any() for i in range(bulk.n)])
+    assert 10 < int(rb.sum()) < int(no.sum())
+    t_rb, st, res = _run(tabs, types, bulk, 16)
+    assert (st[rb] == 1).all() and (res[rb] == 0).all()
+    keep = ~rb
+    plain = wl.Bulk(bulk.type[keep], bulk.params[:, keep], bulk.ts[keep])
+    t_pl, st2, res2 = _run(tabs, wl.order_types(), plain, 16)
+    assert np.array_equal(st[keep], st2) and np.array_equal(res[keep], res2)
+    ok, msg = util.tables_equal(t_pl, t_rb)
+    assert ok, msg
+    # the Python twin agrees
+    t_py = util.copy_tables(tabs)
+    st3, res3 = ref.py_execute(t_py, types, bulk.type, bulk.params, bulk.ts, 16)
+    assert np.array_equal(st3, st) and np.array_equal(res3, res)
+
+
+def test_rollback_new_order_operations_skip_the_unused_item():
+    tabs, types, bulk = util.small_order(42, 60, n_wh=1, d_per_w=2, c_per_d=2, items_per_w=20,
+                                         rollback_frac=1.0)
+    per = ref.bulk_ops(types, bulk.type, bulk.params, bulk.ts, util.sizes_of(tabs), util.roots_of(tabs))
+    for i, _, ops in per:
+        if bulk.type[i] == 1:
+            assert len(ops) == bulk.params[3][i] - 1   # k items, one of them unused
+            assert all(tab == "stock" and row < 20 for (tab, row) in ops)

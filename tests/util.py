@@ -37,13 +37,15 @@ def small_bank(seed: int, n: int, n_branch=2, tpb=2, apt=3, theta=0.0):
     return tabs, wl.bank_types(), bulk
 
 
-def small_order(seed: int, n: int, n_wh=2, d_per_w=2, c_per_d=3, items_per_w=20):
+def small_order(seed: int, n: int, n_wh=2, d_per_w=2, c_per_d=3, items_per_w=20, rollback_frac=0.0):
+    """Order-entry bulk; rollback_frac > 0 registers new-order as the procedure
+    that is not two-phase and makes that fraction of new-orders roll back."""
     rng = np.random.default_rng(seed)
-    bulk = wl.order_bulk(rng, n, n_wh, d_per_w, c_per_d, items_per_w)
+    bulk = wl.order_bulk(rng, n, n_wh, d_per_w, c_per_d, items_per_w, rollback_frac=rollback_frac)
     n_no = int((bulk.type == 1).sum())
     n_l = int(bulk.params[3][bulk.type == 1].sum())
     tabs = wl.order_tables(rng, n_wh, d_per_w, c_per_d, items_per_w, max(n_no, 1), max(n_l, 1))
-    return tabs, wl.order_types(), bulk
+    return tabs, wl.order_types(rollback=rollback_frac > 0), bulk
 
 
 def small_sub(seed: int, n: int, n_sub=5, theta=0.8):
