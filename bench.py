@@ -392,6 +392,95 @@ def bench_micro(args):
                          f"uniform", by_types=fig3, breakdown_T16_x32=fig12, parity_sampled=parity)
 
 
+def bench_pool(args):
+    """Section 5.3's standing pool under skew (the shape of Figure 6): a
+    stream of bulks of single-row updates, alpha of them on one hot row and
+    the rest uniform over 1M rows.  Per-bulk execution must finish every bulk
+    (its hot chain included) before the next; the pool adds each bulk and
+    runs a few 0-sets, leaving the hot chain queued.  Committed transactions
+    per second over the arrival of all bulks, the backlog left, and the time
+    to drain it; parity of the pool's results and tables after the drain."""
+    import torch
+    import oracle
+    from paper_1103_3105_amd import gputx, workloads as wl
+    n_sub, m, rounds, waves = 1_000_000, 1 << 14, args.pool_rounds, args.pool_waves
+    tabs = wl.sub_tables(wl.rng_for(5, 7), n_sub, occupancy=0.0)
+    types = wl.sub_types()
+    out = []
+    for alpha in (0.0, 0.1, 0.3, 0.6):
+        rng = np.random.default_rng(1103_061 + int(alpha * 100))
+        bulks = []
+        for r in range(rounds):
+            sid = np.where(rng.random(m) < alpha, 0, rng.integers(1, n_sub, m))
+            prm = np.zeros((4, m), np.int64)
+            prm[0] = sid
+            prm[1] = rng.integers(0, 4, m)
+            prm[2] = rng.integers(0, 1 << 30, m)
+            bulks.append(wl.Bulk(np.full(m, 6, np.int32), prm, np.arange(r * m, (r + 1) * m, dtype=np.int64)))
+        row = dict(alpha=alpha)
+        for strat in ("TPL", "PART", "KSET"):
+            eng = gputx.Engine(tabs, types, part_size=128)
+            try:
+                devs = [eng.bulk_to_device(b) for b in bulks]
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                committed = 0
+                label = strat
+                for d in devs:
+                    st, res, stats = eng.execute(d, gputx.STRATEGY[strat], 14, ts_sorted=True)
+                    torch.cuda.synchronize()
+                    s_ = gputx.stats_from(stats)
+                    committed += s_.committed
+                    label = s_.label
+                dt = time.perf_counter() - t0
+                row[label] = round(committed / dt)
+            finally:
+                eng.close()
+        eng = gputx.Engine(tabs, types, part_size=128)
+        try:
+            devs = [eng.bulk_to_device(b) for b in bulks]
+            pool = gputx.Pool(eng, rounds * m, 4, 14, max_add=m)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for d in devs:
+                pool.add(d, ts_sorted=True)
+                pool.step(waves)
+            st = pool.state()
+            dt = time.perf_counter() - t0
+            # drain within a step budget; what has run in sequence is checked
+            # against the oracle, the tables only when the pool drained
+            t1 = time.perf_counter()
+            for _ in range(args.pool_drain_steps // 64):
+                fin = pool.state()
+                if fin.error or fin.done_prefix == fin.added:
+                    break
+                pool.step(64)
+            fin = pool.state()
+            drain_s = time.perf_counter() - t1
+            k = int(fin.done_prefix)
+            p_st, p_res = pool.results(k)
+            o_tabs = {kk: v.copy() for kk, v in tabs.items()}
+            want = oracle.run_sequence(o_tabs, types, [(b, 14) for b in bulks])
+            w_st = np.concatenate([w[0] for w in want])[:k]
+            w_res = np.concatenate([w[1] for w in want])[:k]
+            parity = bool(fin.error == 0 and np.array_equal(p_st, w_st) and np.array_equal(p_res, w_res))
+            drained = fin.done_prefix == fin.added
+            if drained:
+                host = eng.table_host("subscriber")
+                parity = parity and all(np.array_equal(a, b) for a, b in zip(host, o_tabs["subscriber"].cols))
+            row["pool"] = dict(txn_per_s_during_arrivals=round(st.committed / dt),
+                               backlog_after_arrivals=int(st.added - st.executed - st.invalid),
+                               waves=int(fin.waves), drained=bool(drained), drain_s=round(drain_s, 3),
+                               checked_prefix=k, parity_vs_oracle=parity)
+            pool.close()
+        finally:
+            eng.close()
+        log(f"[bench] pool alpha={alpha}: {row}")
+        out.append(row)
+    return dict(workload=f"{rounds} bulks of {m} single-row updates (UPD_SUB_FIELD) over {n_sub} rows, "
+                         f"alpha of them on one row; pool: {waves} steps per added bulk", by_alpha=out)
+
+
 def pcie_inclusive(eng, dev, status, results, width, step, reps):
     """Transactions per second with every bulk's signatures copied in from
     pinned host memory and its statuses and results copied back: one stream
@@ -440,16 +529,18 @@ def pcie_inclusive(eng, dev, status, results, width, step, reps):
 
 
 def bench_batch(args):
-    """Config-4 form: 512 uneven bulks over two databases, batched (one graph
-    launch) vs plain (one execute + wait per bulk), with Algorithm 1's
-    thresholds calibrated on a sample of the bulks first."""
+    """Config-4 form: 512 uneven bulks over two databases.  Plain (one
+    execute + wait per bulk, Algorithm 1 with calibrated thresholds) against
+    batched (one graph launch) with the same thresholds, and batched with the
+    executor and launch shape tuned per shape bucket.  Every form starts from
+    the same tables, and its first pass is compared with the oracle."""
     import torch
     import oracle
     from paper_1103_3105_amd import autotune, batching, gputx
     log("[bench] generating the 512-bulk batch workload")
     bw = batching.config4(n_bulks=args.bulks)
     n_txn = bw.n_txns
-    # calibration on a spread of sample bulks (scratch copy of the database)
+    # Algorithm 1's thresholds, calibrated on a spread of sample bulks
     order = sorted(range(len(bw.jobs)), key=lambda k: bw.jobs[k][1].n)
     picks = [order[int(q * (len(order) - 1))] for q in np.linspace(0.05, 0.75, 12)]
     samples = [(bw.jobs[k][1], batching.WIDTH[bw.jobs[k][0]], batching.MAX_OPS[bw.jobs[k][0]])
@@ -457,58 +548,96 @@ def bench_batch(args):
     tuned = autotune.calibrate(bw.tables, bw.types, samples, log=log)
     log(f"[bench] calibrated: w0_bar={tuned['w0_bar']} d_bar={tuned['d_bar']} "
         f"narrow={tuned['kset_narrow']}")
+    # executor and launch shape per shape bucket (database, size class)
+    t0 = time.perf_counter()
+    buckets = autotune.tune_buckets(bw.tables, bw.types, bw.jobs, batching.WIDTH, batching.MAX_OPS, log=log)
+    tune_s = time.perf_counter() - t0
     eng = gputx.Engine(bw.tables, bw.types)
     eng.set_options(w0_bar=int(min(tuned["w0_bar"], 2**62)), c_bar=int(tuned["c_bar"]),
                     d_bar=int(min(tuned["d_bar"], 2**62)), kset_narrow=int(tuned["kset_narrow"]))
+    snap = DeviceSnapshot(eng)
     jobs = batching.device_jobs(eng, bw, gputx.AUTO)
-    o_tabs = {k: v.copy() for k, v in bw.tables.items()}
-    outs = [dict(status=torch.empty(max(b.n, 1), dtype=torch.int32, device=eng.device),
-                 results=torch.empty((max(b.n, 1), batching.WIDTH[db]), dtype=torch.int64,
-                                     device=eng.device),
-                 stats=torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device))
-            for db, b in bw.jobs]
+    jobs_tuned = []
+    for j, (db, b) in zip(jobs, bw.jobs):
+        t = buckets[autotune.bucket_of(db, b.n)]
+        jobs_tuned.append(dict(j, strategy=gputx.STRATEGY[t["strategy"]], grid_blocks=t["grid_blocks"],
+                               kset_narrow=t["kset_narrow"]))
+    want = oracle.run_sequence({k: v.copy() for k, v in bw.tables.items()}, bw.types, batching.sequence(bw))
+
+    def outputs():
+        return [dict(status=torch.empty(max(b.n, 1), dtype=torch.int32, device=eng.device),
+                     results=torch.empty((max(b.n, 1), batching.WIDTH[db]), dtype=torch.int64,
+                                         device=eng.device),
+                     stats=torch.empty(gputx.STATS_BYTES, dtype=torch.uint8, device=eng.device))
+                for db, b in bw.jobs]
+
+    def check(get):
+        return all(np.array_equal(st[:b.n], want[k][0]) and np.array_equal(res[:b.n], want[k][1])
+                   for k, (db, b) in enumerate(bw.jobs) for st, res in [get(k)])
+
+    outs = outputs()
+    snap.restore()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = batching.run_plain(eng, jobs, outs)
     plain_s = time.perf_counter() - t0
-    want = oracle.run_sequence(o_tabs, bw.types, batching.sequence(bw))
-    parity = all(np.array_equal(outs[k]["status"].cpu().numpy()[:b.n], want[k][0]) and
-                 np.array_equal(outs[k]["results"].cpu().numpy()[:b.n], want[k][1])
-                 for k, (db, b) in enumerate(bw.jobs))
+    parity_plain = check(lambda k: (outs[k]["status"].cpu().numpy(), outs[k]["results"].cpu().numpy()))
     committed_plain = sum(gputx.stats_from(o["stats"]).committed for o in outs)
     chosen = [gputx.STRATEGY_NAME[gputx.stats_from(o["stats"]).chosen] for o in outs]
-    log(f"[bench] plain: {plain_s:.3f} s, parity={parity}, chosen={ {c: chosen.count(c) for c in set(chosen)} }")
-    batch = eng.batch(jobs)
-    per = []
-    for k in range(args.warmup + args.steps):
-        eng.truncate_appends()   # the replay appends the same rows again
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        batch.launch()
-        e1.record()
-        torch.cuda.synchronize()
-        if k >= args.warmup:
-            per.append(e0.elapsed_time(e1))
-    per = np.array(per)
-    committed = sum(batch.stats(k).committed for k in range(len(bw.jobs)))
-    errors = sum(batch.stats(k).error != 0 for k in range(len(bw.jobs)))
-    batched_value = committed / (per.mean() / 1e3)
+    log(f"[bench] plain: {plain_s:.3f} s, parity={parity_plain}, "
+        f"chosen={ {c: chosen.count(c) for c in set(chosen)} }")
+
+    def run_batch(js, name):
+        batch = eng.batch(js)
+        try:
+            per = []
+            parity = None
+            for k in range(1 + args.warmup + args.steps):
+                snap.restore()   # every launch from the same tables (outside timing)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                batch.launch()
+                e1.record()
+                torch.cuda.synchronize()
+                if k == 0:
+                    parity = check(lambda i: (batch.outputs[i]["status"].cpu().numpy(),
+                                              batch.outputs[i]["results"].cpu().numpy()))
+                elif k > args.warmup:
+                    per.append(e0.elapsed_time(e1))
+            committed = sum(batch.stats(i).committed for i in range(len(bw.jobs)))
+            errors = sum(batch.stats(i).error != 0 for i in range(len(bw.jobs)))
+        finally:
+            batch.close()
+        ms = float(np.mean(per))
+        log(f"[bench] batched ({name}): {ms:.1f} ms/launch, {committed / (ms / 1e3) / 1e6:.2f}M txn/s, "
+            f"parity={parity}")
+        return committed / (ms / 1e3), ms, bool(parity) and errors == 0
+
+    batched_value, ms_auto, parity_auto = run_batch(jobs, "Algorithm 1")
+    tuned_value, ms_tuned, parity_tuned = run_batch(jobs_tuned, "per-bucket tuned")
     plain_value = committed_plain / plain_s
-    log(f"[bench] batched: {per.mean():.1f} ms/launch, {batched_value / 1e6:.2f}M txn/s; "
-        f"plain {plain_value / 1e6:.2f}M txn/s")
-    batch.close()
     eng.close()
+    tuned_chosen = [buckets[autotune.bucket_of(db, b.n)]["strategy"] for db, b in bw.jobs]
     return dict(workload=f"{len(bw.jobs)} bulks, log-uniform 256..262144 txns, bank (theta in "
                          f"{{0,0.8,0.99}}) or order-entry by coin flip; two lanes",
-                n_txns=n_txn, batched_txn_per_s=round(batched_value, 1),
-                plain_txn_per_s=round(plain_value, 1), speedup=round(batched_value / plain_value, 3),
-                ms_per_launch=round(float(per.mean()), 3), parity_vs_oracle=bool(parity) and errors == 0,
+                n_txns=n_txn, plain_txn_per_s=round(plain_value, 1),
+                batched_txn_per_s=round(batched_value, 1),
+                batched_tuned_txn_per_s=round(tuned_value, 1),
+                speedup=round(batched_value / plain_value, 3),
+                speedup_tuned=round(tuned_value / plain_value, 3),
+                ms_per_launch=round(ms_auto, 3), ms_per_launch_tuned=round(ms_tuned, 3),
+                parity_vs_oracle={"plain": bool(parity_plain), "batched": parity_auto,
+                                  "batched_tuned": parity_tuned},
                 plain_bulk_latency_ms={"p50": round(float(np.percentile(lat, 50) * 1e3), 4),
                                        "p99": round(float(np.percentile(lat, 99) * 1e3), 4)},
                 calibrated={k: (int(v) if isinstance(v, (int, np.integer)) else v)
                             for k, v in tuned.items() if k != "samples"},
-                chosen={c: chosen.count(c) for c in set(chosen)})
+                chosen={c: chosen.count(c) for c in set(chosen)},
+                tuned_chosen={c: tuned_chosen.count(c) for c in set(tuned_chosen)},
+                buckets={f"{k[0]}/2^{k[1]}": {kk: vv for kk, vv in v.items() if kk != "tried"}
+                         for k, v in buckets.items()},
+                tuning_s=round(tune_s, 1))
 
 
 def bench_serve(args):
@@ -580,13 +709,16 @@ def main():
                     help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
-    ap.add_argument("--sections", default="grid,configs,ceilings,micro,batch,serve",
-                    help="extra sections after the headline bulk: grid,configs,ceilings,micro,batch,"
-                         "serve (or none)")
+    ap.add_argument("--sections", default="grid,configs,ceilings,micro,pool,batch,serve",
+                    help="extra sections after the headline bulk: grid,configs,ceilings,micro,pool,"
+                         "batch,serve (or none)")
     ap.add_argument("--grid-n", type=lambda v: [int(x) for x in v.split(",")],
                     default=[1 << 16, 1 << 18, 1 << 20])
     ap.add_argument("--order-n", type=int, default=1 << 18)
     ap.add_argument("--micro-n", type=int, default=1 << 20)
+    ap.add_argument("--pool-rounds", type=int, default=24)
+    ap.add_argument("--pool-waves", type=int, default=4)
+    ap.add_argument("--pool-drain-steps", type=int, default=4096)
     ap.add_argument("--serve-points", type=lambda v: [(float(p.split(':')[0]), float(p.split(':')[1]))
                                                       for p in v.split(",")],
                     default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 200.0)],
@@ -791,6 +923,8 @@ def main():
                               "frac_of_64_addr": round(per_s / out["ceilings"]["atomic_add_per_s_64_addr"], 6)}
     if "micro" in sections:
         out["divergence_micro"] = bench_micro(args)
+    if "pool" in sections:
+        out["standing_pool"] = bench_pool(args)
     if "batch" in sections:
         out["batched_vs_plain"] = bench_batch(args)
     if "serve" in sections:
