@@ -826,10 +826,10 @@ __device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int6
 // One lane per short partition (fewer than a.long_part transactions): its
 // transactions run one after another, in place.
 // Before PART runs: each transaction's record (input index, type and
-// parameters, one record per serial position) and its appended rows (they
-// depend on the signature alone).  Serial order keeps every read and every
-// appended row contiguous; the partition kernels then read one record per
-// transaction.  Under PART no transaction crosses partitions (Algorithm 1
+// parameters, at its partition-sorted position) and its appended rows (they
+// depend on the signature alone).  The appended rows are written in serial
+// order, so they are contiguous; the records lie together per partition, so
+// a partition kernel reads its records contiguously.  Under PART no transaction crosses partitions (Algorithm 1
 // falls back to TPL otherwise), so every valid transaction is PART's.
 __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     const GtxState* st = a.ws.st;
@@ -1156,6 +1156,72 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     return s;
 }
 
+// The order-entry procedures name distinct cells within one transaction
+// (payment: a warehouse, a district and a customer row; a new-order: its
+// items, checked for repeats here).  Their transactions then run one after
+// another with the whole wave on each, lane r updating the cell of ordinal r
+// -- the partition's order is kept, only one transaction's cells are worked
+// on side by side.  Both return the transaction's status, the same on every
+// lane, and write what serial_one writes.
+template <int Q>  // GPUTX_NEW_ORDER or GPUTX_NEW_ORDER_RB
+__device__ __forceinline__ int32_t wave_new_order(const DevType& T, const PartChunk& c, int k, uint32_t* seen) {
+    const int lane = lane_id();
+    const int64_t nk = c.prm[k * c.ps + 3];
+    const bool live = lane < nk;
+    const int64_t item = live ? c.prm[k * c.ps + 4 + lane] : -1;
+    const int64_t q = live ? c.prm[k * c.ps + 19 + lane] : 0;
+    // a rollback new-order stops at its first unused item
+    const bool unused = Q == GPUTX_NEW_ORDER_RB && live && item == T.dims[3];
+    const uint64_t ub = __ballot(unused);
+    const int stop = ub ? __ffsll((unsigned long long)ub) - 1 : 64;
+    const bool mine = live && lane < stop;
+    const uint32_t at = mine ? c.cs[k * c.css + lane] : 0xffffffffu;
+    bool dup = false;
+#pragma unroll
+    for (int r = 1; r < 15; ++r) {
+        const uint32_t o = __shfl(at, (lane + r) & 63);
+        dup = dup || (mine && o == at);
+    }
+    if (__any(dup)) {  // an item named twice: the updates must follow each other
+        int32_t s = 0;
+        if (lane == 0) s = serial_one<Q>(T, c, k, seen);
+        return __shfl(s, 0);
+    }
+    if (mine) *seen &= at;
+    GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)at;
+    int64_t old = 0;
+    int32_t nv = 0;
+    if (mine) {
+        old = *cell;  // the transaction's undo log entry for this item
+        int64_t s = (int64_t)(int32_t)old - q;
+        if (s < 10) s += 91;
+        nv = to_i32(s);
+        *cell = (int64_t)nv;
+    }
+    if (stop < 64) {  // roll back from the undo log: no effect, results 0
+        if (mine) *cell = old;
+        if (lane < proc_results(Q)) c.res[k * c.rs + lane] = 0;
+        if (lane == 0) c.st[k] = GPUTX_ABORT;
+        return GPUTX_ABORT;
+    }
+    const int32_t before = __shfl(nv, (lane + 63) & 63);  // lane r - 1's new value
+    if (lane < proc_results(Q)) c.res[k * c.rs + lane] = lane == 0 ? nk : (lane - 1 < nk ? (int64_t)before : 0);
+    return GPUTX_COMMIT;
+}
+
+__device__ __forceinline__ int32_t wave_payment(const DevType& T, const PartChunk& c, int k, uint32_t* seen) {
+    const int lane = lane_id();
+    if (lane < 3) {
+        const uint32_t at = c.cs[k * c.css + lane];
+        *seen &= at;
+        GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)at;
+        const int64_t nv = wrap_add(*cell, c.prm[k * c.ps + 3]);
+        *cell = nv;
+        c.res[k * c.rs + lane] = nv;
+    }
+    return GPUTX_COMMIT;
+}
+
 // Wave-wide inclusive scans through DPP (GFX9 controls: shift right within
 // 16-lane rows, then the broadcasts of lanes 15 and 31 that carry the scan
 // across rows).  All 64 lanes must be active.
@@ -1365,6 +1431,63 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         return true;
       }
     }
+    if constexpr (P == 0 || P == GPUTX_NEW_ORDER || P == GPUTX_NEW_ORDER_RB) {
+        // the whole wave on each transaction (order-entry procedures), one
+        // serial wave per cell class; other procedures on lane 0
+        if constexpr (P != 0)
+            if (T.cell_class % sw.nsw != sw.ws) return false;
+        uint32_t seen = ~0u;
+        int n_commit = 0, n_abort = 0;
+        for (int k = 0; k < cnt; ++k) {
+            int32_t pc = P;
+            const DevType* Tk = &T;
+            if constexpr (P == 0) {
+                pc = c.proc[k];
+                if ((pc >> 16) % sw.nsw != sw.ws) continue;
+                Tk = &a.types[c.t[k]];
+            }
+            int32_t s = GPUTX_INVALID;
+            switch (pc & 0xffff) {
+            case GPUTX_NEW_ORDER: s = wave_new_order<GPUTX_NEW_ORDER>(*Tk, c, k, &seen); break;
+            case GPUTX_NEW_ORDER_RB: s = wave_new_order<GPUTX_NEW_ORDER_RB>(*Tk, c, k, &seen); break;
+            case GPUTX_PAYMENT: s = wave_payment(*Tk, c, k, &seen); break;
+            default: {
+                int32_t s0 = 0;
+                if (lane_id() == 0) {
+                    switch (pc & 0xffff) {
+#define GTX_ONE(Q)                                                    \
+    case Q:                                                           \
+        s0 = serial_one<Q>(*Tk, c, k, &seen);                         \
+        break;
+                        GTX_ONE(GPUTX_DEBIT_CREDIT)
+                        GTX_ONE(GPUTX_ORDER_STATUS)
+                        GTX_ONE(GPUTX_GET_SUB)
+                        GTX_ONE(GPUTX_GET_CF)
+                        GTX_ONE(GPUTX_UPD_SUB_FIELD)
+                        GTX_ONE(GPUTX_UPD_LOC)
+                        GTX_ONE(GPUTX_INS_CF)
+                        GTX_ONE(GPUTX_DEL_CF)
+#undef GTX_ONE
+                    default:
+                        s0 = GPUTX_INVALID;
+                        seen = 0;  // a staged transaction of no known procedure
+                    }
+                }
+                s = __shfl(s0, 0);
+            }
+            }
+            n_commit += s == GPUTX_COMMIT;
+            n_abort += s == GPUTX_ABORT;
+        }
+        if (lane_id() == 0) {
+            committed += n_commit;
+            aborted += n_abort;
+        }
+        if (__any(!(seen & 8u))) {
+            if (lane_id() == 0) fail(a.ws.st, GPUTX_E_INTERNAL);
+        }
+        return false;
+    }
     // lane 0 of one serial wave per cell class: classes never share a cell
     if (lane_id() != 0) return false;
     if constexpr (P != 0)
@@ -1397,40 +1520,6 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         int n_commit = 0, n_abort = 0;
         for (int k = 0; k < cnt; ++k) {
             const int32_t s = serial_one<P>(T, c, k, &seen);
-            n_commit += s == GPUTX_COMMIT;
-            n_abort += s == GPUTX_ABORT;
-        }
-        committed += n_commit;
-        aborted += n_abort;
-    } else {
-        // mixed chunk: each transaction dispatches to its procedure's code,
-        // which reads only that procedure's parameters and cells
-        int n_commit = 0, n_abort = 0;
-        for (int k = 0; k < cnt; ++k) {
-            const int32_t pc = c.proc[k];
-            if ((pc >> 16) % sw.nsw != sw.ws) continue;
-            const DevType& Tk = a.types[c.t[k]];
-            int32_t s = GPUTX_INVALID;
-            switch (pc & 0xffff) {
-#define GTX_ONE(Q)                                                    \
-    case Q:                                                           \
-        s = serial_one<Q>(Tk, c, k, &seen);                           \
-        break;
-                GTX_ONE(GPUTX_DEBIT_CREDIT)
-                GTX_ONE(GPUTX_NEW_ORDER)
-                GTX_ONE(GPUTX_NEW_ORDER_RB)
-                GTX_ONE(GPUTX_PAYMENT)
-                GTX_ONE(GPUTX_ORDER_STATUS)
-                GTX_ONE(GPUTX_GET_SUB)
-                GTX_ONE(GPUTX_GET_CF)
-                GTX_ONE(GPUTX_UPD_SUB_FIELD)
-                GTX_ONE(GPUTX_UPD_LOC)
-                GTX_ONE(GPUTX_INS_CF)
-                GTX_ONE(GPUTX_DEL_CF)
-#undef GTX_ONE
-            default:
-                seen = 0;  // a staged transaction of no known procedure
-            }
             n_commit += s == GPUTX_COMMIT;
             n_abort += s == GPUTX_ABORT;
         }

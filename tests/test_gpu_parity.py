@@ -423,3 +423,21 @@ def test_part_forms_with_rollbacks(pipeline):
     assert s.chosen == 2
     assert_parity(s, g, o, bulk)
     assert s.aborted > 100
+
+
+@pytest.mark.parametrize("strategy", ["PART", "TPL", "KSET"])
+@pytest.mark.parametrize("rollback", [0.0, 0.1])
+def test_order_entry_repeated_items(strategy, rollback):
+    """New-orders naming an item twice update that stock row twice in a row
+    (PART's wave-wide form falls back to one lane for them); with rollbacks,
+    the undo log restores the row through both updates."""
+    tabs, types, bulk = util.small_order(27, 8000, n_wh=2, d_per_w=10, c_per_d=30, items_per_w=100,
+                                         rollback_frac=rollback)
+    no = np.flatnonzero(bulk.type == 1)
+    rng = np.random.default_rng(28)
+    rep = no[rng.random(no.size) < 0.3]
+    prm = bulk.params.copy()
+    prm[5, rep] = prm[4, rep]          # second item = first item
+    bulk = wl.Bulk(bulk.type, prm, bulk.ts)
+    s, g, o = run_both(tabs, types, bulk, 16, strategy)
+    assert_parity(s, g, o, bulk)
