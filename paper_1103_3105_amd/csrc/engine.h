@@ -46,6 +46,7 @@ struct Ws {
     int32_t* grp_cnt;    // [mcap] per-group completion counters
     uint32_t* qk[2];     // [n] PART sort: partition id
     uint32_t* qv[2];     // [n] PART sort: serial position
+    uint32_t* qinv;      // [n] PART: partition-grouped position of each serial position
     int32_t* heads;      // [n + 1] PART: first sorted position of each non-empty partition
     int32_t* heads_tmp;  // [head blocks] PART: per-block head counts, then offsets
     // PART: one record per partition-sorted position (k_part_gather): input
@@ -102,6 +103,7 @@ struct BulkArgs {
     int32_t pipe_bits;      // pipelined PART cell table: 1 << pipe_bits slots
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
     int32_t part_scan;      // 1: cellwise procedures run as per-cell map scans
+    int32_t tpl_lanes;      // TPL: transactions per wave window (64: workgroup windows)
     int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane
     int32_t res_rows;       // PART LDS result rows: most results of a registered procedure
     int32_t part_early;     // 1: PART's sort and records run before the choice, beside the ranking
@@ -131,6 +133,7 @@ struct PhaseMarks {
 struct SideLane {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipEvent_t sorted = nullptr;  // the bulk's stream passed the item-key sort
 };
 
 // bulk generation (kernels_front.hip); with a side lane and a.part_early set,
@@ -152,8 +155,11 @@ void launch_rank_full(const BulkArgs& a, hipStream_t s);
 void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm);
 // PART's stable sort of transactions by partition and the partition heads
 // (kernels_exec.hip), gated on the choice; with a.part_early set they run
-// ungated and the records (k_part_gather) follow them on the same stream
+// ungated
 void launch_part_sort(const BulkArgs& a, hipStream_t s);
+// PART's records and the bulk's appended rows (k_part_gather), after the
+// partition sort on the same stream
+void launch_part_gather(const BulkArgs& a, hipStream_t s);
 // zero-transaction bulk: reset state and publish statistics
 void launch_empty(const BulkArgs& a, hipStream_t s);
 // workgroups of the persistent executors that fit on one compute unit

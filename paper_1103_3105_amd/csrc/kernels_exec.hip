@@ -137,6 +137,14 @@ __device__ __forceinline__ void count_status(GtxState* st, bool ran, int32_t s) 
     }
 }
 
+__device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int64_t aborted) {
+    long long c = wave_sum64(committed), ab = wave_sum64(aborted);
+    if (lane_id() == 0) {
+        if (c) atomicAdd((unsigned long long*)&st->committed, (unsigned long long)c);
+        if (ab) atomicAdd((unsigned long long*)&st->aborted, (unsigned long long)ab);
+    }
+}
+
 __device__ __forceinline__ int64_t op_begin(const BulkArgs& a, int64_t p) { return a.ws.cnt[p]; }
 __device__ __forceinline__ int64_t op_end(const BulkArgs& a, int64_t p) {
     return p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : a.ws.st->m;
@@ -400,6 +408,92 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
 // ---------------------------------------------------------------------------
 // TPL with counter-based locks
 
+// TPL's poll back-off: naps of kTplNap x 64 cycles (about 0.25 us), at most
+// kTplMaxNaps between two polls.
+constexpr int kTplNap = 10;
+constexpr int kTplMaxNaps = 8;
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
+// One window of transactions, at most one per lane (type t < 0: none): each
+// waits until every lock counter of its operations reaches its target, runs,
+// and increments the counters.  A lane that becomes ready runs with the
+// wave's other ready lanes; the wave loops until all have run.
+__device__ __forceinline__ void tpl_window(const BulkArgs& a, int64_t p, int32_t t, bool& ran, int32_t& s) {
+    GtxState* st = a.ws.st;
+    bool done = t < 0;
+    int64_t o0 = 0, o1 = 0;
+    TxnIn x;
+    if (!done) {
+        o0 = op_begin(a, p);
+        o1 = op_end(a, p);
+        load_txn(a, p, t, x);  // signatures are immutable: load before waiting
+    }
+    // lock groups and targets of the first ops, kept in registers while waiting
+    constexpr int kPre = 4;
+    int32_t pg[kPre], pt[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        pg[k] = 0;
+        pt[k] = 0;
+        if (!done && o0 + k < o1) {
+            const OpInfo inf = a.ws.op_info[o0 + k];
+            pg[k] = inf.grp;
+            pt[k] = inf.tgt;
+        }
+    }
+    uint64_t t0 = 0;
+    while (__any(!done)) {
+        // how many more releases this lane's farthest counter still needs
+        int lack = 0;
+        if (!done) {
+#pragma unroll
+            for (int k = 0; k < kPre; ++k)
+                if (o0 + k < o1) lack = max(lack, pt[k] - ld_relaxed(&a.ws.grp_cnt[pg[k]]));
+            for (int64_t o = o0 + kPre; o < o1; ++o) {
+                const OpInfo inf = a.ws.op_info[o];
+                lack = max(lack, inf.tgt - ld_relaxed(&a.ws.grp_cnt[inf.grp]));
+            }
+        }
+        const bool ready = !done && lack <= 0;
+        if (__any(ready)) {
+            fence_acquire();  // see every write released by the predecessors
+            if (ready) {
+                s = exec_txn(a, x);
+                ran = true;
+            }
+            fence_release();  // publish this transaction's writes
+            if (ready) {
+#pragma unroll
+                for (int k = 0; k < kPre; ++k)
+                    if (o0 + k < o1) atomicAdd(&a.ws.grp_cnt[pg[k]], 1);
+                for (int64_t o = o0 + kPre; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_info[o].grp], 1);
+                done = true;
+            }
+            t0 = 0;
+        } else {
+            if (t0 == 0) t0 = now_ticks();
+            else if (now_ticks() - t0 > a.spin_ticks) {
+                fail(st, GPUTX_E_DEADLOCK);
+                break;
+            }
+            if (failed(st)) break;
+            // proportional back-off: every release the nearest waiting lane
+            // still needs takes at least one lock hand-off (about a
+            // microsecond), so the wave polls again after a nap per missing
+            // release; only the transactions next in line poll at full rate,
+            // which keeps the polls off the hot counters' lines
+            const int naps = min(wave_min_int(done ? INT32_MAX : lack) - 1, kTplMaxNaps);
+            __builtin_amdgcn_s_sleep(1);
+            for (int z = 0; z < naps; ++z) __builtin_amdgcn_s_sleep(kTplNap);
+        }
+    }
+}
+
 __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_TPL) return;
@@ -409,6 +503,31 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
     __shared__ int toff[GTX_WAVES][GPUTX_MAX_TYPES + 1];
     const int lane = lane_id();
     const int w = wave_id();
+    if (a.tpl_lanes < 64) {
+        // narrow windows: each wave claims tpl_lanes transactions of its own
+        // and the other lanes idle, so a transaction that becomes ready waits
+        // for fewer other critical sections to finish first (deep chains are
+        // bound by the dependent step, not by the work); the status counts
+        // are flushed once at the end
+        const int L = a.tpl_lanes;
+        int64_t committed = 0, aborted = 0;
+        while (true) {
+            uint32_t win = 0;
+            if (lane == 0) win = atomicAdd(&st->ticket, 1u);
+            win = __shfl(win, 0);
+            const int64_t base = (int64_t)win * L;
+            if (base >= a.n || failed(st)) break;
+            const int64_t p = base + lane;
+            const int32_t t = lane < L && p < a.n ? a.ws.tty[p] : -1;
+            bool ran = false;
+            int32_t s = 0;
+            tpl_window(a, p, t, ran, s);
+            committed += ran && s == GPUTX_COMMIT;
+            aborted += ran && s == GPUTX_ABORT;
+        }
+        add_counts(st, committed, aborted);
+        return;
+    }
     while (true) {
         if (threadIdx.x == 0) win_s = (int)atomicAdd(&st->ticket, 1u);
         __syncthreads();
@@ -444,67 +563,9 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
             p = slot_pos[threadIdx.x];
             t = p < a.n ? a.ws.tty[p] : -1;
         }
-        bool done = t < 0;
-        int64_t o0 = 0, o1 = 0;
-        TxnIn x;
-        if (!done) {
-            o0 = op_begin(a, p);
-            o1 = op_end(a, p);
-            load_txn(a, p, t, x);  // signatures are immutable: load before waiting
-        }
-        // lock groups and targets of the first ops, kept in registers while waiting
-        constexpr int kPre = 4;
-        int32_t pg[kPre], pt[kPre];
-#pragma unroll
-        for (int k = 0; k < kPre; ++k) {
-            pg[k] = 0;
-            pt[k] = 0;
-            if (!done && o0 + k < o1) {
-                const OpInfo inf = a.ws.op_info[o0 + k];
-                pg[k] = inf.grp;
-                pt[k] = inf.tgt;
-            }
-        }
-        uint64_t t0 = 0;
-        int32_t s = 0;
         bool ran = false;
-        while (__any(!done)) {
-            bool ready = false;
-            if (!done) {
-                ready = true;
-#pragma unroll
-                for (int k = 0; k < kPre; ++k)
-                    if (o0 + k < o1) ready = ready && ld_relaxed(&a.ws.grp_cnt[pg[k]]) >= pt[k];
-                for (int64_t o = o0 + kPre; o < o1; ++o) {
-                    const OpInfo inf = a.ws.op_info[o];
-                    ready = ready && ld_relaxed(&a.ws.grp_cnt[inf.grp]) >= inf.tgt;
-                }
-            }
-            if (__any(ready)) {
-                fence_acquire();  // see every write released by the predecessors
-                if (ready) {
-                    s = exec_txn(a, x);
-                    ran = true;
-                }
-                fence_release();  // publish this transaction's writes
-                if (ready) {
-#pragma unroll
-                    for (int k = 0; k < kPre; ++k)
-                        if (o0 + k < o1) atomicAdd(&a.ws.grp_cnt[pg[k]], 1);
-                    for (int64_t o = o0 + kPre; o < o1; ++o) atomicAdd(&a.ws.grp_cnt[a.ws.op_info[o].grp], 1);
-                    done = true;
-                }
-                t0 = 0;
-            } else {
-                if (t0 == 0) t0 = now_ticks();
-                else if (now_ticks() - t0 > a.spin_ticks) {
-                    fail(st, GPUTX_E_DEADLOCK);
-                    break;
-                }
-                if (failed(st)) break;
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
+        int32_t s = 0;
+        tpl_window(a, p, t, ran, s);
         count_status(st, ran, s);
         __syncthreads();
     }
@@ -737,6 +798,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_pgroup_scatter(BulkArgs a, const 
         const int64_t dst = (int64_t)start[pid] + a.ws.tsv[0][p];
         a.ws.qk[fb][dst] = pid;
         a.ws.qv[fb][dst] = (uint32_t)p;
+        a.ws.qinv[p] = (uint32_t)dst;
         serial_key[p] = a.ws.tty[p] >= 0 ? dst : -1;
     }
 }
@@ -815,22 +877,16 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_heads_down(BulkArgs a) {
         if (h[j]) a.ws.heads[at++] = (int32_t)(i0 + j);
 }
 
-__device__ __forceinline__ void add_counts(GtxState* st, int64_t committed, int64_t aborted) {
-    long long c = wave_sum64(committed), ab = wave_sum64(aborted);
-    if (lane_id() == 0) {
-        if (c) atomicAdd((unsigned long long*)&st->committed, (unsigned long long)c);
-        if (ab) atomicAdd((unsigned long long*)&st->aborted, (unsigned long long)ab);
-    }
-}
-
 // One lane per short partition (fewer than a.long_part transactions): its
 // transactions run one after another, in place.
 // Before PART runs: each transaction's record (input index, type and
-// parameters, at its partition-sorted position) and its appended rows (they
-// depend on the signature alone).  The appended rows are written in serial
-// order, so they are contiguous; the records lie together per partition, so
-// a partition kernel reads its records contiguously.  Under PART no transaction crosses partitions (Algorithm 1
-// falls back to TPL otherwise), so every valid transaction is PART's.
+// parameters, at its partition-grouped position) and its appended rows (they
+// depend on the signature alone).  The bulk is walked in serial order, so
+// the signatures are read and the appended rows written contiguously; each
+// record goes to its grouped position (qinv), so a partition's records lie
+// together and a partition kernel reads them contiguously.  Under PART no
+// transaction crosses partitions (Algorithm 1 falls back to TPL otherwise),
+// so every valid transaction is PART's.
 __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     const GtxState* st = a.ws.st;
     // ahead of the choice too: the records are workspace, and the appended
@@ -841,32 +897,22 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_part_gather(BulkArgs a) {
     // then fails it).
     for (int k = 0; k < a.n_app; ++k)
         if (st->app_total[k] > 0 && a.rowcount[k] + st->app_total[k] > a.capacity[k]) return;
-    const uint32_t* pos = a.ws.qv[a.part_passes & 1];
     for (int64_t q = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; q < a.n;
          q += (int64_t)gridDim.x * GTX_BLOCK) {
-        // the appended rows of the transaction at serial position q
-        const int32_t tq = a.ws.tty[q];
-        if (tq >= 0) {
-            TxnIn y;
-            load_txn(a, q, tq, y);
-            AppendOnlyAcc ap;
-            int64_t unused[GTX_MAX_RESULTS];
-            (void)txn_exec_any(ap, a.types[tq], y.prm, y.ts, y.app0, y.app1, unused);
-        }
-        // the record of the transaction at partition-sorted position q, so
-        // that a partition's records lie together
-        const int32_t p = (int32_t)pos[q];
-        const int32_t t = a.ws.tty[p];
+        const int32_t t = a.ws.tty[q];
         if (t < 0) continue;
-        const DevType& T = a.types[t];
-        const int64_t i = in_index(a, p);
-        int64_t prm[GTX_MAX_PARAMS];
-        load_params(a.params, a.n, min(a.n_params, T.n_params), i, prm);
-        int64_t* r = a.ws.rec + q * a.rec_words;
-        r[0] = (int64_t)(((uint64_t)(uint32_t)t << 32) | (uint32_t)i);
+        // the appended rows of the transaction at serial position q
+        TxnIn y;
+        load_txn(a, q, t, y);
+        AppendOnlyAcc ap;
+        int64_t unused[GTX_MAX_RESULTS];
+        (void)txn_exec_any(ap, a.types[t], y.prm, y.ts, y.app0, y.app1, unused);
+        // its record, at its grouped position
+        int64_t* r = a.ws.rec + (int64_t)a.ws.qinv[q] * a.rec_words;
+        r[0] = (int64_t)(((uint64_t)(uint32_t)t << 32) | (uint32_t)y.i);
 #pragma unroll
         for (int k = 0; k < GTX_MAX_PARAMS; ++k)
-            if (k < a.prm_rows) r[1 + k] = prm[k];
+            if (k < a.prm_rows) r[1 + k] = y.prm[k];
     }
 }
 
@@ -2032,7 +2078,7 @@ int exec_resident_blocks_per_cu() {
     return cached;
 }
 
-static void launch_part_gather(const BulkArgs& a, hipStream_t s) {
+void launch_part_gather(const BulkArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_part_gather, dim3((unsigned)std::min<int64_t>((a.n + GTX_BLOCK - 1) / GTX_BLOCK, 4096)),
                        dim3(GTX_BLOCK), 0, s, a);
 }
@@ -2053,9 +2099,9 @@ void launch_part_sort(const BulkArgs& a, hipStream_t s) {
     sp.cap = a.n; sp.count_dev = nullptr; sp.npass = a.part_passes;
     sp.gate = a.part_early ? nullptr : &a.ws.st->run_part;
     sp.st = a.ws.st; sp.spin_ticks = a.spin_ticks;
+    sp.inv = a.ws.qinv;  // the records' grouped positions, for k_part_gather
     sort_pairs(sp, s);
     launch_part_heads(a, s);
-    if (a.part_early) launch_part_gather(a, s);
 }
 
 // The partition kernels over the grouped transactions: long partitions get a

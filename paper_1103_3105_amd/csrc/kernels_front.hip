@@ -593,8 +593,6 @@ hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, 
         if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->fork, 0);
         if (e != hipSuccess) return e;
         launch_part_sort(a, side->s);
-        e = hipEventRecord(side->join, side->s);
-        if (e != hipSuccess) return e;
     }
     {
         SortPlan sp{};
@@ -607,6 +605,17 @@ hipError_t launch_front(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm, 
         sort_pairs(sp, s);
     }
     pm.mark(PH_OPSORT, s);
+    if (early) {
+        // PART's records are written beside the ranking rather than beside
+        // the item-key sort: both move much of the bulk through HBM, and the
+        // sort's last pass ran twice as long with the gather beside it
+        e = hipEventRecord(side->sorted, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->sorted, 0);
+        if (e != hipSuccess) return e;
+        launch_part_gather(a, side->s);
+        e = hipEventRecord(side->join, side->s);
+        if (e != hipSuccess) return e;
+    }
     const int nbr = (int)blocks_for(a.mcap, kRankTile);
     hipLaunchKernelGGL(k_rank_up, dim3(nbr), dim3(GTX_BLOCK), 0, s, a);
     hipLaunchKernelGGL(k_rank_mid, dim3(1), dim3(GTX_BLOCK), 0, s, a, nbr);

@@ -58,6 +58,7 @@ extern "C" int gputx_default_options(gputx_options* o) {
     o->grid_blocks = 0;
     o->part_pipeline = 1;
     o->part_scan = 1;
+    o->tpl_lanes = 64;
     return GPUTX_OK;
 }
 
@@ -104,12 +105,14 @@ extern "C" int gputx_create(int dev, const gputx_options* opt, gputx_handle* out
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side.s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->side.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->side.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->side.sorted, hipEventDisableTiming);
     if (e != hipSuccess) {
         int rc = gtx_set_err(nullptr, GPUTX_E_HIP, "device setup failed: %s", hipGetErrorString(e));
         if (h->d_types) (void)hipFree(h->d_types);
         if (h->d_rowcount) (void)hipFree(h->d_rowcount);
         if (h->d_capacity) (void)hipFree(h->d_capacity);
         if (h->side.join) (void)hipEventDestroy(h->side.join);
+        if (h->side.sorted) (void)hipEventDestroy(h->side.sorted);
         if (h->side.fork) (void)hipEventDestroy(h->side.fork);
         if (h->side.s) (void)hipStreamDestroy(h->side.s);
         delete h;
@@ -136,6 +139,7 @@ extern "C" int gputx_destroy(gputx_handle h) {
     (void)hipStreamSynchronize(h->side.s);
     (void)hipEventDestroy(h->side.join);
     (void)hipEventDestroy(h->side.fork);
+    (void)hipEventDestroy(h->side.sorted);
     (void)hipStreamDestroy(h->side.s);
     if (h->ev) {
         for (int i = 0; i < gputx_ctx::kRing * PH_COUNT; ++i) (void)hipEventDestroy(h->ev[i]);
@@ -184,7 +188,8 @@ extern "C" int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n
 
 extern "C" int gputx_set_options(gputx_handle h, const gputx_options* opt) {
     if (!h || !opt) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
-    if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0)
+    if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0 || opt->tpl_lanes < 1 ||
+        opt->tpl_lanes > 64)
         return gtx_set_err(h, GPUTX_E_ARG, "bad option value");
     h->opt = *opt;
     return refresh_layout(h);
@@ -476,6 +481,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.grp_cnt = L.take<int32_t>(mcap);
     w.qk[0] = L.take<uint32_t>(n); w.qk[1] = L.take<uint32_t>(n);
     w.qv[0] = L.take<uint32_t>(n); w.qv[1] = L.take<uint32_t>(n);
+    w.qinv = L.take<uint32_t>(n);
     w.heads = L.take<int32_t>(n + 1);
     w.heads_tmp = L.take<int32_t>(std::max<int64_t>(1, (n + 2047) / 2048));
     int prm_rows = 1;
@@ -559,6 +565,7 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     a.kset_narrow = h->opt.kset_narrow;
     a.part_pipeline = h->opt.part_pipeline;
     a.part_scan = h->opt.part_scan;
+    a.tpl_lanes = h->opt.tpl_lanes;
     a.grid_blocks = grid_blocks;
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
     // PART cell table: at most half full when every lane of a chunk stages

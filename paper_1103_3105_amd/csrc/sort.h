@@ -19,6 +19,8 @@ struct SortPlan {
     const int32_t* gate;       // device flag: sort only when non-zero (nullptr: always)
     GtxState* st;              // bulk state: nothing runs after a bulk error
     uint64_t spin_ticks;       // look-back watchdog
+    uint32_t* inv;             // optional [cap]: inv[value] = the pair's sorted position
+                               // (values must be distinct and below cap)
 };
 
 int64_t sort_tiles(int64_t cap);

@@ -21,6 +21,7 @@
 namespace gtx {
 
 constexpr int kItems = 16;
+constexpr int kHistLoads = 8;
 // Workgroup of a pass: 8 waves for 32-bit keys (8192-key tiles, so half as
 // many tiles walk the look-back chain), 4 for 64-bit keys (LDS for 4096).
 template <class K>
@@ -66,11 +67,20 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_sort_hist(const K* keys, const in
     for (int i = threadIdx.x; i < 8 * 256; i += GTX_BLOCK) (&h[0][0])[i] = 0;
     __syncthreads();
     int64_t count = count_dev ? *count_dev : count_cap;
-    int64_t tid = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * GTX_BLOCK;
-    for (int64_t i = tid; i < count; i += stride) {
-        K k = keys[i];
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[p][digit_of(k, p)], 1u);
+    // kHistLoads keys per thread in flight at once: one load per loop trip
+    // left the kernel waiting on memory latency every trip
+    const int64_t step = (int64_t)gridDim.x * GTX_BLOCK * kHistLoads;
+    for (int64_t i0 = (int64_t)blockIdx.x * GTX_BLOCK * kHistLoads + threadIdx.x; i0 < count; i0 += step) {
+        K k[kHistLoads];
+#pragma unroll
+        for (int j = 0; j < kHistLoads; ++j) {
+            const int64_t i = i0 + (int64_t)j * GTX_BLOCK;
+            k[j] = i < count ? keys[i] : (K)0;
+        }
+#pragma unroll
+        for (int j = 0; j < kHistLoads; ++j)
+            if (i0 + (int64_t)j * GTX_BLOCK < count)
+                for (int p = 0; p < npass; ++p) atomicAdd(&h[p][digit_of(k[j], p)], 1u);
     }
     __syncthreads();
     for (int p = 0; p < npass; ++p) {
@@ -118,11 +128,11 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
                                                          int pass, const uint32_t* hist,
                                                          uint32_t* status, int64_t max_tiles,
                                                          uint32_t* ctrl, const int32_t* gate,
-                                                         GtxState* st, uint64_t spin_ticks) {
+                                                         GtxState* st, uint64_t spin_ticks,
+                                                         uint32_t* __restrict__ inv) {
     constexpr int B = sort_block<K>();
     constexpr int kW = B / 64;
     constexpr int kTile = sort_tile<K>();
-    if (sort_gated(gate, st)) return;
     __shared__ uint32_t tile_s;
     __shared__ uint32_t wcnt[kW][256];
     __shared__ uint32_t dstart[256];
@@ -131,10 +141,19 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
     __shared__ uint32_t svals[kTile];
     __shared__ int scratch[kW + 1];
 
+    // The tile ticket, the gate words, the key count and this digit's global
+    // offset are independent loads: issue them together, then wait once.
+    if (threadIdx.x == 0) {
+        const uint32_t ticket = atomicAdd(&ctrl[pass], 1u);
+        tile_s = sort_gated(gate, st) ? 0xffffffffu : ticket;
+    }
     const int64_t count = count_dev ? *count_dev : count_cap;
-    if (threadIdx.x == 0) tile_s = atomicAdd(&ctrl[pass], 1u);
+    const int d = threadIdx.x;
+    const bool digit = d < 256;
+    const uint32_t goff = digit ? hist[pass * 256 + d] : 0u;
     for (int i = threadIdx.x; i < kW * 256; i += B) (&wcnt[0][0])[i] = 0;
     __syncthreads();
+    if (tile_s == 0xffffffffu) return;
     const int64_t tile = tile_s;
     const int64_t base = tile * kTile;
     if (base >= count) return;
@@ -163,8 +182,6 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
 
     // per digit (threads 0..255): exclusive offsets over waves, block total,
     // block-local start
-    const int d = threadIdx.x;
-    const bool digit = d < 256;
     uint32_t tot = 0;
     if (digit) {
 #pragma unroll
@@ -188,7 +205,7 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
         // walk back over up to kLook predecessors per round trip: their
         // status words are loaded together, then taken nearest first until a
         // prefix (done) or a tile that has not published yet (wait for it)
-        constexpr int kLook = 8;
+        constexpr int kLook = 4;
         int64_t t = tile - 1;
         uint64_t t0 = 0;
         const uint32_t* col = status + (int64_t)pass * max_tiles * 256 + d;
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
         }
         st_relaxed(my, kPrefix | (excl + tot));
     }
-    if (digit) gbase[d] = (int64_t)hist[pass * 256 + d] + excl - dstart[d];
+    if (digit) gbase[d] = (int64_t)goff + excl - dstart[d];
     __syncthreads();
 
 #pragma unroll
@@ -245,8 +262,10 @@ __global__ __launch_bounds__(sort_block<K>()) void k_sort_pass(const K* __restri
     for (int i = threadIdx.x; i < n_here; i += B) {
         K kk = skeys[i];
         int64_t out = gbase[digit_of(kk, pass)] + i;
+        const uint32_t vv = svals[i];
         kout[out] = kk;
-        vout[out] = svals[i];
+        vout[out] = vv;
+        if (inv) inv[vv] = (uint32_t)out;
     }
 }
 
@@ -263,7 +282,7 @@ static void sort_impl(const SortPlan& p, hipStream_t s) {
     if (init_blocks < 1) init_blocks = 1;
     hipLaunchKernelGGL(k_sort_init, dim3(init_blocks), dim3(GTX_BLOCK), 0, s, p.status, n_status,
                        p.hist, p.ctrl, p.gate, p.st);
-    int hist_blocks = (int)std::min<int64_t>(512, (p.cap + GTX_BLOCK * 8 - 1) / (GTX_BLOCK * 8));
+    int hist_blocks = (int)std::min<int64_t>(512, (p.cap + GTX_BLOCK * kHistLoads - 1) / (GTX_BLOCK * kHistLoads));
     if (hist_blocks < 1) hist_blocks = 1;
     hipLaunchKernelGGL(k_sort_hist<K>, dim3(hist_blocks), dim3(GTX_BLOCK), 0, s,
                        (const K*)p.keys[0], p.count_dev, p.cap, p.npass, p.hist, p.ctrl, p.gate, p.st);
@@ -272,7 +291,7 @@ static void sort_impl(const SortPlan& p, hipStream_t s) {
         hipLaunchKernelGGL(k_sort_pass<K>, dim3((unsigned)tiles), dim3(sort_block<K>()), 0, s,
                            (const K*)p.keys[src], (const uint32_t*)p.vals[src], (K*)p.keys[src ^ 1],
                            p.vals[src ^ 1], p.count_dev, p.cap, pass, p.hist, p.status, tiles,
-                           p.ctrl, p.gate, p.st, p.spin_ticks);
+                           p.ctrl, p.gate, p.st, p.spin_ticks, pass == p.npass - 1 ? p.inv : nullptr);
     }
 }
 

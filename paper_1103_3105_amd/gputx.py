@@ -37,7 +37,7 @@ class Options(ctypes.Structure):
     _fields_ = [("w0_bar", c_int64), ("c_bar", c_int64), ("d_bar", c_int64),
                 ("part_size", c_int64), ("group_by_type", c_int32), ("kset_narrow", c_int32),
                 ("spin_limit_ms", c_int32), ("grid_blocks", c_int32), ("part_pipeline", c_int32),
-                ("part_scan", c_int32)]
+                ("part_scan", c_int32), ("tpl_lanes", c_int32)]
 
 
 class TableDesc(ctypes.Structure):

@@ -441,3 +441,26 @@ def test_order_entry_repeated_items(strategy, rollback):
     bulk = wl.Bulk(bulk.type, prm, bulk.ts)
     s, g, o = run_both(tabs, types, bulk, 16, strategy)
     assert_parity(s, g, o, bulk)
+
+
+@pytest.mark.parametrize("lanes", [1, 3, 16, 64])
+@pytest.mark.parametrize("workload", ["bank", "order", "sub"])
+def test_tpl_window_shapes(workload, lanes):
+    """TPL with per-wave windows of `lanes` transactions (the other lanes
+    idle) gives the serial result on skewed bank, order entry with rollbacks
+    and repeated items, and the subscriber mix with aborts; a ragged last
+    window included (sizes not a multiple of the window)."""
+    if workload == "bank":
+        tabs, types, bulk = util.small_bank(61, 20_001, n_branch=8, tpb=10, apt=300, theta=0.9)
+        width, opts = 3, {}
+    elif workload == "order":
+        tabs, types, bulk = util.small_order(62, 6_007, n_wh=2, d_per_w=10, c_per_d=30, items_per_w=40,
+                                             rollback_frac=0.1)
+        width, opts = 16, {}
+    else:
+        tabs, types, bulk = util.small_sub(63, 20_003, n_sub=2000, theta=0.8)
+        width, opts = 14, dict(part_size=16)
+    _say("tpl shape", workload, lanes)
+    s, g, o = run_both(tabs, types, bulk, width, "TPL", tpl_lanes=lanes, **opts)
+    assert s.chosen == 1
+    assert_parity(s, g, o, bulk)
