@@ -89,6 +89,20 @@ __device__ __forceinline__ int32_t exec_txn(const BulkArgs& a, const TxnIn& x) {
     return s;
 }
 
+// exec_txn with the cells accessed coherently across the device (CoherentAcc).
+__device__ __forceinline__ int32_t exec_txn_coherent(const BulkArgs& a, const TxnIn& x) {
+    int64_t res[GTX_MAX_RESULTS];
+    CoherentAcc acc;
+    const int32_t s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+    a.status[x.i] = s;
+    int64_t* out = a.results + x.i * a.width;
+#pragma unroll
+    for (int r = 0; r < GTX_MAX_RESULTS; ++r)
+        if (r < a.width) out[r] = res[r];
+    for (int r = GTX_MAX_RESULTS; r < a.width; ++r) out[r] = 0;
+    return s;
+}
+
 // exec_txn for a chunk whose transactions all run procedure P: the type
 // descriptor is read once per chunk by the caller.
 template <int P>
@@ -461,12 +475,18 @@ __device__ __forceinline__ void tpl_window(const BulkArgs& a, int64_t p, int32_t
         }
         const bool ready = !done && lack <= 0;
         if (__any(ready)) {
-            fence_acquire();  // see every write released by the predecessors
+            // The cells go through coherent loads and stores (CoherentAcc):
+            // a lane loads its cells only after it has seen its counters at
+            // their targets, and moves the counters only after its stores
+            // have completed, so the hand-off needs no cache-wide write-back
+            // or invalidation (which would cost every other wave on the XCD
+            // its cached signatures and operation records too).
+            __asm__ volatile("" ::: "memory");
             if (ready) {
-                s = exec_txn(a, x);
+                s = exec_txn_coherent(a, x);
                 ran = true;
             }
-            fence_release();  // publish this transaction's writes
+            __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
             if (ready) {
 #pragma unroll
                 for (int k = 0; k < kPre; ++k)

@@ -275,6 +275,38 @@ struct DirectAcc {
     __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
 };
 
+// Table cells through agent-scope relaxed atomics, which the device keeps
+// coherent across the XCDs' separate L2 caches load by load (they bypass the
+// caches that are not coherent), so a hand-off needs neither a write-back nor
+// an invalidation of a whole L2: the releasing side waits until its cell
+// stores have completed, the acquiring side loads after it has seen the
+// release.  Appended rows are plain stores: nothing reads them before the
+// kernel ends.
+struct CoherentAcc {
+    template <class V>
+    struct Ref {
+        GTX_GLOBAL V* p;
+        __device__ __forceinline__ V get() const {
+            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __device__ __forceinline__ void set(V v) const {
+            __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    template <class V>
+    __device__ __forceinline__ Ref<V> ref(int, GTX_GLOBAL V* p) { return Ref<V>{p}; }
+    template <class V>
+    __device__ __forceinline__ V ld(int, GTX_GLOBAL V* p) {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    template <class V>
+    __device__ __forceinline__ void st(int, GTX_GLOBAL V* p, V v) {
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    template <class V>
+    __device__ __forceinline__ void app(GTX_GLOBAL V* p, V v) { *p = v; }
+};
+
 // In every procedure below, whether and what a transaction appends depends
 // only on its signature (appending procedures never abort, and appended
 // values come from parameters and the timestamp).  So appends can be split
