@@ -142,12 +142,14 @@ typedef struct {
                               time as a scan of those maps per cell, reported as
                               "PART-scan" (stats.part_scan); 0: every partition runs its
                               transactions one after another (Section 5.2 as written)  */
-    int32_t tpl_lanes;     /* TPL launch shape, 1..64 (default 64): 64 runs windows of
-                              256 transactions per workgroup, grouped by type (Section
-                              5.4); fewer gives each wave its own window of tpl_lanes
+    int32_t tpl_lanes;     /* TPL launch shape, 0..64: 64 runs windows of 256
+                              transactions per workgroup, grouped by type (Section
+                              5.4); 1..32 gives each wave its own window of tpl_lanes
                               transactions, one per lane, the other lanes idle, so a
                               transaction that becomes ready waits on fewer other
-                              critical sections of its wave (deep dependency chains) */
+                              critical sections of its wave (deep dependency chains);
+                              0 (default): chosen per bulk from its average
+                              parallelism n / (d + 1) and the grid's waves          */
 } gputx_options;
 
 /* One relation.  Columns are device arrays of capacity rows, caller-owned,

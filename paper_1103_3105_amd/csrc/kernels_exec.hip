@@ -204,57 +204,78 @@ __device__ __forceinline__ void kset_push(const BulkArgs& a, int32_t* fill, int3
 
 // Run chunk c of the frontier (type regions cut in 64-transaction chunks) and
 // release its successors into the next frontier.
+//
+// Each step of a wave is a chain of dependent memory round trips, which the
+// chunk keeps short: the in-degree decrements of the transaction's first
+// operations are all issued together, before the procedure's loads, so their
+// round trips overlap one another and the procedure's (the next wave starts
+// only after this wave's barrier, so the order inside the wave is free).
+// (Loading the named successors' signatures ahead, toward the cache, measured
+// slower: each extra wave-wide load of 64 scattered lines costs issue time on
+// a path this short.)  Status counts accumulate in the caller's registers.
 __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* cpre, const int* cnt,
                                            const int* reg_off, const int32_t* F, int32_t* fill_next,
-                                           int32_t* F_next) {
+                                           int32_t* F_next, int64_t& committed, int64_t& aborted) {
     int t = 0;
     while (cpre[t + 1] <= c) ++t;  // wave-uniform: this chunk's type
     const int idx = (c - cpre[t]) * 64 + lane_id();
     const bool live = idx < cnt[t];
-    int32_t s = 0;
-    int32_t q = 0;
+    if (!live) return;
     constexpr int kPre = 4;  // op records read before the procedure runs
+    const int32_t q = F[reg_off[t] + idx];
+    const int64_t o0 = op_begin(a, q);
+    const int64_t o1 = op_end(a, q);
     OpInfo pre[kPre];
-    int64_t o0 = 0, o1 = 0;
-    if (live) {
-        q = F[reg_off[t] + idx];
-        o0 = op_begin(a, q);
-        o1 = op_end(a, q);
 #pragma unroll
-        for (int k = 0; k < kPre; ++k)
-            if (o0 + k < o1) pre[k] = a.ws.op_info[o0 + k];
-        s = run_at(a, q, t);
+    for (int k = 0; k < kPre; ++k)
+        if (o0 + k < o1) pre[k] = a.ws.op_info[o0 + k];
+    TxnIn x;
+    load_txn(a, q, t, x);
+    // the first operations' in-degree decrements, all in flight together
+    int32_t left[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k)
+        left[k] = (o0 + k < o1 && pre[k].slo < pre[k].shi) ? atomicSub(&a.ws.indeg[pre[k].s0], 1) : 0;
+    // run this transaction
+    const int32_t s = exec_txn(a, x);
+    committed += s == GPUTX_COMMIT;
+    aborted += s == GPUTX_ABORT;
+    // successors that became ready join the next frontier
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        if (left[k] == 1) {
+            const int slot = atomicAdd(&fill_next[pre[k].s0ty], 1);
+            F_next[reg_off[pre[k].s0ty] + slot] = pre[k].s0;
+        }
     }
-    count_status(a.ws.st, live, s);
-    if (live) {
-        for (int64_t o = o0; o < o1; ++o) {
-            OpInfo inf;
-            if (o - o0 < kPre) {
+    for (int64_t o = o0; o < o1; ++o) {
+        OpInfo inf;
+        if (o - o0 < kPre) {
 #pragma unroll
-                for (int k = 0; k < kPre; ++k)
-                    if (o - o0 == k) inf = pre[k];
-            } else {
-                inf = a.ws.op_info[o];
-            }
+            for (int k = 0; k < kPre; ++k)
+                if (o - o0 == k) inf = pre[k];
+        } else {
+            inf = a.ws.op_info[o];
             if (inf.slo < inf.shi && atomicSub(&a.ws.indeg[inf.s0], 1) == 1) {
                 const int slot = atomicAdd(&fill_next[inf.s0ty], 1);
                 F_next[reg_off[inf.s0ty] + slot] = inf.s0;
             }
-            for (int32_t j = inf.slo + 1; j < inf.shi; ++j) {  // rest of a read run
-                const int32_t q2 = a.ws.srt_txn[j];
-                if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
-            }
+        }
+        for (int32_t j = inf.slo + 1; j < inf.shi; ++j) {  // rest of a read run
+            const int32_t q2 = a.ws.srt_txn[j];
+            if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
         }
     }
 }
 
 // Only when K-SET runs: each transaction's in-degree, the in-edges its
 // operations contribute (Section 4.2's dependency graph) ...
-__global__ __launch_bounds__(GTX_BLOCK) void k_kset_indeg(BulkArgs a) {
+// (The three passes run on K-SET's own persistent grid, before its first
+// wave, with grid barriers between them, so a bulk that runs another
+// executor pays one gated launch for all of K-SET.)
+__device__ __forceinline__ void kset_indeg(const BulkArgs& a, int64_t gt, int64_t gs) {
     const GtxState* st = a.ws.st;
-    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
-    for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
-         p += (int64_t)gridDim.x * GTX_BLOCK) {
+    for (int64_t p = gt; p < a.n; p += gs) {
         int in = 0;
         if (a.ws.tty[p] >= 0) {
             const int64_t o1 = p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : st->m;
@@ -266,24 +287,17 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset_indeg(BulkArgs a) {
 
 // ... the transaction of each operation in item-sorted
 // order (the read runs K-SET releases) ...
-__global__ __launch_bounds__(GTX_BLOCK) void k_kset_sorted_txn(BulkArgs a) {
-    const GtxState* st = a.ws.st;
-    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
-    const int64_t m = st->m;
+__device__ __forceinline__ void kset_sorted_txn(const BulkArgs& a, int64_t gt, int64_t gs) {
+    const int64_t m = a.ws.st->m;
     const uint32_t* val = a.ws.pv[a.key_passes & 1];
-    for (int64_t i = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * GTX_BLOCK)
-        a.ws.srt_txn[i] = a.ws.op_txn[val[i] >> 1];
+    for (int64_t i = gt; i < m; i += gs) a.ws.srt_txn[i] = a.ws.op_txn[val[i] >> 1];
 }
 
 // ... and each operation's first successor transaction and its type, so a
 // wave releases successors without gathers on its own path.
-__global__ __launch_bounds__(GTX_BLOCK) void k_kset_succ(BulkArgs a) {
-    const GtxState* st = a.ws.st;
-    if (ld_relaxed(&st->error) != 0 || st->chosen != GPUTX_KSET) return;
-    const int64_t m = st->m;
-    for (int64_t o = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; o < m;
-         o += (int64_t)gridDim.x * GTX_BLOCK) {
+__device__ __forceinline__ void kset_succ(const BulkArgs& a, int64_t gt, int64_t gs) {
+    const int64_t m = a.ws.st->m;
+    for (int64_t o = gt; o < m; o += gs) {
         OpInfo& inf = a.ws.op_info[o];
         const int32_t slo = inf.slo, shi = inf.shi;
         if (slo < shi) {
@@ -304,9 +318,35 @@ __device__ __forceinline__ int chunk_prefix(const int* cnt, int* cpre) {
     return c;
 }
 
+// Wave 0 of a workgroup, after a narrow wave: the next frontier's per-type
+// counts (fill, which is cleared for the wave after), their total and the
+// chunk prefix.
+__device__ __forceinline__ void kset_level_counts(int* fill, int* wcnt, int* cpre, int* total) {
+    const int l = lane_id();
+    const int v = l < GPUTX_MAX_TYPES ? fill[l] : 0;
+    if (l < GPUTX_MAX_TYPES) fill[l] = 0;
+    const int ch = (v + 63) / 64;
+    int inc = ch;
+#pragma unroll
+    for (int off = 1; off < GPUTX_MAX_TYPES; off <<= 1) {
+        const int y = __shfl_up(inc, off);
+        if (l >= off) inc += y;
+    }
+    int tot = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    if (l < GPUTX_MAX_TYPES) {
+        wcnt[l] = v;
+        cpre[l] = inc - ch;
+    }
+    if (l == GPUTX_MAX_TYPES - 1) cpre[GPUTX_MAX_TYPES] = inc;
+    if (l == 0) *total = tot;
+}
+
 __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
     GtxState* st = a.ws.st;
     if (failed(st) || st->chosen != GPUTX_KSET) return;
+    int64_t committed = 0, aborted = 0;
     __shared__ int reg_off[GPUTX_MAX_TYPES];
     __shared__ int wcnt[GPUTX_MAX_TYPES];
     __shared__ int lfill[GPUTX_MAX_TYPES];
@@ -321,6 +361,13 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
         }
     }
     __syncthreads();
+    // in-degrees and sorted transactions, then first successors (which read
+    // the sorted transactions of the whole grid)
+    const int64_t gt = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x, gs = (int64_t)gridDim.x * GTX_BLOCK;
+    kset_indeg(a, gt, gs);
+    kset_sorted_txn(a, gt, gs);
+    if (!grid_barrier(st, a.spin_ticks)) return;
+    kset_succ(a, gt, gs);
     // wave 0: every valid transaction without predecessors
     for (int64_t p = (int64_t)blockIdx.x * GTX_BLOCK + threadIdx.x; p < a.n;
          p += (int64_t)gridDim.x * GTX_BLOCK) {
@@ -349,24 +396,18 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
             // narrow waves: workgroup 0 runs them alone with workgroup barriers
             if (blockIdx.x == 0) {
                 int64_t kk = k;
+                if (threadIdx.x < GPUTX_MAX_TYPES) lfill[threadIdx.x] = 0;
+                __syncthreads();
                 while (true) {
-                    if (threadIdx.x < GPUTX_MAX_TYPES) lfill[threadIdx.x] = 0;
-                    __syncthreads();
                     const int32_t* F = a.ws.front[kk & 1];
                     int32_t* Fn = a.ws.front[(kk + 1) & 1];
                     for (int c = wave_id(); c < cpre[GPUTX_MAX_TYPES]; c += GTX_WAVES)
-                        kset_chunk(a, c, cpre, wcnt, reg_off, F, lfill, Fn);
+                        kset_chunk(a, c, cpre, wcnt, reg_off, F, lfill, Fn, committed, aborted);
                     __syncthreads();
                     ++kk;
-                    if (threadIdx.x == 0) {
-                        int tot = 0;
-                        for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
-                            wcnt[t] = lfill[t];
-                            tot += lfill[t];
-                        }
-                        total_s = tot;
-                        chunk_prefix(wcnt, cpre);
-                        if ((kk & 63) == 0) st_relaxed(&st->narrow_prog, kk);
+                    if (wave_id() == 0) {
+                        kset_level_counts(lfill, wcnt, cpre, &total_s);
+                        if (lane_id() == 0 && (kk & 63) == 0) st_relaxed(&st->narrow_prog, kk);
                     }
                     __syncthreads();
                     if (total_s == 0 || total_s > a.kset_narrow || failed(st)) break;
@@ -413,9 +454,10 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
         const int32_t* F = a.ws.front[k & 1];
         int32_t* Fn = a.ws.front[(k + 1) & 1];
         for (int c = gw; c < cpre[GPUTX_MAX_TYPES]; c += gwaves)
-            kset_chunk(a, c, cpre, wcnt, reg_off, F, st->kset_fill[(k + 1) % 3], Fn);
+            kset_chunk(a, c, cpre, wcnt, reg_off, F, st->kset_fill[(k + 1) % 3], Fn, committed, aborted);
         ++k;
     }
+    add_counts(st, committed, aborted);
     if (blockIdx.x == 0 && threadIdx.x == 0) st->waves = k;
 }
 
@@ -523,13 +565,22 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_tpl(BulkArgs a) {
     __shared__ int toff[GTX_WAVES][GPUTX_MAX_TYPES + 1];
     const int lane = lane_id();
     const int w = wave_id();
-    if (a.tpl_lanes < 64) {
-        // narrow windows: each wave claims tpl_lanes transactions of its own
-        // and the other lanes idle, so a transaction that becomes ready waits
-        // for fewer other critical sections to finish first (deep chains are
+    // window width: the option, or (0) from the bulk's average parallelism
+    // n / (d + 1) -- enough transactions in flight for about four times the
+    // transactions one dependent step can run, over the grid's waves
+    int L = a.tpl_lanes;
+    if (L == 0) {
+        const int64_t par = a.n / (st->depth + 1);
+        const int64_t want = (4 * par + (int64_t)gridDim.x * GTX_WAVES - 1) / ((int64_t)gridDim.x * GTX_WAVES);
+        L = 1;
+        while (L < 64 && L < want) L <<= 1;
+    }
+    if (L < 64) {
+        // narrow windows: each wave claims L transactions of its own and the
+        // other lanes idle, so a transaction that becomes ready waits for
+        // fewer other critical sections to finish first (deep chains are
         // bound by the dependent step, not by the work); the status counts
         // are flushed once at the end
-        const int L = a.tpl_lanes;
         int64_t committed = 0, aborted = 0;
         while (true) {
             uint32_t win = 0;
@@ -2228,9 +2279,6 @@ void launch_exec(const BulkArgs& a, hipStream_t s, const PhaseMarks& pm) {
     // Algorithm 1 picks K-SET only when the 0-set holds at least w0_bar
     // transactions, which a bulk of fewer cannot reach
     if (a.strategy == GPUTX_KSET || (a.strategy == GPUTX_AUTO && a.n >= a.w0_bar)) {
-        hipLaunchKernelGGL(k_kset_indeg, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_kset_sorted_txn, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
-        hipLaunchKernelGGL(k_kset_succ, dim3(1024), dim3(GTX_BLOCK), 0, s, a);
         hipLaunchKernelGGL(k_kset, dim3(a.grid_blocks), dim3(GTX_BLOCK), 0, s, a);
     }
     pm.mark(PH_KSET, s);

@@ -484,7 +484,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_rank_down(BulkArgs a, int nb_cap)
         inf.shi = shi;
         inf.rank = rank;
         inf.in = in_c;
-        inf.s0 = -1;    // filled by k_kset_succ when K-SET runs
+        inf.s0 = -1;    // filled by kset_succ when K-SET runs
         inf.s0ty = -1;
         a.ws.op_info[o] = inf;
         if (i == gs) a.ws.grp_cnt[g] = 0;

@@ -58,7 +58,7 @@ extern "C" int gputx_default_options(gputx_options* o) {
     o->grid_blocks = 0;
     o->part_pipeline = 1;
     o->part_scan = 1;
-    o->tpl_lanes = 64;
+    o->tpl_lanes = 0;
     return GPUTX_OK;
 }
 
@@ -188,7 +188,7 @@ extern "C" int gputx_phase_times(gputx_handle h, double* ms, int cap, int64_t* n
 
 extern "C" int gputx_set_options(gputx_handle h, const gputx_options* opt) {
     if (!h || !opt) return gtx_set_err(h, GPUTX_E_ARG, "null argument");
-    if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0 || opt->tpl_lanes < 1 ||
+    if (opt->part_size < 1 || opt->spin_limit_ms < 1 || opt->grid_blocks < 0 || opt->tpl_lanes < 0 ||
         opt->tpl_lanes > 64)
         return gtx_set_err(h, GPUTX_E_ARG, "bad option value");
     h->opt = *opt;

@@ -443,7 +443,7 @@ def test_order_entry_repeated_items(strategy, rollback):
     assert_parity(s, g, o, bulk)
 
 
-@pytest.mark.parametrize("lanes", [1, 3, 16, 64])
+@pytest.mark.parametrize("lanes", [0, 1, 3, 16, 64])
 @pytest.mark.parametrize("workload", ["bank", "order", "sub"])
 def test_tpl_window_shapes(workload, lanes):
     """TPL with per-wave windows of `lanes` transactions (the other lanes
