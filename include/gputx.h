@@ -367,9 +367,12 @@ typedef struct {
     int64_t first;              /* first ticket of the bulk                         */
     int64_t count;
     int64_t cut_ns;             /* server clock when the bulk was cut               */
+    int64_t issued_ns;          /* server clock when its copies and graphs were queued */
     int64_t done_ns;            /* server clock when its results were in host memory */
     int32_t error;              /* bulk error, 0 = none                             */
     int32_t slot;
+    int32_t front_us;           /* device time: upload and bulk generation          */
+    int32_t exec_us;            /* device time: execution start to results copied   */
 } gputx_serve_bulk;
 
 typedef struct {

@@ -3,13 +3,14 @@
 // Section 3.2's pipeline: transactions enter a transaction pool, a bulk is
 // formed from the pool at every interval t and runs on the GPU, and the
 // results land in a result pool.  A server (gputx_serve_open) owns both pools
-// in host memory and a native thread that cuts, issues and retires bulks:
+// in host memory and two native threads, one that cuts and issues bulks and
+// one that retires them:
 //   * gputx_serve_submit copies signatures into the transaction pool and
 //     hands out tickets (consecutive sequence numbers);
-//   * every interval the thread cuts everything submitted so far (up to the
-//     largest bulk) and issues it on a free slot;
-//   * a finished bulk's statuses and results are copied into the result
-//     pool, where gputx_serve_poll picks them up in ticket order;
+//   * every interval the issuing thread cuts everything submitted so far (up
+//     to the largest bulk) and issues it on a free slot;
+//   * the retiring thread copies a finished bulk's statuses and results into
+//     the result pool, where gputx_serve_poll picks them up in ticket order;
 //   * gputx_serve_close waits for everything submitted, then frees the slots.
 // gputx_serve replays an arrival trace through the same server: a driver
 // loop submits each transaction once its arrival time has passed and polls
@@ -21,6 +22,8 @@
 //    for a ladder of bulk sizes (four per octave, multiples of 256); a bulk is
 //    padded to its size class with invalid transactions (no effect, outputs
 //    ignored), at most a fifth more work.
+//  * A bulk's upload and its results' return are copy kernels between device
+//    memory and mapped pinned host buffers, on the bulk's own streams.
 //  * Bulk generation of a bulk runs on its slot's stream and overlaps the
 //    execution of earlier bulks; executions are ordered on one stream, so the
 //    database sees the bulks in ticket order.
@@ -30,6 +33,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -48,12 +52,14 @@ struct Slot {
     char* dev = nullptr;             // device buffer (bulk arrays, workspace, outputs, stats)
     char* stage = nullptr;           // pinned host staging of the bulk arrays
     char* out_h = nullptr;           // pinned host copy of statuses, results and stats
+    char* stage_d = nullptr;         // the same two host buffers as the device addresses them
+    char* out_d = nullptr;
     hipStream_t fs = nullptr;
     hipEvent_t ready = nullptr, done = nullptr;
+    hipEvent_t t_up = nullptr, t_exec = nullptr;  // upload start, execution start (timed, with ready and done)
     std::vector<hipGraphExec_t> front, exec;
     std::vector<hipGraph_t> graphs;
-    bool busy = false;
-    int64_t first = 0, count = 0, cut_ns = 0, pad = 0;
+    int64_t first = 0, count = 0, cut_ns = 0, issued_ns = 0, pad = 0;
 };
 
 struct BucketLayout {
@@ -62,6 +68,34 @@ struct BucketLayout {
 };
 
 inline size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Byte copy between device memory and mapped pinned host memory, as a kernel
+// on the bulk's own stream: a bulk's upload and its results' return then
+// take exactly the transfer time, where an asynchronous DMA copy of the same
+// buffers now and then held the server thread and the stream for several
+// milliseconds.  Sizes and offsets are multiples of 4 bytes; 16-byte moves
+// where both sides allow.
+__global__ __launch_bounds__(256) void k_serve_copy(char* __restrict__ dst, const char* __restrict__ src,
+                                                    int64_t bytes) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x, nt = (int64_t)gridDim.x * 256;
+    if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
+        const int64_t n16 = bytes / 16;
+        for (int64_t i = t; i < n16; i += nt)
+            reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+        for (int64_t i = n16 * 4 + t; i < bytes / 4; i += nt)
+            reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(src)[i];
+    } else {
+        for (int64_t i = t; i < bytes / 4; i += nt)
+            reinterpret_cast<uint32_t*>(dst)[i] = reinterpret_cast<const uint32_t*>(src)[i];
+    }
+}
+
+inline hipError_t serve_copy(char* dst, const char* src, int64_t bytes, hipStream_t s) {
+    if (bytes <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(512, (bytes / 16 + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_serve_copy, dim3(blocks), dim3(256), 0, s, dst, src, bytes);
+    return hipGetLastError();
+}
 
 BucketLayout layout_for(int64_t n, int np) {
     BucketLayout L;
@@ -115,7 +149,14 @@ struct gputx_server_t {
     int64_t maxb = 0;
     size_t off_ws = 0, off_status = 0, off_results = 0, off_stats = 0, slot_bytes = 0, ws_bytes = 0;
     Clock::time_point t0;
-    std::thread worker;
+    std::thread worker;   // cuts and issues bulks
+    std::thread retirer;  // waits for bulks in issue order and fills the result pool
+    // slots in flight: busy flags, and a ring of slot ids in issue order
+    // (written by the issuing thread, consumed by the retiring one)
+    std::unique_ptr<std::atomic<int>[]> busy;
+    std::vector<int> ring;
+    std::atomic<int64_t> pushed{0}, popped{0};
+    std::atomic<bool> issue_done{false};
     std::atomic<bool> stop{false};
     std::atomic<int> err{0};
     std::mutex err_mu;
@@ -139,6 +180,8 @@ struct gputx_server_t {
             for (auto g : s.graphs) (void)hipGraphDestroy(g);
             if (s.ready) (void)hipEventDestroy(s.ready);
             if (s.done) (void)hipEventDestroy(s.done);
+            if (s.t_up) (void)hipEventDestroy(s.t_up);
+            if (s.t_exec) (void)hipEventDestroy(s.t_exec);
             if (s.fs) (void)hipStreamDestroy(s.fs);
             if (s.dev) (void)hipFree(s.dev);
             if (s.stage) (void)hipHostFree(s.stage);
@@ -149,54 +192,85 @@ struct gputx_server_t {
         es = nullptr;
     }
     void run();
-    bool retire(std::vector<int>& fifo, size_t& head, bool block);
+    void retire_loop();
+    int retire_one(int si);
     bool issue(int si, int64_t first, int64_t cnt, int64_t now);
 };
 
-// Copy a finished bulk into the result pool (ticket order) and log it.
-bool gputx_server_t::retire(std::vector<int>& fifo, size_t& head, bool block) {
-    while (head < fifo.size()) {
-        Slot& s = slots[fifo[head]];
-        hipError_t q = block ? hipEventSynchronize(s.done) : hipEventQuery(s.done);
-        if (q == hipErrorNotReady) return true;
-        if (q != hipSuccess) {
-            set_error(GPUTX_E_HIP, std::string("bulk completion: ") + hipGetErrorString(q));
-            return false;
-        }
-        const int64_t t = since(t0);
-        last_done = t;
-        const int32_t* st = reinterpret_cast<const int32_t*>(s.out_h);
-        const int64_t* rs = reinterpret_cast<const int64_t*>(s.out_h + up256((size_t)maxb * 4));
-        const gputx_bulk_stats* bs =
-            reinterpret_cast<const gputx_bulk_stats*>(s.out_h + up256((size_t)maxb * 4) + up256((size_t)maxb * 8 * W));
-        for (int64_t j = 0; j < s.count; ++j) {
-            const int64_t k = (s.first + j) % cap;
-            r_status[k] = bs->error ? GPUTX_INVALID : st[j];
-            std::memcpy(&r_results[(size_t)k * W], rs + (size_t)j * W, sizeof(int64_t) * W);
-            r_done[k] = t;
-        }
-        {
-            std::lock_guard<std::mutex> lk(log_mu);
-            gputx_serve_bulk r{};
-            r.first = s.first;
-            r.count = s.count;
-            r.cut_ns = s.cut_ns;
-            r.done_ns = t;
-            r.error = bs->error;
-            r.slot = fifo[head];
-            log.push_back(r);
-            rep.committed += bs->committed;
-            rep.aborted += bs->aborted;
-            rep.invalid += bs->invalid - s.pad;  // padding is not part of the pool
-        }
-        if (bs->error)
-            set_error(bs->error, "bulk at ticket " + std::to_string(s.first) + " failed on the device");
-        answered.store(s.first + s.count, std::memory_order_release);
-        s.busy = false;
-        ++head;
-        block = false;
+// Copy finished bulk si into the result pool (ticket order) and log it.
+// Returns 1 when retired, 0 while it is still running, -1 on an error.
+int gputx_server_t::retire_one(int si) {
+    Slot& s = slots[si];
+    // polled rather than waited on: a blocking wait inside the runtime held
+    // up the issuing thread's launches meanwhile
+    const hipError_t q = hipEventQuery(s.done);
+    if (q == hipErrorNotReady) return 0;
+    if (q != hipSuccess) {
+        set_error(GPUTX_E_HIP, std::string("bulk completion: ") + hipGetErrorString(q));
+        return -1;
     }
-    return true;
+    const int64_t t = since(t0);
+    last_done = t;
+    const int32_t* st = reinterpret_cast<const int32_t*>(s.out_h);
+    const int64_t* rs = reinterpret_cast<const int64_t*>(s.out_h + up256((size_t)maxb * 4));
+    const gputx_bulk_stats* bs =
+        reinterpret_cast<const gputx_bulk_stats*>(s.out_h + up256((size_t)maxb * 4) + up256((size_t)maxb * 8 * W));
+    // the ring may wrap inside the bulk: copy in at most two pieces
+    auto put = [&](int64_t k, int64_t j, int64_t m) {
+        if (bs->error) std::fill(&r_status[k], &r_status[k] + m, (int32_t)GPUTX_INVALID);
+        else std::memcpy(&r_status[k], st + j, sizeof(int32_t) * m);
+        std::memcpy(&r_results[(size_t)k * W], rs + (size_t)j * W, sizeof(int64_t) * W * m);
+        std::fill(&r_done[k], &r_done[k] + m, t);
+    };
+    const int64_t k0 = s.first % cap, c0 = std::min(s.count, cap - k0);
+    put(k0, 0, c0);
+    if (s.count > c0) put(0, c0, s.count - c0);
+    {
+        std::lock_guard<std::mutex> lk(log_mu);
+        gputx_serve_bulk r{};
+        r.first = s.first;
+        r.count = s.count;
+        r.cut_ns = s.cut_ns;
+        r.issued_ns = s.issued_ns;
+        r.done_ns = t;
+        float f_ms = 0.f, x_ms = 0.f;
+        if (hipEventElapsedTime(&f_ms, s.t_up, s.ready) != hipSuccess) f_ms = -1.f;
+        if (hipEventElapsedTime(&x_ms, s.t_exec, s.done) != hipSuccess) x_ms = -1.f;
+        r.front_us = (int32_t)(f_ms * 1000.f);
+        r.exec_us = (int32_t)(x_ms * 1000.f);
+        r.error = bs->error;
+        r.slot = si;
+        log.push_back(r);
+        rep.committed += bs->committed;
+        rep.aborted += bs->aborted;
+        rep.invalid += bs->invalid - s.pad;  // padding is not part of the pool
+    }
+    if (bs->error)
+        set_error(bs->error, "bulk at ticket " + std::to_string(s.first) + " failed on the device");
+    answered.store(s.first + s.count, std::memory_order_release);
+    busy[si].store(0, std::memory_order_release);
+    return 1;
+}
+
+// The retiring thread: bulks complete in issue order (their executions share
+// one stream), so it waits for the oldest in flight, copies its results out
+// and frees its slot -- off the issuing thread, whose cuts it would
+// otherwise hold up by the copy of a large bulk's results.
+void gputx_server_t::retire_loop() {
+    (void)hipSetDevice(h->device);
+    while (true) {
+        const int64_t p = popped.load(std::memory_order_relaxed);
+        if (p < pushed.load(std::memory_order_acquire)) {
+            const int r = retire_one(ring[p % ring.size()]);
+            if (r < 0) break;
+            if (r > 0) popped.store(p + 1, std::memory_order_release);
+            else std::this_thread::yield();
+        } else if (issue_done.load(std::memory_order_acquire)) {
+            if (popped.load() == pushed.load()) break;
+        } else {
+            std::this_thread::yield();
+        }
+    }
 }
 
 // Pack tickets [first, first + cnt) from the pool into slot si and launch it.
@@ -229,54 +303,51 @@ bool gputx_server_t::issue(int si, int64_t first, int64_t cnt, int64_t now) {
     s.count = cnt;
     s.pad = L.n - cnt;
     s.cut_ns = now;
-    s.busy = true;
-    char* oh = s.out_h;
     const size_t o_res = up256((size_t)maxb * 4), o_stats = o_res + up256((size_t)maxb * 8 * W);
-    hipError_t e = hipMemcpyAsync(s.dev, s.stage, L.bytes, hipMemcpyHostToDevice, s.fs);
+    hipError_t e = hipEventRecord(s.t_up, s.fs);
+    if (e == hipSuccess) e = serve_copy(s.dev, s.stage_d, (int64_t)L.bytes, s.fs);
     if (e == hipSuccess) e = hipGraphLaunch(s.front[bi], s.fs);
     if (e == hipSuccess) e = hipEventRecord(s.ready, s.fs);
     if (e == hipSuccess) e = hipStreamWaitEvent(es, s.ready, 0);
+    if (e == hipSuccess) e = hipEventRecord(s.t_exec, es);
     if (e == hipSuccess) e = hipGraphLaunch(s.exec[bi], es);
-    if (e == hipSuccess) e = hipMemcpyAsync(oh, s.dev + off_status, cnt * 4, hipMemcpyDeviceToHost, es);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(oh + o_res, s.dev + off_results, (size_t)cnt * 8 * W, hipMemcpyDeviceToHost, es);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(oh + o_stats, s.dev + off_stats, sizeof(gputx_bulk_stats), hipMemcpyDeviceToHost, es);
+    if (e == hipSuccess) e = serve_copy(s.out_d, s.dev + off_status, cnt * 4, es);
+    if (e == hipSuccess) e = serve_copy(s.out_d + o_res, s.dev + off_results, cnt * 8 * W, es);
+    if (e == hipSuccess) e = serve_copy(s.out_d + o_stats, s.dev + off_stats, (int64_t)sizeof(gputx_bulk_stats), es);
     if (e == hipSuccess) e = hipEventRecord(s.done, es);
     if (e != hipSuccess) {
         set_error(GPUTX_E_HIP, std::string("issuing a bulk failed: ") + hipGetErrorString(e));
         return false;
     }
+    s.issued_ns = since(t0);
     return true;
 }
 
-// The server thread: every interval, cut what the pool holds into a bulk.
+// The issuing thread: every interval, cut what the pool holds into a bulk.
 void gputx_server_t::run() {
     (void)hipSetDevice(h->device);
     const int64_t D = o.deadline_ns;
-    std::vector<int> fifo;  // in-flight slots in issue order
-    size_t head = 0;
     int64_t issued = 0, deadline = D;
     int next_slot = 0;
     const int nslots = (int)slots.size();
-    while (true) {
-        if (!retire(fifo, head, false)) break;
-        if (head == fifo.size()) {  // nothing in flight: compact the fifo
-            fifo.clear();
-            head = 0;
-        }
+    while (!err.load(std::memory_order_relaxed)) {
         const int64_t sub = submitted.load(std::memory_order_acquire);
         const bool stopping = stop.load(std::memory_order_acquire);
-        if (stopping && issued == sub && head == fifo.size()) break;
+        if (stopping && issued == sub) break;
         const int64_t now = since(t0);
         if (issued < sub && (now >= deadline || stopping)) {
-            if (slots[next_slot].busy) {  // admission: wait for the oldest bulk in flight
+            if (busy[next_slot].load(std::memory_order_acquire)) {  // admission: wait for a slot
                 std::this_thread::yield();
                 continue;
             }
             const int64_t cnt = std::min(sub - issued, maxb);
-            if (!issue(next_slot, issued, cnt, now)) break;
-            fifo.push_back(next_slot);
+            busy[next_slot].store(1, std::memory_order_relaxed);
+            if (!issue(next_slot, issued, cnt, now)) {
+                busy[next_slot].store(0, std::memory_order_relaxed);
+                break;
+            }
+            ring[pushed.load(std::memory_order_relaxed) % nslots] = next_slot;
+            pushed.fetch_add(1, std::memory_order_release);
             next_slot = (next_slot + 1) % nslots;
             issued += cnt;
             if (issued == sub) deadline = (now / D) * D + D;
@@ -285,13 +356,7 @@ void gputx_server_t::run() {
             std::this_thread::yield();
         }
     }
-    (void)retire(fifo, head, true);
-    (void)hipStreamSynchronize(es);
-    std::lock_guard<std::mutex> lk(log_mu);
-    rep.n_bulks = (int64_t)log.size();
-    rep.elapsed_ns = last_done;
-    rep.slots_used = nslots;
-    rep.slot_bytes = (int64_t)slot_bytes;
+    issue_done.store(true, std::memory_order_release);
 }
 
 extern "C" int gputx_serve_open(gputx_handle h, const gputx_serve_opts* o, int32_t n_params,
@@ -341,6 +406,9 @@ extern "C" int gputx_serve_open(gputx_handle h, const gputx_serve_opts* o, int32
                            (long long)pool_capacity);
     }
     S->slots.resize(nslots);
+    S->busy.reset(new std::atomic<int>[nslots]);
+    for (int i = 0; i < nslots; ++i) S->busy[i].store(0);
+    S->ring.assign(nslots, 0);
 #define OPEN_OK(call)                                                                             \
     do {                                                                                          \
         hipError_t e_ = (call);                                                                   \
@@ -357,11 +425,15 @@ extern "C" int gputx_serve_open(gputx_handle h, const gputx_serve_opts* o, int32
                              up256(sizeof(gputx_bulk_stats));
     for (auto& s : S->slots) {
         OPEN_OK(hipMalloc(&s.dev, S->slot_bytes));
-        OPEN_OK(hipHostMalloc(&s.stage, big.bytes, hipHostMallocDefault));
-        OPEN_OK(hipHostMalloc(&s.out_h, out_bytes, hipHostMallocDefault));
+        OPEN_OK(hipHostMalloc(&s.stage, big.bytes, hipHostMallocMapped));
+        OPEN_OK(hipHostMalloc(&s.out_h, out_bytes, hipHostMallocMapped));
+        OPEN_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&s.stage_d), s.stage, 0));
+        OPEN_OK(hipHostGetDevicePointer(reinterpret_cast<void**>(&s.out_d), s.out_h, 0));
         OPEN_OK(hipStreamCreateWithFlags(&s.fs, hipStreamNonBlocking));
-        OPEN_OK(hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
-        OPEN_OK(hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+        OPEN_OK(hipEventCreate(&s.ready));
+        OPEN_OK(hipEventCreate(&s.done));
+        OPEN_OK(hipEventCreate(&s.t_up));
+        OPEN_OK(hipEventCreate(&s.t_exec));
         for (int64_t n : S->sizes) {
             const BucketLayout L = layout_for(n, np);
             gputx_bulk b{};
@@ -407,11 +479,20 @@ extern "C" int gputx_serve_open(gputx_handle h, const gputx_serve_opts* o, int32
 #undef OPEN_OK
     S->t0 = Clock::now();
     try {
-        S->worker = std::thread([S] { S->run(); });
+        S->retirer = std::thread([S] { S->retire_loop(); });
     } catch (...) {
         S->release();
         delete S;
-        return gtx_set_err(h, GPUTX_E_STATE, "could not start the server thread");
+        return gtx_set_err(h, GPUTX_E_STATE, "could not start the server threads");
+    }
+    try {
+        S->worker = std::thread([S] { S->run(); });
+    } catch (...) {
+        S->issue_done.store(true);
+        S->retirer.join();
+        S->release();
+        delete S;
+        return gtx_set_err(h, GPUTX_E_STATE, "could not start the server threads");
     }
     *out = S;
     return GPUTX_OK;
@@ -479,6 +560,18 @@ extern "C" int gputx_serve_close(gputx_server S, gputx_serve_report* report) {
     if (!S) return gtx_set_err(nullptr, GPUTX_E_ARG, "null server");
     S->stop.store(true, std::memory_order_release);
     if (S->worker.joinable()) S->worker.join();
+    if (S->retirer.joinable()) S->retirer.join();
+    // after an error bulks may still be in flight: drain before freeing
+    (void)hipSetDevice(S->h->device);
+    (void)hipStreamSynchronize(S->es);
+    for (auto& sl : S->slots) (void)hipStreamSynchronize(sl.fs);
+    {
+        std::lock_guard<std::mutex> lk(S->log_mu);
+        S->rep.n_bulks = (int64_t)S->log.size();
+        S->rep.elapsed_ns = S->last_done;
+        S->rep.slots_used = (int32_t)S->slots.size();
+        S->rep.slot_bytes = (int64_t)S->slot_bytes;
+    }
     int rc = GPUTX_OK;
     const int e = S->err.load();
     if (e) rc = gtx_set_err(S->h, e, "%s", S->err_msg.c_str());

@@ -93,8 +93,9 @@ class ServeOpts(ctypes.Structure):
 
 
 class ServeBulk(ctypes.Structure):
-    _fields_ = [("first", c_int64), ("count", c_int64), ("cut_ns", c_int64), ("done_ns", c_int64),
-                ("error", c_int32), ("slot", c_int32)]
+    _fields_ = [("first", c_int64), ("count", c_int64), ("cut_ns", c_int64), ("issued_ns", c_int64),
+                ("done_ns", c_int64), ("error", c_int32), ("slot", c_int32), ("front_us", c_int32),
+                ("exec_us", c_int32)]
 
 
 class ServeReport(ctypes.Structure):
