@@ -640,6 +640,26 @@ def bench_batch(args):
                 tuning_s=round(tune_s, 1))
 
 
+def bench_partsize(args):
+    """PART across partition sizes (root keys per partition, Section 5.2's
+    tuning parameter; Appendix F.1): the subscriber bulk (root: subscriber)
+    and the scaled bank bulk (root: branch), each size checked against the
+    oracle, then the size the calibration picks."""
+    from paper_1103_3105_amd import autotune, workloads as wl
+    out = {}
+    cases = [("subscriber", wl.config5(n=100_000, n_sub=args.n_sub), (1, 4, 16, 64, 256, 1024, 4096)),
+             ("bank", wl.config2(n=1 << 18, theta=0.0, history_capacity=1 << 18), (1, 2, 4, 8))]
+    for name, w, sizes in cases:
+        width = w.n_results
+        strats = [(f"size={s}", "PART", {"part_size": s}) for s in sizes]
+        r = run_strategies(w, w.bulks[0], width, strats, part_size=sizes[0], label=f"part size, {name}")
+        tuned = autotune.tune_part_size(w.tables, w.types, [(w.bulks[0], width, 0)], sizes=sizes, log=log)
+        out[name] = dict(n=w.bulks[0].n, sizes={k: dict(ms=v["ms"], ran=v["ran"], parity=v["parity"])
+                                                for k, v in r.items()},
+                         calibrated=tuned["best"])
+    return out
+
+
 def bench_serve(args):
     """Served form: Poisson arrivals over 10M subscribers, a bulk every deadline."""
     from paper_1103_3105_amd import autotune, gputx, serving, workloads as wl
@@ -661,8 +681,10 @@ def bench_serve(args):
     try:
         for k, (rate, dl) in enumerate(args.serve_points):
             trace = serving.make_trace(rate, args.serve_seconds, args.n_sub, seed=int(rate) % 97)
-            res = serving.serve(eng, trace, dl, slots=args.slots, width=14, max_bulk=1 << 17)
+            res = serving.serve(eng, trace, dl, slots=args.slots, width=14, max_bulk=args.serve_max_bulk)
             pc = res.percentiles()
+            b = res.bulks
+            gaps = np.diff(b["cut_ns"]) / 1e3 if len(b) > 1 else np.zeros(1)
             if k == 0:  # first point starts from the initial tables: check it against the oracle
                 o_tabs = {kk: v.copy() for kk, v in tabs.items()}
                 rc, o_st, o_res = oracle.run_serial(o_tabs, wl.sub_types(), trace.type, trace.params,
@@ -675,7 +697,15 @@ def bench_serve(args):
                                p50_us=round(pc["p50_us"], 1), p99_us=round(pc["p99_us"], 1),
                                bulks=int(res.bulks.shape[0]),
                                mean_bulk=round(float(res.bulks["count"].mean()), 1),
-                               slots=res.slots_used))
+                               slots=res.slots_used,
+                               # per-bulk log: device time of execution (with the results'
+                               # return) and of upload + generation, host time to pack and
+                               # issue, and the largest gap between two cuts
+                               exec_us_p50=float(np.percentile(b["exec_us"], 50)),
+                               exec_us_p99=float(np.percentile(b["exec_us"], 99)),
+                               front_us_p99=float(np.percentile(b["front_us"], 99)),
+                               pack_us_p99=float(np.percentile((b["issued_ns"] - b["cut_ns"]) / 1e3, 99)),
+                               cut_gap_us_max=float(gaps.max())))
             log(f"[bench] serve rate={rate:.0e}/s deadline={dl}us: {res.throughput / 1e6:.2f}M txn/s "
                 f"p50={pc['p50_us']:.0f}us p99={pc['p99_us']:.0f}us bulks={res.bulks.shape[0]}")
     finally:
@@ -709,9 +739,9 @@ def main():
                     help="PART with a staging wave beside the serial one (1) or one wave (0)")
     ap.add_argument("--batch-only", action="store_true", help="only the 512-bulk batched form")
     ap.add_argument("--bulks", type=int, default=512)
-    ap.add_argument("--sections", default="grid,configs,ceilings,micro,pool,batch,serve",
-                    help="extra sections after the headline bulk: grid,configs,ceilings,micro,pool,"
-                         "batch,serve (or none)")
+    ap.add_argument("--sections", default="grid,configs,ceilings,partsize,micro,pool,batch,serve",
+                    help="extra sections after the headline bulk: grid,configs,ceilings,partsize,micro,"
+                         "pool,batch,serve (or none)")
     ap.add_argument("--grid-n", type=lambda v: [int(x) for x in v.split(",")],
                     default=[1 << 16, 1 << 18, 1 << 20])
     ap.add_argument("--order-n", type=int, default=1 << 18)
@@ -721,8 +751,10 @@ def main():
     ap.add_argument("--pool-drain-steps", type=int, default=4096)
     ap.add_argument("--serve-points", type=lambda v: [(float(p.split(':')[0]), float(p.split(':')[1]))
                                                       for p in v.split(",")],
-                    default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 200.0)],
+                    default=[(1e6, 1000.0), (1e7, 500.0), (5e7, 300.0)],
                     help="rate:deadline_us,...")
+    ap.add_argument("--serve-max-bulk", type=int, default=1 << 15,
+                    help="largest bulk the server cuts (a backlog is cut in pieces of this size)")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()
@@ -921,6 +953,8 @@ def main():
                               "per_s": round(per_s),
                               "frac_of_random_atomic": round(per_s / out["ceilings"]["atomic_add_per_s_random_2^26_addr"], 6),
                               "frac_of_64_addr": round(per_s / out["ceilings"]["atomic_add_per_s_64_addr"], 6)}
+    if "partsize" in sections:
+        out["part_size"] = bench_partsize(args)
     if "micro" in sections:
         out["divergence_micro"] = bench_micro(args)
     if "pool" in sections:

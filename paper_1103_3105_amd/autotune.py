@@ -121,6 +121,42 @@ def calibrate(tables, types, sample_bulks: Sequence[tuple], narrow=(64, 256, 102
     return th
 
 
+def tune_part_size(tables, types, sample_bulks: Sequence[tuple], sizes=(1, 4, 16, 64, 256, 1024),
+                   log=None, engine_opts=None) -> dict:
+    """Section 5.2's tuning parameter: the partition size (root keys per
+    partition) PART runs fastest with on the sample bulks, from a candidate
+    set (Appendix F.1 measures PART across partition sizes).  Each candidate
+    runs every sample under PART on a scratch copy of the database; a bulk
+    whose transactions cross partitions at that size runs under TPL (Section
+    5.2), and its time counts as it is.  Returns {best, ms: {size: total ms},
+    ran: {size: executors that ran}}."""
+    from . import gputx
+    scratch = {k: v.copy() for k, v in tables.items()}
+    for t in scratch.values():
+        if t.append:
+            cap = max(b.n for b, _, _ in sample_bulks) * 16
+            t.cols = [np.zeros(cap, c.dtype) for c in t.cols]
+            t.capacity, t.n_rows = cap, 0
+    eng = gputx.Engine(scratch, types, **(engine_opts or {}))
+    ms, ran = {}, {}
+    try:
+        for size in sizes:
+            eng.set_options(part_size=int(size))
+            tot, labels = 0.0, set()
+            for b, width, mo in sample_bulks:
+                dev = eng.bulk_to_device(b)
+                t, st = _time(eng, dev, "PART", width, mo, reps=1)
+                tot += t
+                labels.add(st.label)
+            ms[int(size)] = round(tot, 4)
+            ran[int(size)] = sorted(labels)
+            if log:
+                log(f"[tune] part_size={size}: {tot:.3f} ms ({', '.join(sorted(labels))})")
+    finally:
+        eng.close()
+    return dict(best=min(ms, key=ms.get), ms=ms, ran=ran)
+
+
 def bucket_of(db: str, n: int) -> tuple:
     """Shape bucket of a bulk: its database and the power of two below its size."""
     return (db, max(0, int(n).bit_length() - 1))

@@ -464,3 +464,18 @@ def test_tpl_window_shapes(workload, lanes):
     s, g, o = run_both(tabs, types, bulk, width, "TPL", tpl_lanes=lanes, **opts)
     assert s.chosen == 1
     assert_parity(s, g, o, bulk)
+
+
+def test_part_size_sweep_and_tuning():
+    """PART at several partition sizes (root keys per partition, Section
+    5.2's tuning parameter) gives the serial result each time, and the
+    calibration returns one of the candidates with a time for each."""
+    from paper_1103_3105_amd import autotune
+    tabs, types, bulk = util.small_sub(64, 8_000, n_sub=2000, theta=0.8)
+    for size in (1, 16, 256):
+        _say("part size", size)
+        s, g, o = run_both(tabs, types, bulk, 14, "PART", part_size=size)
+        assert_parity(s, g, o, bulk)
+    tuned = autotune.tune_part_size(tabs, types, [(bulk, 14, 0)], sizes=(1, 16, 256))
+    assert tuned["best"] in (1, 16, 256)
+    assert set(tuned["ms"]) == {1, 16, 256} and all(v > 0 for v in tuned["ms"].values())
