@@ -190,6 +190,13 @@ typedef struct {
     int32_t ts_sorted;      /* 1: caller promises ascending ts (checked on device)  */
     int32_t max_ops;        /* most basic operations per txn, 0: the context's maximum
                                over registered types (checked on device)            */
+    uint32_t type_mask;     /* registered types the bulk may hold (bit t: type t); 0:
+                               all.  PART's per-chunk LDS rows are sized for these
+                               types only (a context that registers order entry
+                               and debit-credit runs debit-credit bulks with the
+                               debit-credit layout); a transaction of a type outside
+                               the mask is INVALID                                   */
+    int32_t reserved;       /* 0                                                     */
 } gputx_bulk;
 
 /* Written by the device during gputx_execute_bulk; read it after the stream

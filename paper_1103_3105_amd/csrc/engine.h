@@ -104,6 +104,7 @@ struct BulkArgs {
     int32_t part_pipeline;  // 1: k_part_pipe where it fits, 0: k_part_wave
     int32_t part_scan;      // 1: cellwise procedures run as per-cell map scans
     int32_t tpl_lanes;      // TPL: transactions per wave window (64: workgroup windows, 0: from n / (d + 1))
+    uint32_t type_mask;     // registered types the bulk may hold (others are INVALID)
     int32_t long_part;      // PART: partitions this long get a workgroup, shorter a lane
     int32_t res_rows;       // PART LDS result rows: most results of a registered procedure
     int32_t part_early;     // 1: PART's sort and records run before the choice, beside the ranking

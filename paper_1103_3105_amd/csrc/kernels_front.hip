@@ -77,7 +77,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_prepare(BulkArgs a) {
         const int32_t t = a.type[i];
         bool valid = false;
         int nops = 0, a0 = 0, a1 = 0, ai0 = -1, ai1 = -1;
-        if (t >= 0 && t < GPUTX_MAX_TYPES && a.types[t].proc != 0) {
+        if (t >= 0 && t < GPUTX_MAX_TYPES && ((a.type_mask >> t) & 1u) && a.types[t].proc != 0) {
             const DevType& T = a.types[t];
             int64_t prm[GTX_MAX_PARAMS];
             load_params(a.params, a.n, min(a.n_params, T.n_params), i, prm);

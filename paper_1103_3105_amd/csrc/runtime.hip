@@ -570,11 +570,16 @@ int gtx_make_args(gputx_handle h, const gputx_bulk* b, int strategy, void* works
     a.spin_ticks = (uint64_t)h->opt.spin_limit_ms * h->wall_khz;
     // PART cell table: at most half full when every lane of a chunk stages
     // the most cells any registered procedure lists
+    uint32_t present = 0;
+    for (int i = 0; i < GPUTX_MAX_TYPES; ++i)
+        if (h->type_present[i]) present |= 1u << i;
+    a.type_mask = (b->type_mask ? b->type_mask : present) & present;
+    if (!a.type_mask) return gtx_set_err(h, GPUTX_E_ARG, "type_mask names no registered type");
     a.cells_max = 1;
     a.prm_rows = 1;
     a.res_rows = 1;
     for (int i = 0; i < GPUTX_MAX_TYPES; ++i) {
-        if (!h->type_present[i]) continue;
+        if (!((a.type_mask >> i) & 1u)) continue;
         a.cells_max = std::max(a.cells_max, proc_cells(h->types[i].proc));
         a.prm_rows = std::max(a.prm_rows, proc_params(h->types[i].proc));
         a.res_rows = std::max(a.res_rows, proc_results(h->types[i].proc));

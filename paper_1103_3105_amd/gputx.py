@@ -55,7 +55,8 @@ class TypeDesc(ctypes.Structure):
 
 class BulkDesc(ctypes.Structure):
     _fields_ = [("n", c_int64), ("type", c_void_p), ("params", c_void_p), ("n_params", c_int32),
-                ("ts", c_void_p), ("ts_sorted", c_int32), ("max_ops", c_int32)]
+                ("ts", c_void_p), ("ts_sorted", c_int32), ("max_ops", c_int32),
+                ("type_mask", ctypes.c_uint32), ("reserved", c_int32)]
 
 
 class BulkStats(ctypes.Structure):
@@ -494,9 +495,14 @@ class Engine:
         return self._ws
 
     def bulk_to_device(self, bulk) -> dict:
+        # the types the bulk holds (the library sizes PART's layout for them)
+        t = np.asarray(bulk.type)
+        t = t[(t >= 0) & (t < MAX_TYPES)]
+        mask = int(np.bitwise_or.reduce(np.left_shift(1, np.unique(t)).astype(np.uint32))) if t.size else 0
         return dict(type=torch.from_numpy(np.ascontiguousarray(bulk.type)).to(self.device),
                     params=torch.from_numpy(np.ascontiguousarray(bulk.params)).to(self.device),
-                    ts=torch.from_numpy(np.ascontiguousarray(bulk.ts)).to(self.device))
+                    ts=torch.from_numpy(np.ascontiguousarray(bulk.ts)).to(self.device),
+                    type_mask=mask)
 
     @staticmethod
     def bulk_desc(dev: dict, ts_sorted: bool, max_ops: int = 0) -> BulkDesc:
@@ -508,6 +514,7 @@ class Engine:
         b.n_params = dev["params"].shape[0]
         b.ts = dev["ts"].data_ptr()
         b.ts_sorted = 1 if ts_sorted else 0
+        b.type_mask = dev.get("type_mask", 0)
         return b
 
     def execute(self, dev: dict, strategy: int, width: int, ts_sorted: bool = False,

@@ -479,3 +479,43 @@ def test_part_size_sweep_and_tuning():
     tuned = autotune.tune_part_size(tabs, types, [(bulk, 14, 0)], sizes=(1, 16, 256))
     assert tuned["best"] in (1, 16, 256)
     assert set(tuned["ms"]) == {1, 16, 256} and all(v > 0 for v in tuned["ms"].values())
+
+
+def test_type_mask_layout_and_exclusion():
+    """A context with order entry and debit-credit registered: a bank bulk
+    whose type mask names debit-credit alone runs with debit-credit's PART
+    layout and gives the serial result; a mask that leaves a present type out
+    makes that type's transactions INVALID (and the rest still serial)."""
+    import torch
+    from paper_1103_3105_amd import batching, gputx
+    bw = batching.config4(n_bulks=6, lo=2048, hi=4096, repeats=1, bank_branches=8,
+                          accounts_per_branch=1000, n_wh=4, items_per_w=1000, c_per_d=30)
+    db, bulk = next((d, b) for d, b in bw.jobs if d == "bank")
+    eng = gputx.Engine(bw.tables, bw.types)
+    try:
+        dev = eng.bulk_to_device(bulk)
+        want_mask = int(np.bitwise_or.reduce(np.left_shift(1, np.unique(bulk.type))))
+        assert dev["type_mask"] == want_mask
+        st, res, stats = eng.execute(dev, gputx.STRATEGY["PART"], batching.WIDTH[db], ts_sorted=True)
+        torch.cuda.synchronize()
+        s = gputx.stats_from(stats)
+        g_st, g_res = st.cpu().numpy()[:bulk.n], res.cpu().numpy()[:bulk.n]
+    finally:
+        eng.close()
+    o_tabs = util.copy_tables(bw.tables)
+    rc, o_st, o_res = oracle.run_serial(o_tabs, bw.types, bulk.type, bulk.params, bulk.ts, batching.WIDTH[db])
+    assert rc == 0 and s.error == 0
+    assert np.array_equal(g_st, o_st) and np.array_equal(g_res, o_res)
+    # leave the bulk's only type out of the mask (keep another registered type)
+    other = next(t.type_id for t in bw.types if t.type_id not in set(np.unique(bulk.type).tolist()))
+    eng = gputx.Engine(bw.tables, bw.types)
+    try:
+        dev = eng.bulk_to_device(bulk)
+        dev["type_mask"] = 1 << other
+        st, res, stats = eng.execute(dev, gputx.STRATEGY["AUTO"], batching.WIDTH[db], ts_sorted=True)
+        torch.cuda.synchronize()
+        s = gputx.stats_from(stats)
+        assert s.error == 0 and s.invalid == bulk.n and s.committed == 0
+        assert np.all(st.cpu().numpy()[:bulk.n] == 2)
+    finally:
+        eng.close()

@@ -33,6 +33,13 @@ def _check_records(res, trace, deadline_ns, max_bulk):
     assert np.all(trace.arrival_ns[last] <= recs["cut_ns"])
     assert np.all(recs["done_ns"] >= recs["cut_ns"])
     assert np.all(np.diff(recs["done_ns"]) >= 0)          # answered in issue order
+    # the per-bulk timings: issued after the cut and before the results were
+    # back; the device times are measured, non-negative and no longer than
+    # the bulk's time from issue to completion
+    assert np.all(recs["issued_ns"] >= recs["cut_ns"])
+    assert np.all(recs["done_ns"] >= recs["issued_ns"])
+    assert np.all(recs["front_us"] >= 0) and np.all(recs["exec_us"] >= 0)
+    assert np.all(recs["exec_us"] * 1000 <= recs["done_ns"] - recs["cut_ns"] + 1000)
     assert np.all(res.latency_ns > 0)
 
 
