@@ -28,6 +28,16 @@ struct __attribute__((aligned(32))) OpInfo {
     int32_t s0ty;  // its type
 };
 
+// K-SET's view of one transaction, written by its preparation passes: the
+// first successor transaction of each of its first four operations (-1:
+// none) and their types (low 16 bits), so a wave releases them with one
+// load.  Bit 16 of s0ty[3]: the transaction has further operations or read
+// runs, which the wave walks in the operation records.
+struct __attribute__((aligned(32))) KsetRec {
+    int32_t s0[4];
+    int32_t s0ty[4];
+};
+
 // Device workspace of one bulk (carved from the caller's workspace).
 struct Ws {
     GtxState* st;
@@ -37,6 +47,7 @@ struct Ws {
     int32_t* cnt;        // [(1 + GTX_MAX_APPEND)][n]: op count then appends; scanned in place
     int32_t* maxrank;    // [n]
     int32_t* indeg;      // [n]
+    KsetRec* ksrec;      // [n] K-SET: first successors per transaction
     int32_t* op_txn;     // [mcap] serial position of each operation
     uint32_t* pk[2];     // [mcap] operation sort: item key
     uint32_t* pv[2];     // [mcap] operation sort: op index << 1 | write

@@ -206,10 +206,13 @@ __device__ __forceinline__ void kset_push(const BulkArgs& a, int32_t* fill, int3
 // release its successors into the next frontier.
 //
 // Each step of a wave is a chain of dependent memory round trips, which the
-// chunk keeps short: the in-degree decrements of the transaction's first
-// operations are all issued together, before the procedure's loads, so their
-// round trips overlap one another and the procedure's (the next wave starts
-// only after this wave's barrier, so the order inside the wave is free).
+// chunk keeps short: the first successors come from the transaction's
+// 32-byte record (one load, where the operation range and then the
+// operation records were two dependent ones), and their in-degree
+// decrements are all issued together, before the procedure's loads, so
+// their round trips overlap one another and the procedure's (the next wave
+// starts only after this wave's barrier, so the order inside the wave is
+// free).
 // (Loading the named successors' signatures ahead, toward the cache, measured
 // slower: each extra wave-wide load of 64 scattered lines costs issue time on
 // a path this short.)  Status counts accumulate in the caller's registers.
@@ -221,49 +224,43 @@ __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* 
     const int idx = (c - cpre[t]) * 64 + lane_id();
     const bool live = idx < cnt[t];
     if (!live) return;
-    constexpr int kPre = 4;  // op records read before the procedure runs
     const int32_t q = F[reg_off[t] + idx];
-    const int64_t o0 = op_begin(a, q);
-    const int64_t o1 = op_end(a, q);
-    OpInfo pre[kPre];
-#pragma unroll
-    for (int k = 0; k < kPre; ++k)
-        if (o0 + k < o1) pre[k] = a.ws.op_info[o0 + k];
+    // the first successors in one load (the operation records only when the
+    // transaction has more operations or read runs)
+    const KsetRec R = a.ws.ksrec[q];
     TxnIn x;
     load_txn(a, q, t, x);
     // the first operations' in-degree decrements, all in flight together
-    int32_t left[kPre];
+    int32_t left[4];
 #pragma unroll
-    for (int k = 0; k < kPre; ++k)
-        left[k] = (o0 + k < o1 && pre[k].slo < pre[k].shi) ? atomicSub(&a.ws.indeg[pre[k].s0], 1) : 0;
+    for (int k = 0; k < 4; ++k) left[k] = R.s0[k] >= 0 ? atomicSub(&a.ws.indeg[R.s0[k]], 1) : 0;
     // run this transaction
     const int32_t s = exec_txn(a, x);
     committed += s == GPUTX_COMMIT;
     aborted += s == GPUTX_ABORT;
     // successors that became ready join the next frontier
 #pragma unroll
-    for (int k = 0; k < kPre; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (left[k] == 1) {
-            const int slot = atomicAdd(&fill_next[pre[k].s0ty], 1);
-            F_next[reg_off[pre[k].s0ty] + slot] = pre[k].s0;
+            const int ty = R.s0ty[k] & 0xffff;
+            const int slot = atomicAdd(&fill_next[ty], 1);
+            F_next[reg_off[ty] + slot] = R.s0[k];
         }
     }
-    for (int64_t o = o0; o < o1; ++o) {
-        OpInfo inf;
-        if (o - o0 < kPre) {
-#pragma unroll
-            for (int k = 0; k < kPre; ++k)
-                if (o - o0 == k) inf = pre[k];
-        } else {
-            inf = a.ws.op_info[o];
-            if (inf.slo < inf.shi && atomicSub(&a.ws.indeg[inf.s0], 1) == 1) {
+    if (R.s0ty[3] >> 16) {
+        // operations past the fourth, and the rest of every read run
+        const int64_t o0 = op_begin(a, q);
+        const int64_t o1 = op_end(a, q);
+        for (int64_t o = o0; o < o1; ++o) {
+            const OpInfo inf = a.ws.op_info[o];
+            if (o - o0 >= 4 && inf.slo < inf.shi && atomicSub(&a.ws.indeg[inf.s0], 1) == 1) {
                 const int slot = atomicAdd(&fill_next[inf.s0ty], 1);
                 F_next[reg_off[inf.s0ty] + slot] = inf.s0;
             }
-        }
-        for (int32_t j = inf.slo + 1; j < inf.shi; ++j) {  // rest of a read run
-            const int32_t q2 = a.ws.srt_txn[j];
-            if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
+            for (int32_t j = inf.slo + 1; j < inf.shi; ++j) {  // rest of a read run
+                const int32_t q2 = a.ws.srt_txn[j];
+                if (atomicSub(&a.ws.indeg[q2], 1) == 1) kset_push(a, fill_next, F_next, reg_off, q2);
+            }
         }
     }
 }
@@ -277,11 +274,26 @@ __device__ __forceinline__ void kset_indeg(const BulkArgs& a, int64_t gt, int64_
     const GtxState* st = a.ws.st;
     for (int64_t p = gt; p < a.n; p += gs) {
         int in = 0;
+        bool more = false;  // operations past the fourth, or read runs to walk
         if (a.ws.tty[p] >= 0) {
+            const int64_t o0 = a.ws.cnt[p];
             const int64_t o1 = p + 1 < a.n ? (int64_t)a.ws.cnt[p + 1] : st->m;
-            for (int64_t o = a.ws.cnt[p]; o < o1; ++o) in += a.ws.op_info[o].in;
+            more = o1 - o0 > 4;
+            for (int64_t o = o0; o < o1; ++o) {
+                const OpInfo inf = a.ws.op_info[o];
+                in += inf.in;
+                more = more || inf.shi - inf.slo > 1;
+            }
         }
         a.ws.indeg[p] = in;
+        KsetRec r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r.s0[k] = -1;
+            r.s0ty[k] = 0;
+        }
+        r.s0ty[3] = more ? 1 << 16 : 0;  // bit 16 of the fourth type word: more
+        a.ws.ksrec[p] = r;
     }
 }
 
@@ -302,8 +314,17 @@ __device__ __forceinline__ void kset_succ(const BulkArgs& a, int64_t gt, int64_t
         const int32_t slo = inf.slo, shi = inf.shi;
         if (slo < shi) {
             const int32_t q = a.ws.srt_txn[slo];
+            const int32_t qt = a.ws.tty[q];
             inf.s0 = q;
-            inf.s0ty = a.ws.tty[q];
+            inf.s0ty = qt;
+            // the transaction's record holds its first four operations' ones
+            const int32_t p = a.ws.op_txn[o];
+            const int64_t k = o - (int64_t)a.ws.cnt[p];
+            if (k < 4) {
+                a.ws.ksrec[p].s0[k] = q;
+                if (k < 3) a.ws.ksrec[p].s0ty[k] = qt;
+                else a.ws.ksrec[p].s0ty[3] = (a.ws.ksrec[p].s0ty[3] & (1 << 16)) | qt;
+            }
         }
     }
 }

@@ -472,6 +472,7 @@ static void plan_ws(const gputx_ctx* h, int64_t n, int max_ops, void* base, Ws* 
     w.cnt = L.take<int32_t>(n * (1 + GTX_MAX_APPEND));
     w.maxrank = L.take<int32_t>(n);
     w.indeg = L.take<int32_t>(n);
+    w.ksrec = L.take<KsetRec>(n);
     w.op_txn = L.take<int32_t>(mcap);
     w.pk[0] = L.take<uint32_t>(mcap); w.pk[1] = L.take<uint32_t>(mcap);
     w.pv[0] = L.take<uint32_t>(mcap); w.pv[1] = L.take<uint32_t>(mcap);
