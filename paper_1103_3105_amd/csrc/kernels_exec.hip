@@ -1294,26 +1294,72 @@ __device__ __forceinline__ int32_t serial_one(const DevType& T, const PartChunk&
     return s;
 }
 
+// The serial waves of a workgroup: this one's index and their number, and
+// its scratch for grouping (group_ordinal).
+struct SerialWave {
+    int ws, nsw;
+    GTX_LDS uint8_t* tag;  // [512 + tag bytes]: 64 group masks, then a tag byte per slot
+};
+
 // The order-entry procedures name distinct cells within one transaction
 // (payment: a warehouse, a district and a customer row; a new-order: its
 // items, checked for repeats here).  Their transactions then run one after
 // another with the whole wave on each, lane r updating the cell of ordinal r
 // -- the partition's order is kept, only one transaction's cells are worked
-// on side by side.  Both return the transaction's status, the same on every
-// lane, and write what serial_one writes.
-template <int Q>  // GPUTX_NEW_ORDER or GPUTX_NEW_ORDER_RB
-__device__ __forceinline__ int32_t wave_new_order(const DevType& T, const PartChunk& c, int k, uint32_t* seen) {
+// on side by side.  A transaction's signature is first read into registers,
+// one parameter and one cell ordinal per lane (wave_fetch).  LDS operations
+// of one wave complete in issue order, so a transaction's read of its cells
+// sees every earlier transaction's writes.  The forms return the
+// transaction's status, the same on every lane, and write what serial_one
+// writes.
+struct WaveTxn {
+    int64_t a;    // new-order: lane's item; payment: the amount
+    int32_t n;    // new-order: item count (1..15 in a valid one)
+    int32_t b;    // new-order: lane's quantity (1..1000 in a valid one)
+    uint32_t at;  // LDS address of the lane's cell ordinal
+};
+__device__ __forceinline__ void wave_fetch(const PartChunk& c, int k, int32_t pc, WaveTxn& x) {
     const int lane = lane_id();
-    const int64_t nk = c.prm[k * c.ps + 3];
+    switch (pc & 0xffff) {
+    case GPUTX_NEW_ORDER:
+    case GPUTX_NEW_ORDER_RB: {  // 34 parameter rows and 15 ordinals exist
+        const int j = min(lane, 14);
+        x.n = (int32_t)c.prm[k * c.ps + 3];
+        x.a = c.prm[k * c.ps + 4 + j];
+        x.b = (int32_t)c.prm[k * c.ps + 19 + j];
+        x.at = c.cs[k * c.css + j];
+        break;
+    }
+    case GPUTX_PAYMENT:
+        x.a = c.prm[k * c.ps + 3];
+        x.at = c.cs[k * c.css + min(lane, 2)];
+        break;
+    case GPUTX_ORDER_STATUS:
+        x.at = c.cs[k * c.css];
+        break;
+    default:
+        break;
+    }
+}
+
+template <int Q>  // GPUTX_NEW_ORDER or GPUTX_NEW_ORDER_RB
+__device__ __forceinline__ int32_t wave_new_order(const DevType& T, const PartChunk& c, int k, const WaveTxn& x,
+                                                  uint32_t* seen) {
+    const int lane = lane_id();
+    const int64_t nk = x.n;
     const bool live = lane < nk;
-    const int64_t item = live ? c.prm[k * c.ps + 4 + lane] : -1;
-    const int64_t q = live ? c.prm[k * c.ps + 19 + lane] : 0;
+    const int64_t item = live ? x.a : -1;
+    const int64_t q = live ? x.b : 0;
     // a rollback new-order stops at its first unused item
     const bool unused = Q == GPUTX_NEW_ORDER_RB && live && item == T.dims[3];
     const uint64_t ub = __ballot(unused);
     const int stop = ub ? __ffsll((unsigned long long)ub) - 1 : 64;
     const bool mine = live && lane < stop;
-    const uint32_t at = mine ? c.cs[k * c.css + lane] : 0xffffffffu;
+    const uint32_t at = mine ? x.at : 0xffffffffu;
+    GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)at;
+    // the undo log entry for the item; read before the repeat check (a
+    // transaction with a repeat reruns on one lane below)
+    const int64_t old = mine ? *cell : 0;
     bool dup = false;
 #pragma unroll
     for (int r = 1; r < 15; ++r) {
@@ -1326,11 +1372,8 @@ __device__ __forceinline__ int32_t wave_new_order(const DevType& T, const PartCh
         return __shfl(s, 0);
     }
     if (mine) *seen &= at;
-    GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)at;
-    int64_t old = 0;
     int32_t nv = 0;
     if (mine) {
-        old = *cell;  // the transaction's undo log entry for this item
         int64_t s = (int64_t)(int32_t)old - q;
         if (s < 10) s += 91;
         nv = to_i32(s);
@@ -1342,20 +1385,82 @@ __device__ __forceinline__ int32_t wave_new_order(const DevType& T, const PartCh
         if (lane == 0) c.st[k] = GPUTX_ABORT;
         return GPUTX_ABORT;
     }
-    const int32_t before = __shfl(nv, (lane + 63) & 63);  // lane r - 1's new value
-    if (lane < proc_results(Q)) c.res[k * c.rs + lane] = lane == 0 ? nk : (lane - 1 < nk ? (int64_t)before : 0);
+    // result 0: the item count; result 1 + r: item r's new quantity
+    if (lane < 15) c.res[k * c.rs + 1 + lane] = live ? (int64_t)nv : 0;
+    else if (lane == 15) c.res[k * c.rs] = nk;
     return GPUTX_COMMIT;
 }
 
-__device__ __forceinline__ int32_t wave_payment(const DevType& T, const PartChunk& c, int k, uint32_t* seen) {
+// Up to four consecutive new-orders of one type at once, sixteen lanes each
+// (lane 16 g + j: item j of the g-th, transaction kg), when no two of their
+// items are the same cell and none rolls back: each lane stores its lane
+// number in its cell's tag byte and reads it back, and one that reads another
+// lane's number shares its cell with that lane (the same transaction or
+// another of the group).  Disjoint new-orders commute, so running them
+// side by side leaves what running them in turn leaves.  Returns false,
+// having changed nothing, when the group must run one at a time.
+template <int Q>  // GPUTX_NEW_ORDER or GPUTX_NEW_ORDER_RB
+__device__ __forceinline__ bool wave_new_order_group(const DevType& T, const PartChunk& c, const CellTab& tab,
+                                                     const SerialWave& sw, int k0, int k1, int k2, int k3, int G,
+                                                     uint32_t* seen) {
+    const int lane = lane_id();
+    const int g = lane >> 4, j = lane & 15;
+    const int k = g == 0 ? k0 : g == 1 ? k1 : g == 2 ? k2 : k3;
+    const bool grp = g < G;
+    int32_t nk = 0, q = 0;
+    int64_t item = -1;
+    uint32_t at = 0;
+    if (grp) {  // 34 parameter rows and 15 ordinals exist
+        const int jj = min(j, 14);
+        nk = (int32_t)c.prm[k * c.ps + 3];
+        item = c.prm[k * c.ps + 4 + jj];
+        q = (int32_t)c.prm[k * c.ps + 19 + jj];
+        at = c.cs[k * c.css + jj];
+    }
+    const bool live = grp && j < nk;
+    const bool unused = Q == GPUTX_NEW_ORDER_RB && live && item == T.dims[3];
+    volatile GTX_LDS uint8_t* tag = sw.tag + 512;
+    const uint32_t h = (at - lds_addr(tab.slot)) >> 4;
+    if (live) tag[h] = (uint8_t)lane;
+    bool clash = false;
+    int64_t old = 0;
+    if (live) {  // LDS operations of a wave complete in order
+        clash = tag[h] != (uint8_t)lane;
+        old = *(GTX_LDS const int64_t*)(uintptr_t)at;
+    }
+    if (__any(clash || unused)) return false;
+    int32_t nv = 0;
+    if (live) {
+        *seen &= at;
+        int64_t s = (int64_t)(int32_t)old - q;
+        if (s < 10) s += 91;
+        nv = to_i32(s);
+        *(GTX_LDS int64_t*)(uintptr_t)at = (int64_t)nv;
+    }
+    // result 0: the item count; result 1 + r: item r's new quantity
+    if (grp) {
+        if (j < 15) c.res[k * c.rs + 1 + j] = live ? (int64_t)nv : 0;
+        else c.res[k * c.rs] = nk;
+    }
+    return true;
+}
+
+__device__ __forceinline__ int32_t wave_payment(const PartChunk& c, int k, const WaveTxn& x, uint32_t* seen) {
     const int lane = lane_id();
     if (lane < 3) {
-        const uint32_t at = c.cs[k * c.css + lane];
-        *seen &= at;
-        GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)at;
-        const int64_t nv = wrap_add(*cell, c.prm[k * c.ps + 3]);
+        *seen &= x.at;
+        GTX_LDS int64_t* cell = (GTX_LDS int64_t*)(uintptr_t)x.at;
+        const int64_t nv = wrap_add(*cell, x.a);
         *cell = nv;
         c.res[k * c.rs + lane] = nv;
+    }
+    return GPUTX_COMMIT;
+}
+
+__device__ __forceinline__ int32_t wave_order_status(const PartChunk& c, int k, const WaveTxn& x, uint32_t* seen) {
+    if (lane_id() == 0) {
+        *seen &= x.at;
+        c.res[k * c.rs] = *(GTX_LDS const int64_t*)(uintptr_t)x.at;
     }
     return GPUTX_COMMIT;
 }
@@ -1406,12 +1511,6 @@ __device__ __forceinline__ int64_t wave_shr1(int64_t v) {  // lane i gets lane i
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// The serial waves of a workgroup: this one's index and their number, and
-// its scratch for grouping (group_ordinal).
-struct SerialWave {
-    int ws, nsw;
-    GTX_LDS uint8_t* tag;  // [512 + tag bytes]: 64 group masks, then a tag byte per slot
-};
 
 // Sort a window's lanes (transactions k0 .. k0+n-1, lane j holding k0 + j,
 // naming the cell at LDS address id) into groups naming the same cell,
@@ -1570,59 +1669,100 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
       }
     }
     if constexpr (P == 0 || P == GPUTX_NEW_ORDER || P == GPUTX_NEW_ORDER_RB) {
-        // the whole wave on each transaction (order-entry procedures), one
-        // serial wave per cell class; other procedures on lane 0
+        // the whole wave on each transaction (order-entry procedures; up to
+        // four new-orders at once), one serial wave per cell class; other
+        // procedures on lane 0.  The wave lists its own transactions of each
+        // 64 with one ballot.
         if constexpr (P != 0)
             if (T.cell_class % sw.nsw != sw.ws) return false;
+        const int lane = lane_id();
         uint32_t seen = ~0u;
         int n_commit = 0, n_abort = 0;
-        for (int k = 0; k < cnt; ++k) {
-            int32_t pc = P;
-            const DevType* Tk = &T;
-            if constexpr (P == 0) {
-                pc = c.proc[k];
-                if ((pc >> 16) % sw.nsw != sw.ws) continue;
-                Tk = &a.types[c.t[k]];
+        for (int b0 = 0; b0 < cnt; b0 += 64) {
+            const int r = b0 + lane;
+            int32_t pw = 0, tw = 0;
+            if (r < cnt) {
+                pw = P != 0 ? (P | (T.cell_class << 16)) : c.proc[r];
+                if constexpr (P == 0) tw = c.t[r];
             }
-            int32_t s = GPUTX_INVALID;
-            switch (pc & 0xffff) {
-            case GPUTX_NEW_ORDER: s = wave_new_order<GPUTX_NEW_ORDER>(*Tk, c, k, &seen); break;
-            case GPUTX_NEW_ORDER_RB: s = wave_new_order<GPUTX_NEW_ORDER_RB>(*Tk, c, k, &seen); break;
-            case GPUTX_PAYMENT: s = wave_payment(*Tk, c, k, &seen); break;
-            default: {
-                int32_t s0 = 0;
-                if (lane_id() == 0) {
-                    switch (pc & 0xffff) {
-#define GTX_ONE(Q)                                                    \
-    case Q:                                                           \
-        s0 = serial_one<Q>(*Tk, c, k, &seen);                         \
-        break;
-                        GTX_ONE(GPUTX_DEBIT_CREDIT)
-                        GTX_ONE(GPUTX_ORDER_STATUS)
-                        GTX_ONE(GPUTX_GET_SUB)
-                        GTX_ONE(GPUTX_GET_CF)
-                        GTX_ONE(GPUTX_UPD_SUB_FIELD)
-                        GTX_ONE(GPUTX_UPD_LOC)
-                        GTX_ONE(GPUTX_INS_CF)
-                        GTX_ONE(GPUTX_DEL_CF)
-#undef GTX_ONE
-                    default:
-                        s0 = GPUTX_INVALID;
-                        seen = 0;  // a staged transaction of no known procedure
+            uint64_t m = __ballot(r < cnt && (pw >> 16) % sw.nsw == sw.ws);
+            while (m) {
+                const int j = __ffsll((unsigned long long)m) - 1;
+                const int k = b0 + j;
+                const int32_t pc = __builtin_amdgcn_readlane(pw, j);
+                const int32_t tk = P != 0 ? 0 : __builtin_amdgcn_readlane(tw, j);
+                const DevType& Tk = P != 0 ? T : a.types[tk];
+                const int pq = pc & 0xffff;
+                if (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB) {
+                    // this one and up to three more of its type that follow it
+                    int k1 = k, k2 = k, k3 = k, G = 1;
+                    uint64_t mm = m & (m - 1);
+#pragma unroll
+                    for (int e = 1; e < 4; ++e) {
+                        if (!mm) break;
+                        const int jn = __ffsll((unsigned long long)mm) - 1;
+                        if (__builtin_amdgcn_readlane(pw, jn) != pc ||
+                            (P == 0 && __builtin_amdgcn_readlane(tw, jn) != tk))
+                            break;
+                        if (e == 1) k1 = b0 + jn;
+                        if (e == 2) k2 = b0 + jn;
+                        if (e == 3) k3 = b0 + jn;
+                        G = e + 1;
+                        mm &= mm - 1;
+                    }
+                    const bool done =
+                        pq == GPUTX_NEW_ORDER
+                            ? wave_new_order_group<GPUTX_NEW_ORDER>(Tk, c, tab, sw, k, k1, k2, k3, G, &seen)
+                            : wave_new_order_group<GPUTX_NEW_ORDER_RB>(Tk, c, tab, sw, k, k1, k2, k3, G, &seen);
+                    if (done) {
+                        n_commit += G;
+                        m = mm;
+                        continue;
                     }
                 }
-                s = __shfl(s0, 0);
+                m &= m - 1;
+                WaveTxn x;
+                wave_fetch(c, k, pc, x);
+                int32_t s = GPUTX_INVALID;
+                switch (pq) {
+                case GPUTX_NEW_ORDER: s = wave_new_order<GPUTX_NEW_ORDER>(Tk, c, k, x, &seen); break;
+                case GPUTX_NEW_ORDER_RB: s = wave_new_order<GPUTX_NEW_ORDER_RB>(Tk, c, k, x, &seen); break;
+                case GPUTX_PAYMENT: s = wave_payment(c, k, x, &seen); break;
+                case GPUTX_ORDER_STATUS: s = wave_order_status(c, k, x, &seen); break;
+                default: {
+                    int32_t s0 = 0;
+                    if (lane == 0) {
+                        switch (pq) {
+#define GTX_ONE(Q)                                                    \
+    case Q:                                                           \
+        s0 = serial_one<Q>(Tk, c, k, &seen);                          \
+        break;
+                            GTX_ONE(GPUTX_DEBIT_CREDIT)
+                            GTX_ONE(GPUTX_GET_SUB)
+                            GTX_ONE(GPUTX_GET_CF)
+                            GTX_ONE(GPUTX_UPD_SUB_FIELD)
+                            GTX_ONE(GPUTX_UPD_LOC)
+                            GTX_ONE(GPUTX_INS_CF)
+                            GTX_ONE(GPUTX_DEL_CF)
+#undef GTX_ONE
+                        default:
+                            s0 = GPUTX_INVALID;
+                            seen = 0;  // a staged transaction of no known procedure
+                        }
+                    }
+                    s = __shfl(s0, 0);
+                }
+                }
+                n_commit += s == GPUTX_COMMIT;
+                n_abort += s == GPUTX_ABORT;
             }
-            }
-            n_commit += s == GPUTX_COMMIT;
-            n_abort += s == GPUTX_ABORT;
         }
-        if (lane_id() == 0) {
+        if (lane == 0) {
             committed += n_commit;
             aborted += n_abort;
         }
         if (__any(!(seen & 8u))) {
-            if (lane_id() == 0) fail(a.ws.st, GPUTX_E_INTERNAL);
+            if (lane == 0) fail(a.ws.st, GPUTX_E_INTERNAL);
         }
         return false;
     }
@@ -1791,10 +1931,16 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
 __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                     const StagedTxn& x, int64_t c0, int64_t end, int lane) {
     const bool live = c0 + lane < end;
-    const int32_t t0 = __builtin_amdgcn_readfirstlane(x.t);  // lane 0 is live if any lane is
     uint32_t won = 0, pending = 0;
-    if (__ballot(live && x.t != t0) == 0) {
-        if (live) {
+    // one pass per type present, its lanes specialised on its procedure with
+    // the type's descriptor read once for the wave (the passes run one after
+    // another, as divergent lanes would)
+    uint64_t left = __ballot(live);
+    while (left) {
+        const int32_t t0 = __builtin_amdgcn_readlane(x.t, __ffsll((unsigned long long)left) - 1);
+        const bool mine = live && x.t == t0;
+        left &= ~__ballot(mine);
+        if (mine) {
             switch (a.types[t0].proc) {
 #define GTX_CLAIM_CASE(P)                                     \
     case P:                                                   \
@@ -1816,8 +1962,6 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
                 won = part_claim<0>(a, c, tab, x, lane, 0, pending);
             }
         }
-    } else if (live) {
-        won = part_claim<0>(a, c, tab, x, lane, 0, pending);
     }
     // list the won slots: one counter update for the whole wave
     const int nw = __popc(won);
@@ -2034,29 +2178,50 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        // A staging lane reads its transaction's record for chunk k + 2 (the
-        // records lie in partition order) while it claims the cells of chunk
-        // k + 1, so a step's global reads do not wait on one another.  xn:
-        // the next chunk to claim.
-        StagedTxn xn;
-        xn.t = 0;
-        if (!serial) {
-            const int64_t j0 = lo + sl, j1 = j0 + cw;
-            StagedTxn x0;
-            x0.t = 0;
-            if (j0 < end) stage_load(a, (int32_t)j0, x0);
-            if (j1 < end) stage_load(a, (int32_t)j1, xn);
-            part_stage_read(a, buf(0), tab, x0, lo, end, sl);
-        }
-        __syncthreads();
-        for (int64_t k = 0; k < nch; ++k) {
-            const int64_t c0 = lo + cw * k;
-            StagedTxn xa = xn;
-            if (serial) {
-                const int cnt = (int)min<int64_t>(cw, end - c0);
+        // After a chunk the staging wave may have asked for a flush
+        // (flag[k & 1], written before the barrier that ends the step):
+        // every wave writes back and empties the table, and the staging
+        // wave then stages chunk k + 1.  The serial and the staging waves
+        // run loops of their own (so that neither holds the other's
+        // registers), which meet the same barriers in the same order.
+        auto flush_step = [&](int64_t k, auto&& restage) {
+            if (flag[k & 1]) {  // same value in every wave
+                part_flush(tab, tid, nthr);
+                __syncthreads();
+                if (tid == 0) *tab.nlist = 0;
+                __syncthreads();
+                restage();
+                __syncthreads();
+            }
+        };
+        if (serial) {
+            __syncthreads();  // chunk 0 staged
+            for (int64_t k = 0; k < nch; ++k) {
+                const int cnt = (int)min<int64_t>(cw, end - lo - cw * k);
                 if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted))
                     part_writeout_own(a, buf(k), cnt, lane, sw);
-            } else {
+                __syncthreads();
+                flush_step(k, [] {});
+            }
+        } else {
+            // A staging lane reads its transaction's record for chunk k + 2
+            // (the records lie in partition order) while it claims the cells
+            // of chunk k + 1, so a step's global reads do not wait on one
+            // another.  xn: the next chunk to claim.
+            StagedTxn xn;
+            xn.t = 0;
+            {
+                const int64_t j0 = lo + sl, j1 = j0 + cw;
+                StagedTxn x0;
+                x0.t = 0;
+                if (j0 < end) stage_load(a, (int32_t)j0, x0);
+                if (j1 < end) stage_load(a, (int32_t)j1, xn);
+                part_stage_read(a, buf(0), tab, x0, lo, end, sl);
+            }
+            __syncthreads();  // chunk 0 staged
+            for (int64_t k = 0; k < nch; ++k) {
+                const int64_t c0 = lo + cw * k;
+                StagedTxn xa = xn;
                 bool flush = false;
                 if (k + 1 < nch) {
                     flush = *tab.nlist + cw * a.cells_max > part_pipe_fill(cap);
@@ -2065,17 +2230,10 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
                     if (!flush) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 }
                 if (sl == 0) flag[k & 1] = flush;
+                __syncthreads();
+                flush_step(k, [&] { part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl); });
+                xn = xa;
             }
-            __syncthreads();
-            if (flag[k & 1]) {  // same value in every wave
-                part_flush(tab, tid, nthr);
-                __syncthreads();
-                if (tid == 0) *tab.nlist = 0;
-                __syncthreads();
-                if (!serial) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
-                __syncthreads();
-            }
-            xn = xa;
         }
         // every staged cell; the table is empty after
         part_flush(tab, tid, nthr);

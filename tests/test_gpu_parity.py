@@ -443,6 +443,30 @@ def test_order_entry_repeated_items(strategy, rollback):
     assert_parity(s, g, o, bulk)
 
 
+@pytest.mark.parametrize("pipeline", [0, 1])
+@pytest.mark.parametrize("rollback", [0.0, 0.02])
+def test_part_new_order_groups(pipeline, rollback):
+    """New-orders over a large item space rarely share a stock row, so PART's
+    serial wave runs them four at a time (sixteen lanes each); a group in
+    which two items meet, or a new-order rolls back, runs one at a time.  A
+    few planted repeats and shared items exercise both within the same
+    chunks."""
+    tabs, types, bulk = util.small_order(29, 30_000, n_wh=3, d_per_w=10, c_per_d=30, items_per_w=100_000,
+                                         rollback_frac=rollback)
+    no = np.flatnonzero(bulk.type == 1)
+    rng = np.random.default_rng(30)
+    prm = bulk.params.copy()
+    rep = no[rng.random(no.size) < 0.02]
+    prm[5, rep] = prm[4, rep]                  # an item named twice in one new-order
+    nxt = no[1:][rng.random(no.size - 1) < 0.02]
+    prm[4, nxt] = prm[4, nxt - 1]              # an item of the transaction before (if it is a new-order)
+    bulk = wl.Bulk(bulk.type, prm, bulk.ts)
+    _say("new-order groups", pipeline, rollback)
+    s, g, o = run_both(tabs, types, bulk, 16, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2
+    assert_parity(s, g, o, bulk)
+
+
 @pytest.mark.parametrize("lanes", [0, 1, 3, 16, 64])
 @pytest.mark.parametrize("workload", ["bank", "order", "sub"])
 def test_tpl_window_shapes(workload, lanes):
