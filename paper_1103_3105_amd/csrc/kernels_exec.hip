@@ -1519,12 +1519,11 @@ __device__ __forceinline__ int64_t wave_shr1(int64_t v) {  // lane i gets lane i
 // the whole group) names the group; each lane ORs its bit into that lane's
 // group mask, then reads the mask, and the groups are laid out in the order
 // of those lanes.  Returns the lane's sorted slot, and whether it starts or
-// ends its group.  Lanes past n are groups of their own.  Needs all 64
-// lanes of the wave.
-__device__ __forceinline__ int group_ordinal(const CellTab& tab, GTX_LDS uint8_t* mine, uint32_t id, int n,
+// ends its group.  Lanes that are not live are groups of their own.  Needs
+// all 64 lanes of the wave.
+__device__ __forceinline__ int group_ordinal(const CellTab& tab, GTX_LDS uint8_t* mine, uint32_t id, bool live,
                                              bool& head, bool& last) {
     const int j = lane_id();
-    const bool live = j < n;
     GTX_LDS uint64_t* gmask = (GTX_LDS uint64_t*)mine;
     // volatile: the read must see whichever lane's store landed, not this lane's
     volatile GTX_LDS uint8_t* tag = mine + 512;
@@ -1596,7 +1595,7 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
         if constexpr (kW) {
             // take the transaction at this lane's sorted slot instead
             bool hd, ls;
-            const int to = group_ordinal(tab, sw.tag, id, n, hd, ls);
+            const int to = group_ordinal(tab, sw.tag, id, live, hd, ls);
             const uint32_t fl = push32(to, (hd ? 1u : 0u) | (ls ? 2u : 0u));
             id = push32(to, id);
 #pragma unroll
@@ -1629,6 +1628,105 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
     }
 }
 
+// Cellwise procedures of at most three cells, which a mixed window takes.
+__device__ __forceinline__ bool mixed_window_proc(int pc) {
+    return pc == GPUTX_DEBIT_CREDIT || pc == GPUTX_PAYMENT || pc == GPUTX_ORDER_STATUS || pc == GPUTX_GET_CF ||
+           pc == GPUTX_UPD_SUB_FIELD || pc == GPUTX_UPD_LOC;
+}
+__device__ __forceinline__ void mixed_cell_map(int pc, int r, const int64_t* p, int64_t old, bool& fa, int64_t& fb,
+                                               int64_t& nv, bool& w, int& res_at, int64_t& res, bool apply) {
+    switch (pc) {
+#define GTX_MIXED(P)                                          \
+    case P:                                                   \
+        if (apply)                                            \
+            cell_apply<P>(r, old, p, nv, w, res_at, res);     \
+        else                                                  \
+            cell_affine<P>(r, p, fa, fb);                     \
+        break;
+        GTX_MIXED(GPUTX_DEBIT_CREDIT)
+        GTX_MIXED(GPUTX_PAYMENT)
+        GTX_MIXED(GPUTX_ORDER_STATUS)
+        GTX_MIXED(GPUTX_GET_CF)
+        GTX_MIXED(GPUTX_UPD_SUB_FIELD)
+        GTX_MIXED(GPUTX_UPD_LOC)
+#undef GTX_MIXED
+    default:
+        break;
+    }
+}
+
+// A run of G (2..21) transactions of one serial wave's list, all of
+// cellwise procedures of at most three cells (mixed_window_proc), as one
+// window: lane 3 t + r takes cell ordinal r of the run's t-th transaction
+// (b0 + the t-th set bit of run).  A transaction names each of its cells
+// once, so lanes in transaction order give each cell's accesses in
+// timestamp order, and grouping the lanes by cell and scanning the groups'
+// maps gives every access the value before it, as in the window form of one
+// procedure (lanes_window) -- whatever the procedures and ordinals that meet
+// on a cell.  The last access of each group stores the cell, also when it
+// only reads it.  Results go to the chunk's rows; every such procedure
+// commits.
+__device__ __forceinline__ void mixed_window(const PartChunk& c, const CellTab& tab, const SerialWave& sw, int b0,
+                                             int32_t pw, uint64_t run, int G, uint32_t* seen) {
+    const int lane = lane_id();
+    const int t = lane / 3, r = lane - 3 * t;
+    int pos = 0;
+    uint64_t mm = run;
+    for (int q = 0; q < G; ++q) {
+        const int j = __ffsll((unsigned long long)mm) - 1;
+        mm &= mm - 1;
+        if (t == q) pos = j;
+    }
+    const int pc = __shfl(pw, pos) & 0xffff;
+    const int k = b0 + pos;
+    const bool act = t < G && r < proc_cells(pc);
+    uint32_t id = 0;
+    int64_t p[4] = {0, 0, 0, 0};
+    int64_t init = 0;
+    if (act) {
+        id = c.cs[k * c.css + r];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < c.ps) p[q] = c.prm[k * c.ps + q];
+        init = *(GTX_LDS const int64_t*)(uintptr_t)id;
+        *seen &= id;
+    }
+    bool hd, ls;
+    const int to = group_ordinal(tab, sw.tag, id, act, hd, ls);
+    // each lane takes the access at its sorted slot
+    const uint32_t fl = push32(to, (act ? 1u : 0u) | (hd ? 2u : 0u) | (ls ? 4u : 0u) | ((uint32_t)r << 3) |
+                                       ((uint32_t)pc << 8));
+    id = push32(to, id);
+    init = push64(to, init);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = push64(to, p[q]);
+    const int kk = (int)push32(to, (uint32_t)k);
+    const bool live = fl & 1u, head = fl & 2u, last = fl & 4u;
+    const int rr = (fl >> 3) & 3, pcx = (int)(fl >> 8);
+    bool fa = false;
+    int64_t fb = 0, nv = 0, res = 0;
+    bool w = false;
+    int at = -1;
+    if (live) mixed_cell_map(pcx, rr, p, 0, fa, fb, nv, w, at, res, false);
+    int A = fa;
+    int64_t B = fb;
+    if (head) {
+        B = A ? wrap_add(init, B) : B;
+        A = 0;
+    }
+    wave_affine_scan(A, B);
+    const int64_t before = wave_shr1(B);
+    const int64_t old = head ? init : before;
+    if (live) {
+        mixed_cell_map(pcx, rr, p, old, fa, fb, nv, w, at, res, true);
+        if (at >= 0 && at < c.rs) c.res[kk * c.rs + at] = res;
+        // the group's last access leaves the cell's final value, whether or
+        // not its own procedure writes (a read after writes must not drop
+        // them)
+        if (last) *(GTX_LDS int64_t*)(uintptr_t)id = w ? nv : old;
+    }
+}
+
 // The chunk's cnt transactions run in order against the staged cells: as
 // windows (cellwise procedures, all serial waves; outcomes go straight to
 // the status and results arrays, and part_serial returns true), or on lane 0
@@ -1642,7 +1740,7 @@ __device__ __forceinline__ void lanes_window(const BulkArgs& a, const PartChunk&
 // keeps the LDS latency off the dependence chain.  Every procedure also runs
 // through the generic path, which checks that each ordinal it names was
 // staged, whenever a chunk mixes types.
-template <int P>
+template <int P, int MC>
 __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T, const PartChunk& c,
                                             const CellTab& tab, const SerialWave& sw, int cnt,
                                             int64_t& committed, int64_t& aborted) {
@@ -1693,7 +1791,26 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                 const int32_t tk = P != 0 ? 0 : __builtin_amdgcn_readlane(tw, j);
                 const DevType& Tk = P != 0 ? T : a.types[tk];
                 const int pq = pc & 0xffff;
-                if (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB) {
+                if (a.part_scan && mixed_window_proc(pq)) {
+                    // this one and the cellwise ones right after it, up to 21
+                    uint64_t run = 0, mm = m;
+                    int G = 0;
+                    while (mm && G < 21) {
+                        const int jn = __ffsll((unsigned long long)mm) - 1;
+                        if (!mixed_window_proc(__builtin_amdgcn_readlane(pw, jn) & 0xffff)) break;
+                        run |= 1ull << jn;
+                        mm &= mm - 1;
+                        ++G;
+                    }
+                    if (G >= 2) {
+                        mixed_window(c, tab, sw, b0, pw, run, G, &seen);
+                        n_commit += G;
+                        m = mm;
+                        continue;
+                    }
+                }
+                constexpr bool kNewOrder = MC >= proc_cells(GPUTX_NEW_ORDER);
+                if (kNewOrder && (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB)) {
                     // this one and up to three more of its type that follow it
                     int k1 = k, k2 = k, k3 = k, G = 1;
                     uint64_t mm = m & (m - 1);
@@ -1724,9 +1841,13 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                 WaveTxn x;
                 wave_fetch(c, k, pc, x);
                 int32_t s = GPUTX_INVALID;
-                switch (pq) {
-                case GPUTX_NEW_ORDER: s = wave_new_order<GPUTX_NEW_ORDER>(Tk, c, k, x, &seen); break;
-                case GPUTX_NEW_ORDER_RB: s = wave_new_order<GPUTX_NEW_ORDER_RB>(Tk, c, k, x, &seen); break;
+                switch (kNewOrder ? pq : (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB) ? -1 : pq) {
+                case GPUTX_NEW_ORDER:
+                    if constexpr (kNewOrder) s = wave_new_order<GPUTX_NEW_ORDER>(Tk, c, k, x, &seen);
+                    break;
+                case GPUTX_NEW_ORDER_RB:
+                    if constexpr (kNewOrder) s = wave_new_order<GPUTX_NEW_ORDER_RB>(Tk, c, k, x, &seen);
+                    break;
                 case GPUTX_PAYMENT: s = wave_payment(c, k, x, &seen); break;
                 case GPUTX_ORDER_STATUS: s = wave_order_status(c, k, x, &seen); break;
                 default: {
@@ -1735,7 +1856,10 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                         switch (pq) {
 #define GTX_ONE(Q)                                                    \
     case Q:                                                           \
-        s0 = serial_one<Q>(Tk, c, k, &seen);                          \
+        if constexpr (proc_cells(Q) <= MC)                            \
+            s0 = serial_one<Q>(Tk, c, k, &seen);                      \
+        else                                                          \
+            seen = 0;                                                 \
         break;
                             GTX_ONE(GPUTX_DEBIT_CREDIT)
                             GTX_ONE(GPUTX_GET_SUB)
@@ -1822,6 +1946,13 @@ size_t part_wave_lds(const BulkArgs& a) {
 // Serial waves of the pipelined form: cellwise procedures share their cell
 // ordinals among them (debit-credit and payment have three).
 constexpr int kPipeSerial = 3;
+// The most cells per transaction the pipelined form of width cw is built
+// for: the wide forms' cell tables could not hold more than this many per
+// transaction below their fill limit anyway, so the procedures with more
+// (new-order, and the full subscriber read at width 256) are left out of
+// them, which keeps their registers for the procedures that do run there.
+constexpr int kAllCells = proc_cells(0);  // the most any procedure names
+__host__ __device__ constexpr int part_pipe_cells(int cw) { return cw >= 256 ? 8 : cw >= 128 ? 14 : kAllCells; }
 // The pipelined form's table holds at most half of its slots: it
 // is flushed before a chunk could take it past that.
 __host__ __device__ inline int part_pipe_fill(int cap) { return cap / 2; }
@@ -1832,11 +1963,13 @@ size_t part_pipe_lds(const BulkArgs& a, int cw) {
 // Dynamic LDS a PART workgroup may use: the device's opt-in per-workgroup
 // limit (160 KB on gfx950), or the default 64 KB if raising it fails.
 static size_t g_part_lds_limit = 64 * 1024;
-// The pipelined form of width cw runs when its LDS fits and one chunk's cells
-// fit in half the table (so that several chunks fit below the fill limit).
+// The pipelined form of width cw runs when its LDS fits, one chunk's cells
+// fit in half the table (so that several chunks fit below the fill limit),
+// and no registered procedure of the bulk names more cells than the form's
+// instance is built for.
 static bool part_pipe_fits(const BulkArgs& a, int cw) {
     return a.part_pipeline && part_pipe_lds(a, cw) <= g_part_lds_limit &&
-           (int64_t(1) << a.pipe_bits) >= int64_t(2) * cw * a.cells_max;
+           (int64_t(1) << a.pipe_bits) >= int64_t(2) * cw * a.cells_max && a.cells_max <= part_pipe_cells(cw);
 }
 
 __device__ __forceinline__ PartChunk part_chunk_at(unsigned char* base, const BulkArgs& a, int cw) {
@@ -1925,11 +2058,28 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
     return claim.won;
 }
 
+// A transaction of a procedure this kernel instance was built without (it
+// names more cells than the instance's chunk width allows; the host never
+// sends one): its row gets the sink slot and no procedure, which the serial
+// side reports, and the bulk fails.
+__device__ __forceinline__ void part_claim_none(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
+                                                const StagedTxn& x, int lane) {
+    for (int r = 0; r < c.css; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
+    c.idx[lane] = x.i;
+    c.t[lane] = x.t;
+    c.proc[lane] = 0xffff;
+    c.st[lane] = GPUTX_INVALID;
+    fail(a.ws.st, GPUTX_E_INTERNAL);
+}
+
 // The live lanes (c0 + lane < end) claim their transactions, read earlier
 // into x, and the wave lists the slots it won.  Returns the lane's won cells
-// whose values are still to be loaded.  Needs the whole wave.
+// whose values are still to be loaded.  Needs the whole wave.  MC: the most
+// cells per transaction of the procedures compiled in.
+template <int MC>
 __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
-                                                    const StagedTxn& x, int64_t c0, int64_t end, int lane) {
+                                                    const StagedTxn& x, int64_t c0, int64_t end, int lane,
+                                                    int& list0, int& nlisted) {
     const bool live = c0 + lane < end;
     uint32_t won = 0, pending = 0;
     // one pass per type present, its lanes specialised on its procedure with
@@ -1942,9 +2092,12 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
         left &= ~__ballot(mine);
         if (mine) {
             switch (a.types[t0].proc) {
-#define GTX_CLAIM_CASE(P)                                     \
-    case P:                                                   \
-        won = part_claim<P>(a, c, tab, x, lane, t0, pending); \
+#define GTX_CLAIM_CASE(P)                                         \
+    case P:                                                       \
+        if constexpr (proc_cells(P) <= MC)                        \
+            won = part_claim<P>(a, c, tab, x, lane, t0, pending); \
+        else                                                      \
+            part_claim_none(a, c, tab, x, lane);                  \
         break;
                 GTX_CLAIM_CASE(GPUTX_DEBIT_CREDIT)
                 GTX_CLAIM_CASE(GPUTX_NEW_ORDER)
@@ -1959,7 +2112,10 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
                 GTX_CLAIM_CASE(GPUTX_DEL_CF)
 #undef GTX_CLAIM_CASE
             default:
-                won = part_claim<0>(a, c, tab, x, lane, 0, pending);
+                if constexpr (MC >= kAllCells)
+                    won = part_claim<0>(a, c, tab, x, lane, 0, pending);
+                else
+                    part_claim_none(a, c, tab, x, lane);
             }
         }
     }
@@ -1967,21 +2123,55 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
     const int nw = __popc(won);
     const int incl = wave_incl_sum_dpp(nw);
     const int total = __builtin_amdgcn_readlane(incl, 63);
+    list0 = 0;
+    nlisted = total;
     if (total == 0) return pending;
     int e0 = 0;
     if (lane % 64 == 63) e0 = __hip_atomic_fetch_add(tab.nlist, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    int e = __builtin_amdgcn_readlane(e0, 63) + incl - nw;
+    list0 = __builtin_amdgcn_readlane(e0, 63);
+    int e = list0 + incl - nw;
     const uint32_t* row = c.cs + lane * c.css;
     const uint32_t base = lds_addr(tab.slot);
     for (uint32_t m = won; m; m &= m - 1) tab.list[e++] = (int32_t)((row[__ffs(m) - 1] - base) >> 4);
     return pending;
 }
 
+// The values of the cells a wave won (list entries list0 .. list0 + n - 1),
+// spread over its lanes with up to eight loads in flight per lane.  None of
+// these cells was in the table before this chunk's claims, so no serial
+// wave works on them yet, and a value already loaded during the claims is
+// loaded again unchanged (the tables change only at flushes).
+__device__ __forceinline__ void list_values_load(const CellTab& tab, int list0, int n) {
+    const int lane = lane_id();  // the wave's own lanes (not the chunk's rows)
+    for (int b = 0; b < n; b += 8 * 64) {
+        int32_t h[8];
+        int64_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = b + q * 64 + lane;
+            h[q] = e < n ? tab.list[list0 + e] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (h[q] >= 0) v[q] = cell_value_of(cell_val_addr(tab, (uint32_t)h[q]));
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (h[q] >= 0) tab.slot[h[q]].val = v[q];
+    }
+}
+
 // Stage a chunk whose transactions were read already (x): claim the cells,
-// then load the won ones.  Needs the whole wave.
+// then load the won ones (lane by lane when only procedures of a few cells
+// left values to load, else spread over the wave).  Needs the whole wave.
+template <int MC>
 __device__ __forceinline__ void part_stage_read(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                 const StagedTxn& x, int64_t c0, int64_t end, int lane) {
-    const uint32_t pending = part_claim_wave(a, c, tab, x, c0, end, lane);
+    int list0, nlisted;
+    const uint32_t pending = part_claim_wave<MC>(a, c, tab, x, c0, end, lane, list0, nlisted);
+    if (__any(pending >> 4)) {
+        list_values_load(tab, list0, nlisted);
+        return;
+    }
     const uint32_t* row = c.cs + lane * c.css;
     ValLoads vl;
     claim_values_issue(row, pending, vl);
@@ -1993,7 +2183,7 @@ __device__ __forceinline__ void part_stage(const BulkArgs& a, const PartChunk& c
     StagedTxn x;
     x.t = 0;
     if (c0 + lane < end) stage_load(a, (int32_t)(c0 + lane), x);
-    part_stage_read(a, c, tab, x, c0, end, lane);
+    part_stage_read<kAllCells>(a, c, tab, x, c0, end, lane);
 }
 
 // A serial wave writes the statuses and results of the chunk's transactions
@@ -2047,6 +2237,7 @@ __device__ __forceinline__ void part_flush(const CellTab& tab, int tid, int nthr
 // transaction of the chunk has the same type.  Returns true when the
 // outcomes went straight to the status and results arrays (window form);
 // otherwise they are in the chunk's rows.
+template <int MC>
 __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChunk& c, const CellTab& tab,
                                                const SerialWave& sw, int cnt, int lane, int64_t& committed,
                                                int64_t& aborted) {
@@ -2056,9 +2247,12 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
     const bool uniform = __ballot(differ) == 0;
     const int proc = uniform ? a.types[t0].proc : 0;
     switch (proc) {
-#define GTX_PART_CASE(P)                                                   \
-    case P:                                                                \
-        return part_serial<P>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
+#define GTX_PART_CASE(P)                                                              \
+    case P:                                                                           \
+        if constexpr (proc_cells(P) <= MC)                                            \
+            return part_serial<P, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted); \
+        else                                                                          \
+            return part_serial<0, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
         GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
         GTX_PART_CASE(GPUTX_NEW_ORDER)
         GTX_PART_CASE(GPUTX_NEW_ORDER_RB)
@@ -2072,7 +2266,7 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
         GTX_PART_CASE(GPUTX_DEL_CF)
 #undef GTX_PART_CASE
     default:
-        return part_serial<0>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
+        return part_serial<0, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
     }
 }
 
@@ -2121,7 +2315,8 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
         for (int64_t c0 = lo; c0 < end; c0 += 64) {
             part_stage(a, c, tab, c0, end, lane);
             __syncthreads();
-            const bool written = part_run_chunk(a, c, tab, sw, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
+            const bool written =
+                part_run_chunk<kAllCells>(a, c, tab, sw, (int)min<int64_t>(64, end - c0), lane, committed, aborted);
             __syncthreads();
             if (!written) part_writeout(a, c, c0, end, lane);
             part_flush(tab, lane, 64);
@@ -2146,6 +2341,7 @@ __global__ __launch_bounds__(64) void k_part_wave(BulkArgs a) {
 template <int CW>
 __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a) {
     constexpr int cw = CW;
+    constexpr int MC = part_pipe_cells(CW);
     constexpr int nser = 64 * kPipeSerial;
     constexpr int nthr = nser + cw;
     GtxState* st = a.ws.st;
@@ -2158,7 +2354,7 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
     auto buf = [&](int64_t k) { return part_chunk_at(part_lds + (k & 1) * cb, a, cw); };
     const int cap = 1 << a.pipe_bits;
     const CellTab tab = part_table_at(part_lds + 2 * cb, a.pipe_bits, part_pipe_fill(cap));
-    GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk
+    GTX_LDS int32_t* flag = tab.nlist + 1;  // [2] flush before the next chunk: the step's stamp
     // one decision for the whole workgroup (another workgroup may fail the
     // bulk meanwhile; all waves must still meet at every barrier)
     if (tid == 0) flag[0] = !failed(st) && st->chosen == GPUTX_PART && (int)blockIdx.x < st->n_heads;
@@ -2169,23 +2365,29 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
     part_init_rows(buf(1), tab, tid, nthr);
     if (tid == 0) *tab.nlist = 0;
 
+    if (tid == 0) flag[0] = flag[1] = -1;  // every wave read the decision above
+
     const int nh = st->n_heads;
     const int ws = __builtin_amdgcn_readfirstlane(tid >> 6);
     const SerialWave sw{ws, kPipeSerial, tab.tag + (serial ? ws : 0) * tab.tstride};
     int64_t committed = 0, aborted = 0;
+    int32_t steps = 0;  // chunks run so far, the same count in every wave
     __syncthreads();
     for (int b = blockIdx.x; b < nh; b += gridDim.x) {
         const int64_t lo = a.ws.heads[b], end = a.ws.heads[b + 1];
         if (end - lo < a.long_part) continue;  // a lane of k_part runs it
         const int64_t nch = (end - lo + cw - 1) / cw;
-        // After a chunk the staging wave may have asked for a flush
-        // (flag[k & 1], written before the barrier that ends the step):
-        // every wave writes back and empties the table, and the staging
-        // wave then stages chunk k + 1.  The serial and the staging waves
-        // run loops of their own (so that neither holds the other's
-        // registers), which meet the same barriers in the same order.
+        // A staging wave that finds the table too full to stage chunk k + 1
+        // asks for a flush: it stamps flag[k & 1] with the step's number
+        // before the barrier that ends the step.  Then every wave writes back
+        // and empties the table, and the staging waves stage chunk k + 1
+        // (again, for any that staged it already).  The stamp needs no reset,
+        // and every wave reads the same value: the slot is written again only
+        // two barriers later.  The serial and the staging waves run loops of
+        // their own (so that neither holds the other's registers), which
+        // meet the same barriers in the same order.
         auto flush_step = [&](int64_t k, auto&& restage) {
-            if (flag[k & 1]) {  // same value in every wave
+            if (flag[k & 1] == steps) {  // same value in every wave
                 part_flush(tab, tid, nthr);
                 __syncthreads();
                 if (tid == 0) *tab.nlist = 0;
@@ -2198,10 +2400,11 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
             __syncthreads();  // chunk 0 staged
             for (int64_t k = 0; k < nch; ++k) {
                 const int cnt = (int)min<int64_t>(cw, end - lo - cw * k);
-                if (!part_run_chunk(a, buf(k), tab, sw, cnt, lane, committed, aborted))
+                if (!part_run_chunk<MC>(a, buf(k), tab, sw, cnt, lane, committed, aborted))
                     part_writeout_own(a, buf(k), cnt, lane, sw);
                 __syncthreads();
                 flush_step(k, [] {});
+                ++steps;
             }
         } else {
             // A staging lane reads its transaction's record for chunk k + 2
@@ -2216,7 +2419,7 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
                 x0.t = 0;
                 if (j0 < end) stage_load(a, (int32_t)j0, x0);
                 if (j1 < end) stage_load(a, (int32_t)j1, xn);
-                part_stage_read(a, buf(0), tab, x0, lo, end, sl);
+                part_stage_read<MC>(a, buf(0), tab, x0, lo, end, sl);
             }
             __syncthreads();  // chunk 0 staged
             for (int64_t k = 0; k < nch; ++k) {
@@ -2227,11 +2430,12 @@ __global__ __launch_bounds__(64 * kPipeSerial + CW) void k_part_pipe(BulkArgs a)
                     flush = *tab.nlist + cw * a.cells_max > part_pipe_fill(cap);
                     const int64_t j2 = c0 + 2 * cw + sl;
                     if (j2 < end) stage_load(a, (int32_t)j2, xa);
-                    if (!flush) part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
+                    if (!flush) part_stage_read<MC>(a, buf(k + 1), tab, xn, c0 + cw, end, sl);
                 }
-                if (sl == 0) flag[k & 1] = flush;
+                if (flush && lane == 0) flag[k & 1] = steps;
                 __syncthreads();
-                flush_step(k, [&] { part_stage_read(a, buf(k + 1), tab, xn, c0 + cw, end, sl); });
+                flush_step(k, [&] { part_stage_read<MC>(a, buf(k + 1), tab, xn, c0 + cw, end, sl); });
+                ++steps;
                 xn = xa;
             }
         }

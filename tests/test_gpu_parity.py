@@ -444,6 +444,25 @@ def test_order_entry_repeated_items(strategy, rollback):
 
 
 @pytest.mark.parametrize("pipeline", [0, 1])
+@pytest.mark.parametrize("mix", [(0.0, 0.5, 0.5), (0.3, 0.4, 0.3)])
+def test_part_mixed_windows(pipeline, mix):
+    """A serial wave's run of payments and order-status reads executes as one
+    window over their cell accesses, grouped by cell.  Two customers per
+    district make a read often the last access of a customer's group, after
+    payments to it in the same window: the cell must keep their sum."""
+    rng = np.random.default_rng(32)
+    n = 12_000
+    bulk = wl.order_bulk(rng, n, 2, 4, 2, 300, mix=mix)
+    n_no = int((bulk.type == 1).sum())
+    n_l = int(bulk.params[3][bulk.type == 1].sum())
+    tabs = wl.order_tables(rng, 2, 4, 2, 300, max(n_no, 1), max(n_l, 1))
+    _say("mixed windows", pipeline, mix)
+    s, g, o = run_both(tabs, wl.order_types(), bulk, 16, "PART", part_pipeline=pipeline)
+    assert s.chosen == 2
+    assert_parity(s, g, o, bulk)
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
 @pytest.mark.parametrize("rollback", [0.0, 0.02])
 def test_part_new_order_groups(pipeline, rollback):
     """New-orders over a large item space rarely share a stock row, so PART's
