@@ -136,11 +136,14 @@ typedef struct {
     int32_t spin_limit_ms; /* watchdog on every device wait; expiry -> GPUTX_E_DEADLOCK  */
     int32_t grid_blocks;   /* persistent grid size (0: one workgroup per compute unit)  */
     int32_t part_pipeline; /* PART with a staging wave beside the serial one (1, default) */
-    int32_t part_scan;     /* 1 (default): PART runs procedures whose effect on each cell
-                              is a map of that cell alone (debit-credit, payment, order
-                              status, the subscriber reads and field updates) 64 at a
-                              time as a scan of those maps per cell, reported as
-                              "PART-scan" (stats.part_scan); 0: every partition runs its
+    int32_t part_scan;     /* 1 (default): PART runs several transactions of a partition
+                              at once where that leaves the serial result: procedures
+                              whose effect on each cell is a map of that cell alone
+                              (debit-credit, payment, order status, the subscriber reads
+                              and field updates) as a scan of those maps per cell, up to
+                              four new-orders with distinct items or four subscriber
+                              reads side by side; reported as "PART-scan"
+                              (stats.part_scan); 0: every partition runs its
                               transactions one after another (Section 5.2 as written)  */
     int32_t tpl_lanes;     /* TPL launch shape, 0..64: 64 runs windows of 256
                               transactions per workgroup, grouped by type (Section
@@ -213,8 +216,9 @@ typedef struct {
     int64_t aborted;
     int64_t invalid;
     int64_t appended;   /* rows appended to append-only tables (batched update)   */
-    int64_t part_scan;  /* PART ran: partition chunks executed in the scan form
-                           (gputx_options.part_scan); 0 = Section 5.2's
+    int64_t part_scan;  /* PART ran: partition chunks (of a mixed chunk, each
+                           serial wave's share) that ran transactions side by
+                           side (gputx_options.part_scan); 0 = Section 5.2's
                            one-after-another run throughout                      */
     int64_t reserved[6];
 } gputx_bulk_stats;

@@ -1445,6 +1445,22 @@ __device__ __forceinline__ bool wave_new_order_group(const DevType& T, const Par
     return true;
 }
 
+// Up to four consecutive subscriber reads at once, sixteen lanes each (lane
+// 16 g + j reads field j of the g-th, transaction kg): reads with no write
+// between them see the same values in any order.
+__device__ __forceinline__ void wave_get_sub_group(const PartChunk& c, int k0, int k1, int k2, int k3, int G,
+                                                   uint32_t* seen) {
+    constexpr int NF = proc_cells(GPUTX_GET_SUB);
+    const int lane = lane_id();
+    const int g = lane >> 4, j = lane & 15;
+    const int k = g == 0 ? k0 : g == 1 ? k1 : g == 2 ? k2 : k3;
+    if (g < G && j < NF) {
+        const uint32_t at = c.cs[k * c.css + j];
+        *seen &= at;
+        c.res[k * c.rs + j] = *(GTX_LDS const int64_t*)(uintptr_t)at;
+    }
+}
+
 __device__ __forceinline__ int32_t wave_payment(const PartChunk& c, int k, const WaveTxn& x, uint32_t* seen) {
     const int lane = lane_id();
     if (lane < 3) {
@@ -1691,6 +1707,16 @@ __device__ __forceinline__ void mixed_window(const PartChunk& c, const CellTab& 
         init = *(GTX_LDS const int64_t*)(uintptr_t)id;
         *seen &= id;
     }
+    if (!__any(act && proc_cell_writes(pc))) {  // reads only: every access sees the staged value
+        if (act) {
+            bool fa, w;
+            int64_t fb, nv, res;
+            int at = -1;
+            mixed_cell_map(pc, r, p, init, fa, fb, nv, w, at, res, true);
+            if (at >= 0 && at < c.rs) c.res[k * c.rs + at] = res;
+        }
+        return;
+    }
     bool hd, ls;
     const int to = group_ordinal(tab, sw.tag, id, act, hd, ls);
     // each lane takes the access at its sorted slot
@@ -1767,15 +1793,18 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
       }
     }
     if constexpr (P == 0 || P == GPUTX_NEW_ORDER || P == GPUTX_NEW_ORDER_RB) {
-        // the whole wave on each transaction (order-entry procedures; up to
-        // four new-orders at once), one serial wave per cell class; other
-        // procedures on lane 0.  The wave lists its own transactions of each
-        // 64 with one ballot.
+        // one serial wave per cell class, which lists its own transactions of
+        // each 64 with one ballot.  With the scan form, several transactions
+        // at once where that leaves the serial result: runs of cellwise ones
+        // as a window, up to four disjoint new-orders or four subscriber
+        // reads; otherwise one at a time, the order-entry procedures with
+        // the whole wave, others on lane 0.
         if constexpr (P != 0)
             if (T.cell_class % sw.nsw != sw.ws) return false;
         const int lane = lane_id();
         uint32_t seen = ~0u;
         int n_commit = 0, n_abort = 0;
+        bool multi = false;  // some transactions ran side by side (the scan form)
         for (int b0 = 0; b0 < cnt; b0 += 64) {
             const int r = b0 + lane;
             int32_t pw = 0, tw = 0;
@@ -1802,15 +1831,37 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                         mm &= mm - 1;
                         ++G;
                     }
-                    if (G >= 2) {
+                    if (G >= 8) {  // shorter runs are faster one at a time
                         mixed_window(c, tab, sw, b0, pw, run, G, &seen);
+                        multi = true;
                         n_commit += G;
                         m = mm;
                         continue;
                     }
                 }
+                if (a.part_scan && pq == GPUTX_GET_SUB && proc_cells(GPUTX_GET_SUB) <= MC) {
+                    // this one and up to three more reads of the subscriber row that follow it
+                    int k1 = k, k2 = k, k3 = k, G = 1;
+                    uint64_t mm = m & (m - 1);
+#pragma unroll
+                    for (int e = 1; e < 4; ++e) {
+                        if (!mm) break;
+                        const int jn = __ffsll((unsigned long long)mm) - 1;
+                        if ((__builtin_amdgcn_readlane(pw, jn) & 0xffff) != GPUTX_GET_SUB) break;
+                        if (e == 1) k1 = b0 + jn;
+                        if (e == 2) k2 = b0 + jn;
+                        if (e == 3) k3 = b0 + jn;
+                        G = e + 1;
+                        mm &= mm - 1;
+                    }
+                    wave_get_sub_group(c, k, k1, k2, k3, G, &seen);
+                    multi = multi || G > 1;
+                    n_commit += G;
+                    m = mm;
+                    continue;
+                }
                 constexpr bool kNewOrder = MC >= proc_cells(GPUTX_NEW_ORDER);
-                if (kNewOrder && (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB)) {
+                if (kNewOrder && a.part_scan && (pq == GPUTX_NEW_ORDER || pq == GPUTX_NEW_ORDER_RB)) {
                     // this one and up to three more of its type that follow it
                     int k1 = k, k2 = k, k3 = k, G = 1;
                     uint64_t mm = m & (m - 1);
@@ -1832,6 +1883,7 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                             ? wave_new_order_group<GPUTX_NEW_ORDER>(Tk, c, tab, sw, k, k1, k2, k3, G, &seen)
                             : wave_new_order_group<GPUTX_NEW_ORDER_RB>(Tk, c, tab, sw, k, k1, k2, k3, G, &seen);
                     if (done) {
+                        multi = multi || G > 1;
                         n_commit += G;
                         m = mm;
                         continue;
@@ -1884,6 +1936,7 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
         if (lane == 0) {
             committed += n_commit;
             aborted += n_abort;
+            if (multi) atomicAdd((unsigned long long*)&a.ws.st->scan_chunks, 1ull);
         }
         if (__any(!(seen & 8u))) {
             if (lane == 0) fail(a.ws.st, GPUTX_E_INTERNAL);
