@@ -1092,7 +1092,10 @@ __device__ __forceinline__ uint32_t cell_hash(uint64_t key, int bits) {
 // cells, their ordinals known at compile time) each cell's value is loaded
 // before its claim instead, into a register, and the won ones are stored
 // after the last claim (store_won): the loads then overlap the claims.
-template <int NV>
+// CAS_FIRST: procedures whose cells are mostly new to the table (a
+// new-order's stock rows) try the CAS at once, one LDS round trip per probe
+// instead of a read and then the CAS.
+template <int NV, bool CAS_FIRST = false>
 struct CellClaim {
     CellTab tab;
     uint32_t* cs;  // the transaction's row of cell addresses
@@ -1108,8 +1111,10 @@ struct CellClaim {
         uint32_t h = cell_hash(key, tab.bits);
         uint32_t got = cell_sink_addr(tab);  // no free slot: the serial side reports the miss
         for (uint32_t probe = 0; probe <= mask; ++probe, h = (h + 1) & mask) {
-            uint64_t cur = __hip_atomic_load(&tab.slot[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (cur == 0) {
+            uint64_t cur = 0;
+            if constexpr (!CAS_FIRST)
+                cur = __hip_atomic_load(&tab.slot[h].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == 0) {  // on failure the CAS leaves the slot's key in cur
                 __hip_atomic_compare_exchange_strong(&tab.slot[h].key, &cur, want, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (cur == 0) {
@@ -2088,7 +2093,7 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
                  : k < kStagePrm ? s.prm[k] : a.ws.rec[(int64_t)s.p * a.rec_words + 1 + k];
     const int ncs = P != 0 ? proc_cells(P) : c.css;  // ordinals the serial side can read
     for (int r = 0; r < ncs; ++r) c.cs[lane * c.css + r] = cell_sink_addr(tab);
-    CellClaim<NV> claim;
+    CellClaim<NV, P == GPUTX_NEW_ORDER || P == GPUTX_NEW_ORDER_RB> claim;
     claim.tab = tab;
     claim.cs = c.cs + lane * c.css;
     claim.won = 0;
