@@ -339,6 +339,22 @@ __device__ __forceinline__ int chunk_prefix(const int* cnt, int* cpre) {
     return c;
 }
 
+// Wave-wide inclusive scans through DPP (GFX9 controls: shift right within
+// 16-lane rows, then the broadcasts of lanes 15 and 31 that carry the scan
+// across rows).  All 64 lanes must be active.
+constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_add_step(int v) {
+    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ int wave_incl_sum_dpp(int v) {
+    v = dpp_add_step<kDppRowShr + 1, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 2, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 4, 0xf>(v);
+    v = dpp_add_step<kDppRowShr + 8, 0xf>(v);
+    v = dpp_add_step<kDppBcast15, 0xa>(v);
+    return dpp_add_step<kDppBcast31, 0xc>(v);
+}
 // Wave 0 of a workgroup, after a narrow wave: the next frontier's per-type
 // counts (fill, which is cleared for the wave after), their total and the
 // chunk prefix.
@@ -347,15 +363,8 @@ __device__ __forceinline__ void kset_level_counts(int* fill, int* wcnt, int* cpr
     const int v = l < GPUTX_MAX_TYPES ? fill[l] : 0;
     if (l < GPUTX_MAX_TYPES) fill[l] = 0;
     const int ch = (v + 63) / 64;
-    int inc = ch;
-#pragma unroll
-    for (int off = 1; off < GPUTX_MAX_TYPES; off <<= 1) {
-        const int y = __shfl_up(inc, off);
-        if (l >= off) inc += y;
-    }
-    int tot = v;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
+    const int inc = wave_incl_sum_dpp(ch);  // DPP: no LDS round trip on the wave's path
+    const int tot = __builtin_amdgcn_readlane(wave_incl_sum_dpp(v), 63);
     if (l < GPUTX_MAX_TYPES) {
         wcnt[l] = v;
         cpre[l] = inc - ch;
@@ -1486,22 +1495,6 @@ __device__ __forceinline__ int32_t wave_order_status(const PartChunk& c, int k, 
     return GPUTX_COMMIT;
 }
 
-// Wave-wide inclusive scans through DPP (GFX9 controls: shift right within
-// 16-lane rows, then the broadcasts of lanes 15 and 31 that carry the scan
-// across rows).  All 64 lanes must be active.
-constexpr int kDppRowShr = 0x110, kDppBcast15 = 0x142, kDppBcast31 = 0x143;
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_add_step(int v) {
-    return v + __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
-}
-__device__ __forceinline__ int wave_incl_sum_dpp(int v) {
-    v = dpp_add_step<kDppRowShr + 1, 0xf>(v);
-    v = dpp_add_step<kDppRowShr + 2, 0xf>(v);
-    v = dpp_add_step<kDppRowShr + 4, 0xf>(v);
-    v = dpp_add_step<kDppRowShr + 8, 0xf>(v);
-    v = dpp_add_step<kDppBcast15, 0xa>(v);
-    return dpp_add_step<kDppBcast31, 0xc>(v);
-}
 // Maps v -> a ? v + b : b (wrapping add; a is 0 or 1).  A lane composes its
 // map after the one it receives; lanes without a source receive the
 // identity (1, 0).
