@@ -382,7 +382,7 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
     __shared__ int lfill[GPUTX_MAX_TYPES];
     __shared__ int cpre[GPUTX_MAX_TYPES + 1];
     __shared__ int64_t k_s;
-    __shared__ int done_s, total_s;
+    __shared__ int done_s, total_s, failed_s;
     if (threadIdx.x == 0) {
         int o = 0;
         for (int t = 0; t < GPUTX_MAX_TYPES; ++t) {
@@ -437,10 +437,14 @@ __global__ __launch_bounds__(GTX_BLOCK) void k_kset(BulkArgs a) {
                     ++kk;
                     if (wave_id() == 0) {
                         kset_level_counts(lfill, wcnt, cpre, &total_s);
-                        if (lane_id() == 0 && (kk & 63) == 0) st_relaxed(&st->narrow_prog, kk);
+                        if (lane_id() == 0) {
+                            if ((kk & 63) == 0) st_relaxed(&st->narrow_prog, kk);
+                            // one read for the workgroup: every thread must take the same exit
+                            failed_s = failed(st);
+                        }
                     }
                     __syncthreads();
-                    if (total_s == 0 || total_s > a.kset_narrow || failed(st)) break;
+                    if (total_s == 0 || total_s > a.kset_narrow || failed_s) break;
                 }
                 if (threadIdx.x < GPUTX_MAX_TYPES) {
                     st_relaxed(&st->kset_fill[kk % 3][threadIdx.x], wcnt[threadIdx.x]);
