@@ -1083,6 +1083,21 @@ struct CellTab {
 // LDS address of a slot's value (16-byte slots: bit 3 is set), and of the
 // sink slot's key (bit 3 clear), which stands for an ordinal no cell backs.
 __device__ __forceinline__ uint32_t lds_addr(GTX_LDS const void* p) { return (uint32_t)(uintptr_t)p; }
+// The type descriptors do not change while a kernel runs.  One that is the
+// same for the whole wave is read through the constant address space, so
+// the compiler can use scalar loads: their completion is counted apart from
+// the vector memory operations, and waiting for a descriptor field then does
+// not also wait for reads and stores in flight (the staging lanes' records
+// read a step ahead, the serial waves' outcomes of the chunk before).
+#define GTX_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ DevType dev_type_uniform(const DevType* types, int t) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const GTX_CONST DevType*)(uintptr_t)types)[__builtin_amdgcn_readfirstlane(t)];
+#else
+    return types[t];  // the host pass only parses device functions
+#endif
+}
+
 __device__ __forceinline__ uint32_t cell_val_addr(const CellTab& t, uint32_t h) { return lds_addr(&t.slot[h].val); }
 __device__ __forceinline__ uint32_t cell_sink_addr(const CellTab& t) { return lds_addr(&t.slot[1u << t.bits].key); }
 template <class V>
@@ -1820,7 +1835,9 @@ __device__ __forceinline__ bool part_serial(const BulkArgs& a, const DevType& T,
                 const int k = b0 + j;
                 const int32_t pc = __builtin_amdgcn_readlane(pw, j);
                 const int32_t tk = P != 0 ? 0 : __builtin_amdgcn_readlane(tw, j);
-                const DevType& Tk = P != 0 ? T : a.types[tk];
+                DevType Tm;
+                if constexpr (P == 0) Tm = dev_type_uniform(a.types, tk);
+                const DevType& Tk = P != 0 ? T : Tm;
                 const int pq = pc & 0xffff;
                 if (a.part_scan && mixed_window_proc(pq)) {
                     // this one and the cellwise ones right after it, up to 21
@@ -2078,7 +2095,9 @@ __device__ __forceinline__ uint32_t part_claim(const BulkArgs& a, const PartChun
     constexpr int NV = (P != 0 && proc_cells(P) <= 4) ? proc_cells(P) : 0;
     constexpr int NP = P != 0 ? proc_params(P) : GTX_MAX_PARAMS;
     const int32_t t = P != 0 ? tu : s.t;
-    const DevType& T = a.types[t];
+    DevType Tu;
+    if constexpr (P != 0) Tu = dev_type_uniform(a.types, tu);
+    const DevType& T = P != 0 ? Tu : a.types[t];
     TxnIn x;
     x.t = t;
     x.i = s.i;
@@ -2146,7 +2165,7 @@ __device__ __forceinline__ uint32_t part_claim_wave(const BulkArgs& a, const Par
         const bool mine = live && x.t == t0;
         left &= ~__ballot(mine);
         if (mine) {
-            switch (a.types[t0].proc) {
+            switch (dev_type_uniform(a.types, t0).proc) {
 #define GTX_CLAIM_CASE(P)                                         \
     case P:                                                       \
         if constexpr (proc_cells(P) <= MC)                        \
@@ -2300,14 +2319,15 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
     bool differ = false;
     for (int e = lane; e < cnt; e += 64) differ = differ || c.t[e] != t0;
     const bool uniform = __ballot(differ) == 0;
-    const int proc = uniform ? a.types[t0].proc : 0;
+    const DevType T0 = dev_type_uniform(a.types, t0);
+    const int proc = uniform ? T0.proc : 0;
     switch (proc) {
 #define GTX_PART_CASE(P)                                                              \
     case P:                                                                           \
         if constexpr (proc_cells(P) <= MC)                                            \
-            return part_serial<P, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted); \
+            return part_serial<P, MC>(a, T0, c, tab, sw, cnt, committed, aborted);       \
         else                                                                          \
-            return part_serial<0, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
+            return part_serial<0, MC>(a, T0, c, tab, sw, cnt, committed, aborted);
         GTX_PART_CASE(GPUTX_DEBIT_CREDIT)
         GTX_PART_CASE(GPUTX_NEW_ORDER)
         GTX_PART_CASE(GPUTX_NEW_ORDER_RB)
@@ -2321,7 +2341,7 @@ __device__ __forceinline__ bool part_run_chunk(const BulkArgs& a, const PartChun
         GTX_PART_CASE(GPUTX_DEL_CF)
 #undef GTX_PART_CASE
     default:
-        return part_serial<0, MC>(a, a.types[t0], c, tab, sw, cnt, committed, aborted);
+        return part_serial<0, MC>(a, T0, c, tab, sw, cnt, committed, aborted);
     }
 }
 
