@@ -48,6 +48,21 @@ struct TxnIn {
     int64_t prm[GTX_MAX_PARAMS];
 };
 
+// The type descriptors do not change while a kernel runs.  One that is the
+// same for the whole wave is read through the constant address space, so
+// the compiler can use scalar loads: their completion is counted apart from
+// the vector memory operations, and waiting for a descriptor field then does
+// not also wait for reads and stores in flight (the staging lanes' records
+// read a step ahead, the serial waves' outcomes of the chunk before).
+#define GTX_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ DevType dev_type_uniform(const DevType* types, int t) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const GTX_CONST DevType*)(uintptr_t)types)[__builtin_amdgcn_readfirstlane(t)];
+#else
+    return types[t];  // the host pass only parses device functions
+#endif
+}
+
 __device__ __forceinline__ void load_txn(const BulkArgs& a, int64_t p, int32_t t, TxnIn& x) {
     const DevType& T = a.types[t];
     x.t = t;
@@ -90,10 +105,40 @@ __device__ __forceinline__ int32_t exec_txn(const BulkArgs& a, const TxnIn& x) {
 }
 
 // exec_txn with the cells accessed coherently across the device (CoherentAcc).
-__device__ __forceinline__ int32_t exec_txn_coherent(const BulkArgs& a, const TxnIn& x) {
+// tu >= 0: every active lane's transaction has type tu; its descriptor is
+// then read through scalar loads (dev_type_uniform), one copy per procedure
+// so that only the procedures that pick a column at run time keep theirs in
+// private memory.
+__device__ __forceinline__ int32_t exec_txn_coherent(const BulkArgs& a, const TxnIn& x, int32_t tu = -1) {
     int64_t res[GTX_MAX_RESULTS];
     CoherentAcc acc;
-    const int32_t s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+    int32_t s;
+    if (tu >= 0) {
+        switch (dev_type_uniform(a.types, tu).proc) {
+#define GTX_TPL_CASE(P)                                                              \
+    case P: {                                                                        \
+        const DevType T = dev_type_uniform(a.types, tu);                             \
+        s = txn_exec_p<P>(acc, T, x.prm, x.ts, x.app0, x.app1, res);                 \
+        break;                                                                       \
+    }
+            GTX_TPL_CASE(GPUTX_DEBIT_CREDIT)
+            GTX_TPL_CASE(GPUTX_NEW_ORDER)
+            GTX_TPL_CASE(GPUTX_NEW_ORDER_RB)
+            GTX_TPL_CASE(GPUTX_PAYMENT)
+            GTX_TPL_CASE(GPUTX_ORDER_STATUS)
+            GTX_TPL_CASE(GPUTX_GET_SUB)
+            GTX_TPL_CASE(GPUTX_GET_CF)
+            GTX_TPL_CASE(GPUTX_UPD_SUB_FIELD)
+            GTX_TPL_CASE(GPUTX_UPD_LOC)
+            GTX_TPL_CASE(GPUTX_INS_CF)
+            GTX_TPL_CASE(GPUTX_DEL_CF)
+#undef GTX_TPL_CASE
+        default:
+            s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+        }
+    } else {
+        s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
+    }
     a.status[x.i] = s;
     int64_t* out = a.results + x.i * a.width;
 #pragma unroll
@@ -558,8 +603,11 @@ __device__ __forceinline__ void tpl_window(const BulkArgs& a, int64_t p, int32_t
             // or invalidation (which would cost every other wave on the XCD
             // its cached signatures and operation records too).
             __asm__ volatile("" ::: "memory");
+            // the ready lanes' type, when they share one
+            const int32_t tr = __builtin_amdgcn_readfirstlane(ready ? t : INT32_MAX);
+            const int32_t tu = __ballot(ready && t != tr) == 0 ? tr : -1;
             if (ready) {
-                s = exec_txn_coherent(a, x);
+                s = exec_txn_coherent(a, x, tu);
                 ran = true;
             }
             __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1083,20 +1131,6 @@ struct CellTab {
 // LDS address of a slot's value (16-byte slots: bit 3 is set), and of the
 // sink slot's key (bit 3 clear), which stands for an ordinal no cell backs.
 __device__ __forceinline__ uint32_t lds_addr(GTX_LDS const void* p) { return (uint32_t)(uintptr_t)p; }
-// The type descriptors do not change while a kernel runs.  One that is the
-// same for the whole wave is read through the constant address space, so
-// the compiler can use scalar loads: their completion is counted apart from
-// the vector memory operations, and waiting for a descriptor field then does
-// not also wait for reads and stores in flight (the staging lanes' records
-// read a step ahead, the serial waves' outcomes of the chunk before).
-#define GTX_CONST __attribute__((address_space(4)))
-__device__ __forceinline__ DevType dev_type_uniform(const DevType* types, int t) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return ((const GTX_CONST DevType*)(uintptr_t)types)[__builtin_amdgcn_readfirstlane(t)];
-#else
-    return types[t];  // the host pass only parses device functions
-#endif
-}
 
 __device__ __forceinline__ uint32_t cell_val_addr(const CellTab& t, uint32_t h) { return lds_addr(&t.slot[h].val); }
 __device__ __forceinline__ uint32_t cell_sink_addr(const CellTab& t) { return lds_addr(&t.slot[1u << t.bits].key); }
