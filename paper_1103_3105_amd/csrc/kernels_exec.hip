@@ -63,8 +63,7 @@ __device__ __forceinline__ DevType dev_type_uniform(const DevType* types, int t)
 #endif
 }
 
-__device__ __forceinline__ void load_txn(const BulkArgs& a, int64_t p, int32_t t, TxnIn& x) {
-    const DevType& T = a.types[t];
+__device__ __forceinline__ void load_txn(const BulkArgs& a, const DevType& T, int64_t p, int32_t t, TxnIn& x) {
     x.t = t;
     x.i = in_index(a, p);
     x.np = min(a.n_params, T.n_params);
@@ -72,6 +71,9 @@ __device__ __forceinline__ void load_txn(const BulkArgs& a, int64_t p, int32_t t
     x.ts = a.ts[x.i];
     x.app0 = T.app_idx[0] >= 0 ? a.rowcount[T.app_idx[0]] + a.ws.cnt[(int64_t)(1 + T.app_idx[0]) * a.n + p] : 0;
     x.app1 = T.app_idx[1] >= 0 ? a.rowcount[T.app_idx[1]] + a.ws.cnt[(int64_t)(1 + T.app_idx[1]) * a.n + p] : 0;
+}
+__device__ __forceinline__ void load_txn(const BulkArgs& a, int64_t p, int32_t t, TxnIn& x) {
+    load_txn(a, a.types[t], p, t, x);
 }
 
 __device__ __forceinline__ int64_t rl64(int64_t v, int k) {
@@ -274,13 +276,41 @@ __device__ __forceinline__ void kset_chunk(const BulkArgs& a, int c, const int* 
     // transaction has more operations or read runs)
     const KsetRec R = a.ws.ksrec[q];
     TxnIn x;
-    load_txn(a, q, t, x);
+    {  // the chunk's type is the wave's: its descriptor through scalar loads
+        const DevType Tl = dev_type_uniform(a.types, t);
+        load_txn(a, Tl, q, t, x);
+    }
     // the first operations' in-degree decrements, all in flight together
     int32_t left[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) left[k] = R.s0[k] >= 0 ? atomicSub(&a.ws.indeg[R.s0[k]], 1) : 0;
-    // run this transaction
-    const int32_t s = exec_txn(a, x);
+    // run this transaction, dispatched once on the chunk's procedure with a
+    // scalar-loaded descriptor per case (waiting for it then waits for none
+    // of the in-degree atomics in flight; only the procedures that pick a
+    // column at run time keep their copy in private memory)
+    int32_t s;
+    switch (dev_type_uniform(a.types, t).proc) {
+#define GTX_KSET_CASE(P)                                       \
+    case P: {                                                  \
+        const DevType T = dev_type_uniform(a.types, t);        \
+        s = exec_txn_p<P>(a, T, x);                            \
+        break;                                                 \
+    }
+        GTX_KSET_CASE(GPUTX_DEBIT_CREDIT)
+        GTX_KSET_CASE(GPUTX_NEW_ORDER)
+        GTX_KSET_CASE(GPUTX_NEW_ORDER_RB)
+        GTX_KSET_CASE(GPUTX_PAYMENT)
+        GTX_KSET_CASE(GPUTX_ORDER_STATUS)
+        GTX_KSET_CASE(GPUTX_GET_SUB)
+        GTX_KSET_CASE(GPUTX_GET_CF)
+        GTX_KSET_CASE(GPUTX_UPD_SUB_FIELD)
+        GTX_KSET_CASE(GPUTX_UPD_LOC)
+        GTX_KSET_CASE(GPUTX_INS_CF)
+        GTX_KSET_CASE(GPUTX_DEL_CF)
+#undef GTX_KSET_CASE
+    default:
+        s = exec_txn(a, x);
+    }
     committed += s == GPUTX_COMMIT;
     aborted += s == GPUTX_ABORT;
     // successors that became ready join the next frontier
