@@ -107,38 +107,27 @@ __device__ __forceinline__ int32_t exec_txn(const BulkArgs& a, const TxnIn& x) {
 }
 
 // exec_txn with the cells accessed coherently across the device (CoherentAcc).
-// tu >= 0: every active lane's transaction has type tu; its descriptor is
-// then read through scalar loads (dev_type_uniform), one copy per procedure
-// so that only the procedures that pick a column at run time keep theirs in
-// private memory.
+// tu >= 0: every active lane's transaction has type tu.  For the narrow
+// procedures of fixed columns its descriptor is then read through scalar
+// loads (dev_type_uniform), one copy per procedure; the others (and mixed
+// waves) keep the per-lane read, which keeps this hot loop's code small.
 __device__ __forceinline__ int32_t exec_txn_coherent(const BulkArgs& a, const TxnIn& x, int32_t tu = -1) {
     int64_t res[GTX_MAX_RESULTS];
     CoherentAcc acc;
     int32_t s;
-    if (tu >= 0) {
-        switch (dev_type_uniform(a.types, tu).proc) {
+    const int pu = tu >= 0 ? dev_type_uniform(a.types, tu).proc : 0;
+    switch (pu) {
 #define GTX_TPL_CASE(P)                                                              \
     case P: {                                                                        \
         const DevType T = dev_type_uniform(a.types, tu);                             \
         s = txn_exec_p<P>(acc, T, x.prm, x.ts, x.app0, x.app1, res);                 \
         break;                                                                       \
     }
-            GTX_TPL_CASE(GPUTX_DEBIT_CREDIT)
-            GTX_TPL_CASE(GPUTX_NEW_ORDER)
-            GTX_TPL_CASE(GPUTX_NEW_ORDER_RB)
-            GTX_TPL_CASE(GPUTX_PAYMENT)
-            GTX_TPL_CASE(GPUTX_ORDER_STATUS)
-            GTX_TPL_CASE(GPUTX_GET_SUB)
-            GTX_TPL_CASE(GPUTX_GET_CF)
-            GTX_TPL_CASE(GPUTX_UPD_SUB_FIELD)
-            GTX_TPL_CASE(GPUTX_UPD_LOC)
-            GTX_TPL_CASE(GPUTX_INS_CF)
-            GTX_TPL_CASE(GPUTX_DEL_CF)
+        GTX_TPL_CASE(GPUTX_DEBIT_CREDIT)
+        GTX_TPL_CASE(GPUTX_PAYMENT)
+        GTX_TPL_CASE(GPUTX_ORDER_STATUS)
 #undef GTX_TPL_CASE
-        default:
-            s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
-        }
-    } else {
+    default:
         s = txn_exec_any(acc, a.types[x.t], x.prm, x.ts, x.app0, x.app1, res);
     }
     a.status[x.i] = s;
